@@ -1,0 +1,189 @@
+/*
+ * pdz — perfect-hash (Paradeisos) Hubbard H.v and Lanczos on one MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only; no C++ types cross this boundary and
+ * no exception escapes it.  Every function returns a pdz_status; on failure a
+ * message is available from pdz_last_error() on the calling thread.
+ *
+ * Model (Sec. II.B, Eq. 1):
+ *     H = - sum_{bonds (i,j)} t_ij sum_s (c+_{i,s} c_{j,s} + c+_{j,s} c_{i,s})
+ *         + U sum_i n_{i,up} n_{i,dn}
+ * on N sites with n_up up and n_dn down electrons (canonical ensemble,
+ * Sec. II.A), dimension D = C(N, n_up) * C(N, n_dn).
+ *
+ * Basis and vector layout (Sec. II.A and Sec. III):
+ *  - one spin species: site i <-> bit i of a uint32 occupation string; a
+ *    sector lists every N-bit string with n set bits in ascending order;
+ *  - a basis element is (phi_up, phi_dn), built from the vacuum with the up
+ *    operators left of the down operators and the site index increasing from
+ *    right to left;
+ *  - its index is idx = C(N, n_dn) * idx_up(phi_up) + idx_dn(phi_dn), so a
+ *    vector of length D is the row-major matrix X[idx_up][idx_dn];
+ *  - idx_s(phi) is the forward map of Sec. III (Eq. 3): the sum over the set
+ *    bits j_0 < j_1 < ... of C(j_m, m+1); its inverse is the backward map.
+ *
+ * Devices and streams: every call works on the HIP device current on the
+ * calling thread.  `stream` is a hipStream_t (NULL = legacy default stream).
+ * Device pointers must belong to that device.  Calls documented as
+ * asynchronous only enqueue work on `stream`.
+ *
+ * Integer widths: sector ranks are uint32 (C(32,16) < 2^31); D, counts and
+ * offsets are uint64.
+ */
+#ifndef PDZ_H
+#define PDZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pdz_status;
+#define PDZ_OK 0
+#define PDZ_EINVAL (-1)   /* invalid argument (null pointer, bad bond, non-finite value, ...) */
+#define PDZ_ERANGE (-2)   /* size outside the supported range */
+#define PDZ_ENOMEM (-3)   /* device or host allocation failed */
+#define PDZ_EHIP (-4)     /* a HIP runtime call failed */
+#define PDZ_ENOCONV (-5)  /* iteration limit reached; results hold the best estimate */
+#define PDZ_EDEVICE (-6)  /* a kernel found invalid device data (see pdz_device_errors) */
+
+typedef enum { PDZ_F64 = 0, PDZ_F32 = 1 } pdz_dtype;
+
+/* One undirected bond: contributes -t (c+_i c_j + c+_j c_i) for each spin
+ * (Eq. 1).  i != j, 0 <= i, j < n_sites, t finite.  Repeated pairs add. */
+typedef struct {
+    int32_t i;
+    int32_t j;
+    double t;
+} pdz_bond;
+
+/* Opaque, immutable problem handle: sizes, tables and plans on one device. */
+typedef struct pdz_problem_s* pdz_problem;
+
+typedef struct {
+    uint64_t D;          /* C(N,n_up) * C(N,n_dn)                          */
+    uint64_t D_up;       /* C(N,n_up)                                       */
+    uint64_t D_dn;       /* C(N,n_dn)                                       */
+    uint64_t nnz;        /* structural nonzeros: D diagonal + all hops      */
+    uint64_t hops_up;    /* allowed up hops summed over the up sector       */
+    uint64_t hops_dn;    /* allowed down hops summed over the down sector   */
+    int32_t n_sites, n_up, n_dn, n_bonds;
+    int32_t max_hops_up; /* most hops out of one up-sector state            */
+    int32_t max_hops_dn; /* most hops out of one down-sector state          */
+    int32_t device;      /* HIP device the handle lives on                  */
+    int32_t hv_path;     /* 0: sector hop tables, 1: on-the-fly ranks        */
+} pdz_info;
+
+/* ------------------------------------------------------------------ problems */
+
+/* Validate the problem statement (Eq. 1; Sec. II.A), build the binomial table
+ * C_i^m by Pascal's rule (Sec. III) and the per-sector hop tables on the
+ * current device (each hop target ranked by the forward map on the device),
+ * and return a handle.  Synchronous.
+ * Errors: PDZ_ERANGE if n_sites < 1 or > 32 or D >= 2^62;
+ *         PDZ_EINVAL for a null out/bonds (bonds may be NULL iff n_bonds == 0),
+ *         n_bonds < 0, n_up/n_dn outside [0, n_sites], a bond with i == j or
+ *         an endpoint outside [0, n_sites), a non-finite t or U;
+ *         PDZ_ENOMEM / PDZ_EHIP from the device.
+ * Ownership: the library owns everything behind the handle. */
+pdz_status pdz_problem_create(int32_t n_sites, const pdz_bond* bonds, int32_t n_bonds, double U,
+                              int32_t n_up, int32_t n_dn, pdz_problem* out);
+
+/* Release a handle.  NULL is a no-op.  Synchronises the device first. */
+pdz_status pdz_problem_destroy(pdz_problem p);
+
+/* Sizes and counts of a problem (host only, no device work). */
+pdz_status pdz_problem_info(pdz_problem p, pdz_info* out);
+
+/* --------------------------------------------------------- the perfect hash */
+
+/* Forward map (Sec. III, Eq. 3): ranks[k] = idx(bits[k]) within the sector of
+ * N-bit strings with n set bits.  bits, ranks: device arrays of `count`
+ * uint32.  A string whose popcount is not n, or with bits at or above
+ * n_sites, gets rank 0xFFFFFFFF and raises the device error word.
+ * Asynchronous.  Errors: PDZ_ERANGE (n_sites outside [1,32]), PDZ_EINVAL
+ * (n outside [0,n_sites], null pointer with count > 0). */
+pdz_status pdz_rank(int32_t n_sites, int32_t n, const uint32_t* bits, uint64_t count, uint32_t* ranks,
+                    void* stream);
+
+/* Backward map (Sec. III): bits[k] = the string of rank ranks[k].  A rank
+ * >= C(n_sites, n) gives bits 0xFFFFFFFF and raises the device error word.
+ * Asynchronous.  Errors as pdz_rank. */
+pdz_status pdz_unrank(int32_t n_sites, int32_t n, const uint32_t* ranks, uint64_t count, uint32_t* bits,
+                      void* stream);
+
+/* Synchronise the current device, return the device error word raised by
+ * kernels since the last call (0 if none) in *word, and clear it.
+ * Returns PDZ_EDEVICE when the word was non-zero. */
+pdz_status pdz_device_errors(uint32_t* word);
+
+/* ------------------------------------------------------------------- H.v */
+
+/* y = H x, matrix-free (Eq. 1), in precision dt (F64: doubles; F32: floats,
+ * float accumulation).  x, y: device arrays of D elements in the layout above;
+ * they must not overlap.  Each y element is summed by one thread in a fixed
+ * order, so results are bitwise reproducible.  Asynchronous.
+ * Errors: PDZ_EINVAL (null handle/pointer, overlapping x and y, bad dtype). */
+pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* stream);
+
+/* ---------------------------------------------------------------- Lanczos */
+
+typedef struct {
+    int32_t max_iter;      /* >= 1: Lanczos steps at most                                       */
+    double tol;            /* accept when beta_{k+1} |s_k| <= tol * |theta| (>= 0)              */
+    int32_t storage;       /* pdz_dtype of the Krylov vectors and of H.v                        */
+    int32_t reorth;        /* 0: three-term recurrence only; 1: full re-orthogonalisation       */
+    uint64_t seed;         /* start vector when v0 == NULL: SplitMix64 output r -> 2u-1         */
+    int32_t check_every;   /* host reads the device convergence flag every this many steps (>=1) */
+    int32_t use_graph;     /* 1: replay blocks of check_every steps as a captured HIP graph     */
+    int32_t refine;        /* 1: build the Ritz vector and return its FP64 Rayleigh quotient    */
+} pdz_lanczos_opts;
+
+typedef struct {
+    double E0;             /* lowest Ritz value of the tridiagonal T_k                          */
+    double resid_est;      /* beta_{k+1} |s_k|                                                  */
+    double E0_refined;     /* FP64 Rayleigh quotient of the Ritz vector (refine == 1), else E0  */
+    double resid_refined;  /* FP64 |H y - E0_refined y| / |y| (refine == 1), else -1           */
+    double seconds;        /* wall time of the call                                             */
+    int32_t iters;         /* Lanczos steps taken                                               */
+    int32_t converged;     /* 1 if the tolerance was met or the Krylov space became invariant   */
+} pdz_lanczos_result;
+
+/* Fill *o with defaults: max_iter 300, tol 1e-12, F64, no reorth, seed 1,
+ * check_every 10, use_graph 1, refine 0. */
+pdz_status pdz_lanczos_default_opts(pdz_lanczos_opts* o);
+
+/* Bytes of device workspace pdz_lanczos needs for these options. */
+pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, size_t* bytes);
+
+/* Lowest eigenvalue of H by Lanczos (cited in Sec. I), device resident:
+ * H.v, dot products (FP64 accumulation), the alpha/beta recurrence and the
+ * tridiagonal eigensolve (Sturm bisection, FP64) all run on the device; the
+ * host reads one flag per block of check_every steps.
+ * v0: device array of D elements in `storage` precision, or NULL for the
+ *     seeded start vector; it is normalised internally (not modified).
+ * ws: caller-owned device workspace of at least pdz_lanczos_workspace_size
+ *     bytes.  ritz_out: NULL, or a device array of D doubles that receives the
+ *     normalised Ritz vector (forces refine).  Synchronous.
+ * Errors: PDZ_EINVAL (bad options, null handle/result, ws too small, zero or
+ * non-finite start vector); PDZ_ENOCONV when max_iter is reached (res holds
+ * the best estimate). */
+pdz_status pdz_lanczos(pdz_problem p, const pdz_lanczos_opts* o, const void* v0, void* ws, size_t ws_bytes,
+                       double* ritz_out, pdz_lanczos_result* res, void* stream);
+
+/* ------------------------------------------------------------------ misc */
+
+/* Message of the last failing call on this thread ("" if none).  Valid until
+ * the next pdz call on the same thread. */
+const char* pdz_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t pdz_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDZ_H */

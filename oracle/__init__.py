@@ -20,7 +20,7 @@ Everything here is the plain definition, written from the paper:
 
 The oracle shares no code with the HIP path.  Its inputs come from synth/.
 """
-from .fock import (sector_list, popcount, index_in_sorted, composite_keys,
+from .fock import (sector_list, popcount, index_in_sorted, composite_keys, count_below,
                    apply_hop, apply_hop_vec, annihilate_sign, create_sign)
 from .hamiltonian import (Problem, build_csr, hv_rows, diag_values, nnz_structural,
                           one_body_matrix)

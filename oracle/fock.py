@@ -44,6 +44,24 @@ def index_in_sorted(sorted_list: np.ndarray, keys) -> np.ndarray:
     return pos.astype(np.int64)
 
 
+def count_below(x: int, n: int) -> int:
+    """Number of non-negative integers y < x with exactly n set bits.
+
+    Plain counting: every such y agrees with x above some set bit i of x, has
+    0 at bit i, and any n - (ones of x above i) bits among the i lower bits.
+    Equals the position of x in the ascending sector list when popcount(x) = n.
+    """
+    x = int(x)
+    total, ones_above = 0, 0
+    for i in range(x.bit_length() - 1, -1, -1):
+        if (x >> i) & 1:
+            need = n - ones_above
+            if 0 <= need <= i:
+                total += comb(i, need)
+            ones_above += 1
+    return total
+
+
 def composite_keys(up_list: np.ndarray, dn_list: np.ndarray, N: int) -> np.ndarray:
     """Sorted key list of the full basis: key = (phi_up << N) | phi_dn.
 

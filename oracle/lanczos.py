@@ -43,7 +43,12 @@ def lanczos(matvec: Callable[[np.ndarray], np.ndarray], v0: np.ndarray, max_iter
     if not np.isfinite(nrm) or nrm == 0.0:
         raise ValueError("start vector has zero or non-finite norm")
     v /= nrm
-    V = [v] if (reorth or want_vector) else None
+    V = None
+    nV = 0
+    if reorth or want_vector:
+        V = np.empty((max_iter + 1, len(v)), dtype=np.float64)
+        V[0] = v
+        nV = 1
     v_prev = np.zeros_like(v)
     beta = 0.0
     alphas, betas, thetas = [], [], []
@@ -56,8 +61,8 @@ def lanczos(matvec: Callable[[np.ndarray], np.ndarray], v0: np.ndarray, max_iter
         w -= alpha * v
         if reorth:
             for _ in range(2):
-                for q in V:
-                    w -= np.dot(q, w) * q
+                Q = V[:nV]
+                w -= Q.T @ (Q @ w)
         alphas.append(alpha)
         beta_next = float(np.linalg.norm(w))
         theta, s = _lowest(alphas, betas)
@@ -71,11 +76,10 @@ def lanczos(matvec: Callable[[np.ndarray], np.ndarray], v0: np.ndarray, max_iter
         v_prev, v = v, w / beta_next
         beta = beta_next
         if V is not None:
-            V.append(v)
+            V[nV] = v
+            nV += 1
     ritz = None
     if want_vector and V is not None:
         m = len(alphas)
-        ritz = np.zeros_like(v0, dtype=np.float64)
-        for c, q in zip(s, V[:m]):
-            ritz += c * q
+        ritz = V[:m].T @ s
     return LanczosResult(float(theta), k, converged, float(resid), alphas, betas[:len(alphas)], thetas, ritz)

@@ -1,0 +1,157 @@
+"""pdz: perfect-hash (Paradeisos) Hubbard H.v and Lanczos on MI355X.
+
+Thin Python front end of libpdz.so.  torch supplies device memory and
+streams; every step of H.v and Lanczos runs in the HIP library.
+"""
+import ctypes
+
+from . import _lib
+from ._lib import PdzError, PDZ_F64, PDZ_F32, LanczosOpts, LanczosResult
+
+__all__ = ["Problem", "rank", "unrank", "device_errors", "PdzError", "PDZ_F64", "PDZ_F32", "lib",
+           "LanczosOpts", "LanczosResult"]
+
+
+def lib():
+    return _lib.load()
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype_code(dtype):
+    import torch
+    if dtype in (torch.float64, "f64", PDZ_F64):
+        return PDZ_F64
+    if dtype in (torch.float32, "f32", PDZ_F32):
+        return PDZ_F32
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+class Problem:
+    """A Hubbard problem on the current HIP device (pdz_problem handle)."""
+
+    def __init__(self, n_sites, bonds, U, n_up, n_dn):
+        L = lib()
+        arr = (_lib.Bond * max(1, len(bonds)))()
+        for k, b in enumerate(bonds):
+            i, j, t = (b.i, b.j, b.t) if hasattr(b, "i") else b
+            arr[k] = _lib.Bond(int(i), int(j), float(t))
+        h = ctypes.c_void_p()
+        _lib.check(L.pdz_problem_create(int(n_sites), arr if bonds else None, len(bonds), float(U),
+                                        int(n_up), int(n_dn), ctypes.byref(h)))
+        self._h = h
+        self.n_sites, self.U, self.n_up, self.n_dn = n_sites, U, n_up, n_dn
+        self.bonds = list(bonds)
+        self.info = self._info()
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.n_sites, w.bonds, w.U, w.n_up, w.n_dn)
+
+    def _info(self):
+        inf = _lib.Info()
+        _lib.check(lib().pdz_problem_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _lib.Info._fields_}
+
+    @property
+    def D(self):
+        return self.info["D"]
+
+    @property
+    def nnz(self):
+        return self.info["nnz"]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().pdz_problem_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hv(self, x, y=None, stream=None):
+        """y = H x for a contiguous device tensor x (float64 or float32)."""
+        import torch
+        if not x.is_cuda or not x.is_contiguous() or x.numel() != self.D:
+            raise ValueError("x must be a contiguous device tensor of D elements")
+        if y is None:
+            y = torch.empty_like(x)
+        if y.dtype != x.dtype or y.numel() != self.D or not y.is_contiguous():
+            raise ValueError("y must match x")
+        _lib.check(lib().pdz_hv(self._h, _dtype_code(x.dtype), ctypes.c_void_p(x.data_ptr()),
+                                ctypes.c_void_p(y.data_ptr()), _stream_handle(stream)))
+        return y
+
+    def lanczos_opts(self, **kw):
+        o = LanczosOpts()
+        _lib.check(lib().pdz_lanczos_default_opts(ctypes.byref(o)))
+        for k, v in kw.items():
+            if k == "storage":
+                v = _dtype_code(v)
+            setattr(o, k, v)
+        return o
+
+    def workspace_size(self, opts):
+        n = ctypes.c_size_t()
+        _lib.check(lib().pdz_lanczos_workspace_size(self._h, ctypes.byref(opts), ctypes.byref(n)))
+        return n.value
+
+    def lanczos(self, v0=None, ritz=None, workspace=None, stream=None, allow_noconv=True, **kw):
+        """Lowest eigenvalue by the device-resident Lanczos of libpdz.
+
+        Returns a dict with E0, resid_est, E0_refined, resid_refined, seconds,
+        iters, converged, status.
+        """
+        import torch
+        o = self.lanczos_opts(**kw)
+        nbytes = self.workspace_size(o)
+        if workspace is None:
+            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+        res = LanczosResult()
+        st = lib().pdz_lanczos(self._h, ctypes.byref(o),
+                               ctypes.c_void_p(v0.data_ptr()) if v0 is not None else None,
+                               ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                               ctypes.c_void_p(ritz.data_ptr()) if ritz is not None else None,
+                               ctypes.byref(res), _stream_handle(stream))
+        _lib.check(st, allow=(_lib.PDZ_ENOCONV,) if allow_noconv else ())
+        out = {f: getattr(res, f) for f, _ in LanczosResult._fields_}
+        out["status"] = st
+        return out
+
+
+def rank(n_sites, n, bits, stream=None):
+    """Forward map of uint32 occupation strings (device int32/uint32 tensor)."""
+    import torch
+    out = torch.empty_like(bits)
+    _lib.check(lib().pdz_rank(int(n_sites), int(n), ctypes.c_void_p(bits.data_ptr()), bits.numel(),
+                              ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def unrank(n_sites, n, ranks, stream=None):
+    """Backward map of uint32 ranks (device int32/uint32 tensor)."""
+    import torch
+    out = torch.empty_like(ranks)
+    _lib.check(lib().pdz_unrank(int(n_sites), int(n), ctypes.c_void_p(ranks.data_ptr()), ranks.numel(),
+                                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def device_errors():
+    """Synchronise and return (and clear) the device error word."""
+    w = ctypes.c_uint32()
+    st = lib().pdz_device_errors(ctypes.byref(w))
+    if st not in (_lib.PDZ_OK, _lib.PDZ_EDEVICE):
+        _lib.check(st)
+    return w.value

@@ -1,0 +1,105 @@
+"""ctypes binding of libpdz.so: argument marshalling only.
+
+Every step of the hot path runs in the HIP library; this module converts
+Python arguments and torch device tensors into the pointers and sizes of the
+C ABI declared in include/pdz.h, and turns failing status codes into
+PdzError.  It refuses to run without the compiled library.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdz.so")
+
+PDZ_OK = 0
+PDZ_EINVAL = -1
+PDZ_ERANGE = -2
+PDZ_ENOMEM = -3
+PDZ_EHIP = -4
+PDZ_ENOCONV = -5
+PDZ_EDEVICE = -6
+STATUS_NAMES = {0: "PDZ_OK", -1: "PDZ_EINVAL", -2: "PDZ_ERANGE", -3: "PDZ_ENOMEM", -4: "PDZ_EHIP",
+                -5: "PDZ_ENOCONV", -6: "PDZ_EDEVICE"}
+
+PDZ_F64 = 0
+PDZ_F32 = 1
+
+
+class PdzError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Bond(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_int32), ("j", ctypes.c_int32), ("t", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_uint64), ("D_up", ctypes.c_uint64), ("D_dn", ctypes.c_uint64),
+                ("nnz", ctypes.c_uint64), ("hops_up", ctypes.c_uint64), ("hops_dn", ctypes.c_uint64),
+                ("n_sites", ctypes.c_int32), ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32),
+                ("n_bonds", ctypes.c_int32), ("max_hops_up", ctypes.c_int32), ("max_hops_dn", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("hv_path", ctypes.c_int32)]
+
+
+class LanczosOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("storage", ctypes.c_int32),
+                ("reorth", ctypes.c_int32), ("seed", ctypes.c_uint64), ("check_every", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("refine", ctypes.c_int32)]
+
+
+class LanczosResult(ctypes.Structure):
+    _fields_ = [("E0", ctypes.c_double), ("resid_est", ctypes.c_double), ("E0_refined", ctypes.c_double),
+                ("resid_refined", ctypes.c_double), ("seconds", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "pdz_problem_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(Bond), ctypes.c_int32, ctypes.c_double,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "pdz_problem_destroy": (ctypes.c_int32, [_P]),
+    "pdz_problem_info": (ctypes.c_int32, [_P, ctypes.POINTER(Info)]),
+    "pdz_rank": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]),
+    "pdz_unrank": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]),
+    "pdz_device_errors": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_uint32)]),
+    "pdz_hv": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, _P]),
+    "pdz_lanczos_default_opts": (ctypes.c_int32, [ctypes.POINTER(LanczosOpts)]),
+    "pdz_lanczos_workspace_size": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), ctypes.POINTER(ctypes.c_size_t)]),
+    "pdz_lanczos": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, _P, ctypes.c_size_t, _P,
+                                     ctypes.POINTER(LanczosResult), _P]),
+    "pdz_last_error": (ctypes.c_char_p, []),
+    "pdz_version": (ctypes.c_int32, []),
+}
+
+_lib = None
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def load(path: str = LIB_PATH):
+    """Load libpdz.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1707_03974_amd.build` "
+                          "(the HIP library is required; there is no fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int, allow=()):
+    if status != PDZ_OK and status not in allow:
+        msg = load().pdz_last_error()
+        raise PdzError(status, msg.decode() if msg else "")
+    return status

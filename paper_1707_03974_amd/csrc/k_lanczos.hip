@@ -1,0 +1,763 @@
+// Device-resident Lanczos for the lowest eigenvalue of H (the Krylov method
+// cited in Sec. I).
+//
+// Recurrence (FP64 scalars):
+//     w = H v_k;  alpha_k = <v_k, w>;  w -= alpha_k v_k + beta_k v_{k-1};
+//     [full re-orthogonalisation against v_1..v_k, twice];
+//     beta_{k+1} = |w|;  v_{k+1} = w / beta_{k+1}.
+// T_k = tridiag(beta, alpha, beta).  Its lowest eigenvalue theta comes from
+// Sturm-count multisection, its eigenvector s from inverse iteration, and the
+// Ritz pair is accepted when beta_{k+1} |s_k| <= tol |theta|.
+//
+// Vectors may be stored in FP32 or FP64; every dot product multiplies in FP64
+// and accumulates in FP64.  Reductions use a fixed grid and a fixed tree, so
+// results are bitwise reproducible run to run.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pdz_internal.h"
+
+namespace pdz {
+
+namespace {
+
+constexpr int kRedBlock = 256;
+constexpr int kRedGrid = 1024;   // partial sums per reduction (fixed for determinism)
+constexpr int kMaxIter = 2000;
+
+struct Ctl {
+    int k;          // completed Lanczos steps
+    int done;       // non-zero: every later kernel of the run is a no-op
+    int converged;  // tolerance met or invariant subspace
+    int breakdown;  // beta_{k+1} vanished
+    double theta;   // lowest Ritz value of T_k
+    double resid;   // beta_{k+1} |s_k|
+    double norm0;   // norm of the start vector
+    double scratch[4];
+};
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// SplitMix64, output r of the generator seeded with `seed`, as a double in [-1, 1).
+__device__ __forceinline__ double splitmix_uniform(uint64_t seed, uint64_t r) {
+    uint64_t z = seed + (r + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_random_start(T* v, uint64_t D, uint64_t seed) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x)
+        v[i] = (T)splitmix_uniform(seed, i);
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(kRedBlock) void k_copy(const TS* __restrict__ s, TD* __restrict__ d, uint64_t D) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x)
+        d[i] = (TD)s[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_fill_zero(T* v, uint64_t D) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x)
+        v[i] = (T)0;
+}
+
+__global__ void k_set_step(Ctl* c, int k, int done) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->k = k;
+        c->done = done;
+    }
+}
+
+__global__ void k_clear_bits(uint32_t* err, uint32_t bits) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicAnd(err, ~bits);
+}
+
+__global__ void k_init_ctl(Ctl* c, double* beta) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->k = 0;
+        c->done = 0;
+        c->converged = 0;
+        c->breakdown = 0;
+        c->theta = 0.0;
+        c->resid = 0.0;
+        c->norm0 = 0.0;
+        beta[0] = 0.0;
+    }
+}
+
+// partial[blockIdx] = sum over the block's strided elements of a[i] * b[i] (FP64)
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kRedBlock) void k_dot_partial(const TA* __restrict__ a, const TB* __restrict__ b,
+                                                           uint64_t D, double* partial, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[kRedBlock];
+    double acc = 0.0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x)
+        acc += (double)a[i] * (double)b[i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+enum FinalMode { kStoreSum = 0, kStoreSqrt = 1 };
+
+// out[index] = sum(partial) or sqrt(sum); index = *kidx + off when kidx != NULL.
+__global__ __launch_bounds__(kRedBlock) void k_finalize(const double* partial, int n, double* out, const int* kidx,
+                                                        int off, int mode, const int* skip, uint32_t* err) {
+    if (skip && *skip) return;
+    __shared__ double red[kRedBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partial[i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        const double v = (mode == kStoreSqrt) ? sqrt(acc) : acc;
+        out[(kidx ? *kidx : 0) + off] = v;
+        if (!isfinite(v)) atomicOr(err, kErrNonFinite);
+    }
+}
+
+// v *= 1 / s[*kidx + off]
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_scale(T* v, uint64_t D, const double* s, const int* kidx, int off,
+                                                     const int* skip) {
+    if (skip && *skip) return;
+    const double inv = 1.0 / s[(kidx ? *kidx : 0) + off];
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x)
+        v[i] = (T)((double)v[i] * inv);
+}
+
+// w -= alpha_k v + beta_k vprev, partial[] = |w|^2 of the stored result.
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_update(T* __restrict__ w, const T* __restrict__ v,
+                                                      const T* __restrict__ vp, uint64_t D, const double* alpha,
+                                                      const double* beta, const int* kidx, double* partial,
+                                                      const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[kRedBlock];
+    const int k = *kidx;
+    const double a = alpha[k], b = beta[k];
+    double acc = 0.0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x) {
+        const T r = (T)((double)w[i] - a * (double)v[i] - b * (double)vp[i]);
+        w[i] = r;
+        acc += (double)r * (double)r;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Full re-orthogonalisation: c_j = <V_j, w> for j < nvec (grid.y = j).
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_dots_basis(const T* __restrict__ V, uint64_t ld, uint64_t D, int nvec,
+                                                          const T* __restrict__ w, double* partial, const int* skip) {
+    if (*skip) return;
+    const int j = blockIdx.y;
+    if (j >= nvec) return;
+    __shared__ double red[kRedBlock];
+    const T* q = V + (uint64_t)j * ld;
+    double acc = 0.0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x)
+        acc += (double)q[i] * (double)w[i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[(uint64_t)j * gridDim.x + blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_finalize_basis(const double* partial, int n, double* c,
+                                                              const int* skip) {
+    if (*skip) return;
+    __shared__ double red[kRedBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partial[(uint64_t)blockIdx.x * n + i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) c[blockIdx.x] = acc;
+}
+
+// w -= sum_j c_j V_j
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_sub_basis(const T* __restrict__ V, uint64_t ld, uint64_t D, int nvec,
+                                                         const double* __restrict__ c, T* __restrict__ w,
+                                                         const int* skip) {
+    if (*skip) return;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x) {
+        double acc = (double)w[i];
+        for (int j = 0; j < nvec; ++j) acc -= c[j] * (double)V[(uint64_t)j * ld + i];
+        w[i] = (T)acc;
+    }
+}
+
+// y += s_j v (FP64 y)
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_axpy_coef(double* __restrict__ y, const T* __restrict__ v, uint64_t D,
+                                                         const double* s, int j) {
+    const double c = s[j];
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x)
+        y[i] += c * (double)v[i];
+}
+
+// y = sum_j s_j V_j
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_combine_basis(double* __restrict__ y, const T* __restrict__ V,
+                                                             uint64_t ld, uint64_t D, int m,
+                                                             const double* __restrict__ s) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc += s[j] * (double)V[(uint64_t)j * ld + i];
+        y[i] = acc;
+    }
+}
+
+// partial[] = |Hy - theta y|^2, theta = *th
+__global__ __launch_bounds__(kRedBlock) void k_resid_partial(const double* __restrict__ hy, const double* __restrict__ y,
+                                                             uint64_t D, const double* th, double* partial) {
+    __shared__ double red[kRedBlock];
+    const double t = *th;
+    double acc = 0.0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x) {
+        const double r = hy[i] - t * y[i];
+        acc += r * r;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Number of eigenvalues of T below x (Sturm sequence via the LDL^T pivots).
+__device__ int sturm_count(const double* a, const double* e, int k, double x) {
+    int cnt = 0;
+    double q = a[0] - x;
+    if (q < 0.0) ++cnt;
+    for (int i = 1; i < k; ++i) {
+        if (q == 0.0) q = 1e-300;
+        q = (a[i] - x) - e[i] * e[i] / q;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// One block: theta = lambda_min(T_k), s = its normalised eigenvector, the
+// convergence test, and the step counter.  alpha[0..k-1] is the diagonal,
+// beta[1..k-1] the off-diagonal, beta[k] = beta_{k+1}.
+__global__ __launch_bounds__(kRedBlock) void k_tridiag(const double* alpha, const double* beta, double* s_out,
+                                                       double* theta_hist, Ctl* ctl, double tol, int max_iter,
+                                                       uint32_t* err) {
+    if (ctl->done) return;
+    __shared__ double a[kMaxIter];
+    __shared__ double e[kMaxIter];
+    __shared__ double lo_s[kRedBlock], hi_s[kRedBlock];
+    __shared__ int found;
+    __shared__ double bounds[2];
+    const int k = ctl->k + 1;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        a[i] = alpha[i];
+        e[i] = (i == 0) ? 0.0 : beta[i];
+    }
+    __syncthreads();
+    // Gershgorin interval
+    double lo = 1e300, hi = -1e300;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        const double r = fabs(e[i]) + (i + 1 < k ? fabs(e[i + 1]) : 0.0);
+        lo = fmin(lo, a[i] - r);
+        hi = fmax(hi, a[i] + r);
+    }
+    lo_s[threadIdx.x] = lo;
+    hi_s[threadIdx.x] = hi;
+    __syncthreads();
+    for (int st = kRedBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            lo_s[threadIdx.x] = fmin(lo_s[threadIdx.x], lo_s[threadIdx.x + st]);
+            hi_s[threadIdx.x] = fmax(hi_s[threadIdx.x], hi_s[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double pad = 1e-12 * fmax(1.0, fmax(fabs(lo_s[0]), fabs(hi_s[0])));
+        bounds[0] = lo_s[0] - pad;
+        bounds[1] = hi_s[0] + pad;
+    }
+    __syncthreads();
+    // multisection: each round splits [lo, hi] into blockDim+1 pieces
+    for (int round = 0; round < 64; ++round) {
+        lo = bounds[0];
+        hi = bounds[1];
+        if (!(hi - lo > 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
+        const double x = lo + (hi - lo) * (double)(threadIdx.x + 1) / (double)(blockDim.x + 1);
+        if (threadIdx.x == 0) found = blockDim.x;
+        __syncthreads();
+        const int c = sturm_count(a, e, k, x);
+        if (c >= 1) atomicMin(&found, (int)threadIdx.x);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int t = found;
+            const double nlo = (t == 0) ? lo : lo + (hi - lo) * (double)t / (double)(blockDim.x + 1);
+            const double nhi = (t == (int)blockDim.x) ? hi : lo + (hi - lo) * (double)(t + 1) / (double)(blockDim.x + 1);
+            bounds[0] = nlo;
+            bounds[1] = nhi;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double theta = 0.5 * (bounds[0] + bounds[1]);
+        // inverse iteration with shift below the eigenvalue: T - sigma I is positive semidefinite
+        const double sigma = bounds[0] - 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(bounds[0]));
+        double* z = s_out;
+        for (int i = 0; i < k; ++i) z[i] = 1.0;
+        double nrm = 0.0;
+        for (int it = 0; it < 3; ++it) {
+            // LDL^T solve of (T - sigma I) z = z; d and l reuse lo_s/hi_s only when k fits, else recompute
+            double dprev = a[0] - sigma;
+            if (dprev == 0.0) dprev = 1e-300;
+            // forward: L y = b  (store y in z), with pivots d_i
+            // we need d_i again in the backward pass; keep them in e-shaped storage of theta_hist tail
+            double* dpiv = theta_hist + max_iter;   // scratch of length max_iter
+            dpiv[0] = dprev;
+            for (int i = 1; i < k; ++i) {
+                const double l = e[i] / dpiv[i - 1];
+                double di = (a[i] - sigma) - l * e[i];
+                if (di == 0.0) di = 1e-300;
+                dpiv[i] = di;
+                z[i] -= l * z[i - 1];
+            }
+            // D x = y, L^T z = x
+            z[k - 1] /= dpiv[k - 1];
+            for (int i = k - 2; i >= 0; --i) z[i] = z[i] / dpiv[i] - (e[i + 1] / dpiv[i]) * z[i + 1];
+            nrm = 0.0;
+            for (int i = 0; i < k; ++i) nrm += z[i] * z[i];
+            nrm = sqrt(nrm);
+            if (!(nrm > 0.0) || !isfinite(nrm)) break;
+            for (int i = 0; i < k; ++i) z[i] /= nrm;
+        }
+        const double bk1 = beta[k];
+        const double resid = fabs(bk1 * z[k - 1]);
+        theta_hist[k - 1] = theta;
+        ctl->theta = theta;
+        ctl->resid = resid;
+        ctl->k = k;
+        const double scale = fmax(fabs(theta), 1e-300);
+        const bool breakdown = !(bk1 > 1e-14 * fmax(1.0, fabs(theta)));
+        const bool conv = breakdown || resid <= tol * scale;
+        if (!isfinite(theta) || !isfinite(bk1)) {
+            atomicOr(err, kErrNonFinite);
+            ctl->done = 1;
+        }
+        if (conv) {
+            ctl->converged = 1;
+            ctl->breakdown = breakdown ? 1 : 0;
+            ctl->done = 1;
+        }
+        if (k >= max_iter) ctl->done = 1;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t vec = 0;
+    size_t buf[3] = {0, 0, 0};
+    size_t basis = 0;
+    size_t y = 0, hy = 0;
+    size_t alpha = 0, beta = 0, theta = 0, s = 0, partial = 0, coefs = 0, ctl = 0;
+    size_t total = 0;
+    int nvec_basis = 0;
+};
+
+Layout make_layout(uint64_t D, const pdz_lanczos_opts* o) {
+    Layout L;
+    const size_t es = o->storage == PDZ_F64 ? 8 : 4;
+    L.vec = align256((size_t)D * es);
+    size_t off = 0;
+    if (o->reorth) {
+        L.nvec_basis = o->max_iter + 1;
+        L.basis = off;
+        off += L.vec * (size_t)L.nvec_basis;
+        L.buf[0] = off;   // zero vector for v_0
+        off += L.vec;
+    } else {
+        for (int i = 0; i < 3; ++i) {
+            L.buf[i] = off;
+            off += L.vec;
+        }
+    }
+    if (o->refine) {
+        L.y = off;
+        off += align256((size_t)D * 8);
+        L.hy = off;
+        off += align256((size_t)D * 8);
+    }
+    const size_t m = (size_t)o->max_iter + 8;
+    L.alpha = off;
+    off += align256(m * 8);
+    L.beta = off;
+    off += align256(m * 8);
+    L.theta = off;
+    off += align256(2 * m * 8);
+    L.s = off;
+    off += align256(m * 8);
+    L.partial = off;
+    off += align256((size_t)kRedGrid * (o->reorth ? m : 1) * 8);
+    L.coefs = off;
+    off += align256(m * 8);
+    L.ctl = off;
+    off += align256(sizeof(Ctl));
+    L.total = off;
+    return L;
+}
+
+unsigned grid_elems(uint64_t D) {
+    uint64_t g = (D + kRedBlock - 1) / kRedBlock;
+    if (g > (uint64_t)kRedGrid * 4) g = (uint64_t)kRedGrid * 4;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+template <typename T>
+struct Run {
+    const pdz_problem_s* p;
+    const pdz_lanczos_opts* o;
+    Layout L;
+    char* ws;
+    hipStream_t s;
+    uint32_t* err;
+    uint64_t D;
+    T* buf(int i) const { return reinterpret_cast<T*>(ws + L.buf[i]); }
+    T* basis(int j) const { return reinterpret_cast<T*>(ws + L.basis + (size_t)j * L.vec); }
+    uint64_t ld() const { return L.vec / sizeof(T); }
+    double* y() const { return reinterpret_cast<double*>(ws + L.y); }
+    double* hy() const { return reinterpret_cast<double*>(ws + L.hy); }
+    double* alpha() const { return reinterpret_cast<double*>(ws + L.alpha); }
+    double* beta() const { return reinterpret_cast<double*>(ws + L.beta); }
+    double* theta() const { return reinterpret_cast<double*>(ws + L.theta); }
+    double* svec() const { return reinterpret_cast<double*>(ws + L.s); }
+    double* partial() const { return reinterpret_cast<double*>(ws + L.partial); }
+    double* coefs() const { return reinterpret_cast<double*>(ws + L.coefs); }
+    Ctl* ctl() const { return reinterpret_cast<Ctl*>(ws + L.ctl); }
+    int* done() const { return &ctl()->done; }
+    int* kptr() const { return &ctl()->k; }
+
+    pdz_status launch_check() {
+        PDZ_HIP(hipGetLastError());
+        return ok();
+    }
+
+    // v_1 = v0 / |v0| into dst; zero vector into zero_dst.
+    pdz_status start(const void* v0, T* dst, T* zero_dst) {
+        const unsigned g = grid_elems(D);
+        hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, ctl(), beta());
+        if (v0)
+            hipLaunchKernelGGL((k_copy<T, T>), dim3(g), dim3(kRedBlock), 0, s, static_cast<const T*>(v0), dst, D);
+        else
+            hipLaunchKernelGGL(k_random_start<T>, dim3(g), dim3(kRedBlock), 0, s, dst, D, (uint64_t)o->seed);
+        hipLaunchKernelGGL(k_fill_zero<T>, dim3(g), dim3(kRedBlock), 0, s, zero_dst, D);
+        hipLaunchKernelGGL((k_dot_partial<T, T>), dim3(kRedGrid), dim3(kRedBlock), 0, s, dst, dst, D, partial(),
+                           (const int*)nullptr);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, &ctl()->norm0,
+                           (const int*)nullptr, 0, (int)kStoreSqrt, (const int*)nullptr, err);
+        pdz_status st = launch_check();
+        if (st != PDZ_OK) return st;
+        Ctl h;
+        PDZ_HIP(hipMemcpyAsync(&h, ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        PDZ_HIP(hipStreamSynchronize(s));
+        if (!(h.norm0 > 0.0) || !std::isfinite(h.norm0))
+            return fail(PDZ_EINVAL, "start vector has zero or non-finite norm");
+        hipLaunchKernelGGL(k_scale<T>, dim3(g), dim3(kRedBlock), 0, s, dst, D, &ctl()->norm0, (const int*)nullptr, 0,
+                           (const int*)nullptr);
+        return launch_check();
+    }
+
+    // One Lanczos step with v = v_k, vp = v_{k-1}, w the output slot.
+    // `reorth_nvec` > 0: re-orthogonalise against basis(0..reorth_nvec-1).
+    pdz_status step(T* v, T* vp, T* w, int reorth_nvec) {
+        const unsigned g = grid_elems(D);
+        pdz_status st = launch_hv(p, (pdz_dtype)o->storage, v, w, s, done());
+        if (st != PDZ_OK) return st;
+        hipLaunchKernelGGL((k_dot_partial<T, T>), dim3(kRedGrid), dim3(kRedBlock), 0, s, v, w, D, partial(), done());
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, alpha(), kptr(), 0,
+                           (int)kStoreSum, done(), err);
+        hipLaunchKernelGGL(k_update<T>, dim3(kRedGrid), dim3(kRedBlock), 0, s, w, v, vp, D, alpha(), beta(), kptr(),
+                           partial(), done());
+        if (reorth_nvec > 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_dots_basis<T>, dim3(kRedGrid, reorth_nvec), dim3(kRedBlock), 0, s, basis(0), ld(), D,
+                                   reorth_nvec, w, partial(), done());
+                hipLaunchKernelGGL(k_finalize_basis, dim3(reorth_nvec), dim3(kRedBlock), 0, s, partial(), kRedGrid,
+                                   coefs(), done());
+                hipLaunchKernelGGL(k_sub_basis<T>, dim3(g), dim3(kRedBlock), 0, s, basis(0), ld(), D, reorth_nvec, coefs(), w,
+                                   done());
+            }
+            hipLaunchKernelGGL((k_dot_partial<T, T>), dim3(kRedGrid), dim3(kRedBlock), 0, s, w, w, D, partial(), done());
+        }
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, beta(), kptr(), 1,
+                           (int)kStoreSqrt, done(), err);
+        hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kRedBlock), 0, s, alpha(), beta(), svec(), theta(), ctl(), o->tol,
+                           o->max_iter, err);
+        hipLaunchKernelGGL(k_scale<T>, dim3(g), dim3(kRedBlock), 0, s, w, D, beta(), kptr(), 0, done());
+        return launch_check();
+    }
+
+    pdz_status read_ctl(Ctl* h) {
+        PDZ_HIP(hipMemcpyAsync(h, ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        PDZ_HIP(hipStreamSynchronize(s));
+        return ok();
+    }
+
+    pdz_status iterate(Ctl* h) {
+        pdz_status st;
+        if (o->reorth) {
+            for (int k = 1; k <= o->max_iter; ++k) {
+                // v_k = basis(k-1), v_{k-1} = basis(k-2) or the zero vector, w -> basis(k)
+                T* vp = (k >= 2) ? basis(k - 2) : buf(0);
+                st = step(basis(k - 1), vp, basis(k), k);
+                if (st != PDZ_OK) return st;
+                if (k % o->check_every == 0 || k == o->max_iter) {
+                    st = read_ctl(h);
+                    if (st != PDZ_OK) return st;
+                    if (h->done) return ok();
+                }
+            }
+            return read_ctl(h);
+        }
+        // three rotating buffers; a block of `period` steps (multiple of 3) keeps the rotation aligned
+        int period = o->check_every;
+        if (period % 3) period += 3 - period % 3;
+        auto enqueue_block = [&]() -> pdz_status {
+            for (int t = 0; t < period; ++t) {
+                const int a = t % 3;
+                pdz_status s2 = step(buf(a), buf((a + 2) % 3), buf((a + 1) % 3), 0);
+                if (s2 != PDZ_OK) return s2;
+            }
+            return ok();
+        };
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph = nullptr;
+        if (o->use_graph) {
+            PDZ_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            st = enqueue_block();
+            hipGraph_t g2 = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &g2);
+            if (st != PDZ_OK) {
+                if (g2) (void)hipGraphDestroy(g2);
+                return st;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            graph = g2;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+        }
+        st = ok();
+        for (int done_steps = 0; done_steps < o->max_iter; done_steps += period) {
+            if (exec) {
+                hipError_t e = hipGraphLaunch(exec, s);
+                if (e != hipSuccess) {
+                    st = hip_fail(e, "hipGraphLaunch");
+                    break;
+                }
+            } else {
+                st = enqueue_block();
+                if (st != PDZ_OK) break;
+            }
+            st = read_ctl(h);
+            if (st != PDZ_OK || h->done) break;
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (st != PDZ_OK) return st;
+        return read_ctl(h);
+    }
+
+    // Ritz vector y = sum_j s_j v_j (FP64), normalised; FP64 Rayleigh quotient and residual.
+    pdz_status refine(const void* v0, int m, double* E_ref, double* r_ref) {
+        const unsigned g = grid_elems(D);
+        if (o->reorth) {
+            hipLaunchKernelGGL(k_combine_basis<T>, dim3(g), dim3(kRedBlock), 0, s, y(), basis(0), ld(), D, m, svec());
+        } else {
+            // regenerate v_1..v_m with the same kernels and the stored alpha, beta
+            Ctl saved;
+            pdz_status st = read_ctl(&saved);
+            if (st != PDZ_OK) return st;
+            std::vector<double> alpha_h(m + 1), beta_h(m + 2), s_h(m);
+            PDZ_HIP(hipMemcpyAsync(alpha_h.data(), alpha(), (size_t)m * 8, hipMemcpyDeviceToHost, s));
+            PDZ_HIP(hipMemcpyAsync(beta_h.data(), beta(), (size_t)(m + 1) * 8, hipMemcpyDeviceToHost, s));
+            PDZ_HIP(hipStreamSynchronize(s));
+            st = start(v0, buf(0), buf(2));
+            if (st != PDZ_OK) return st;
+            // restore the recurrence coefficients overwritten by start()
+            PDZ_HIP(hipMemcpyAsync(alpha(), alpha_h.data(), (size_t)m * 8, hipMemcpyHostToDevice, s));
+            PDZ_HIP(hipMemcpyAsync(beta(), beta_h.data(), (size_t)(m + 1) * 8, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_fill_zero<double>, dim3(g), dim3(kRedBlock), 0, s, y(), D);
+            for (int j = 0; j < m; ++j) {
+                const int a = j % 3;
+                T* v = buf(a);
+                T* vp = buf((a + 2) % 3);
+                T* w = buf((a + 1) % 3);
+                hipLaunchKernelGGL(k_axpy_coef<T>, dim3(g), dim3(kRedBlock), 0, s, y(), v, D, svec(), j);
+                if (j + 1 < m) {
+                    // the step kernels read alpha/beta at index *kptr: set k = j on the device
+                    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, ctl(), j, 0);
+                    st = launch_hv(p, (pdz_dtype)o->storage, v, w, s, nullptr);
+                    if (st != PDZ_OK) return st;
+                    hipLaunchKernelGGL(k_update<T>, dim3(kRedGrid), dim3(kRedBlock), 0, s, w, v, vp, D, alpha(), beta(),
+                                       kptr(), partial(), (const int*)nullptr);
+                    hipLaunchKernelGGL(k_scale<T>, dim3(g), dim3(kRedBlock), 0, s, w, D, beta(), kptr(), 1,
+                                       (const int*)nullptr);
+                }
+            }
+            hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, ctl(), saved.k, saved.done);
+        }
+        double* sc = &ctl()->scratch[0];
+        hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(kRedGrid), dim3(kRedBlock), 0, s, y(), y(), D,
+                           partial(), (const int*)nullptr);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, sc, (const int*)nullptr, 0,
+                           (int)kStoreSqrt, (const int*)nullptr, err);
+        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kRedBlock), 0, s, y(), D, sc, (const int*)nullptr, 0,
+                           (const int*)nullptr);
+        pdz_status st = launch_hv(p, PDZ_F64, y(), hy(), s, nullptr);
+        if (st != PDZ_OK) return st;
+        hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(kRedGrid), dim3(kRedBlock), 0, s, y(), hy(), D,
+                           partial(), (const int*)nullptr);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, sc + 1,
+                           (const int*)nullptr, 0, (int)kStoreSum, (const int*)nullptr, err);
+        hipLaunchKernelGGL(k_resid_partial, dim3(kRedGrid), dim3(kRedBlock), 0, s, hy(), y(), D, sc + 1, partial());
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, sc + 2,
+                           (const int*)nullptr, 0, (int)kStoreSqrt, (const int*)nullptr, err);
+        st = launch_check();
+        if (st != PDZ_OK) return st;
+        double h[3];
+        PDZ_HIP(hipMemcpyAsync(h, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        PDZ_HIP(hipStreamSynchronize(s));
+        *E_ref = h[1];
+        *r_ref = h[2];
+        return ok();
+    }
+
+    pdz_status run(const void* v0, double* ritz_out, pdz_lanczos_result* res) {
+        T* v1 = o->reorth ? basis(0) : buf(0);
+        T* zero = o->reorth ? buf(0) : buf(2);
+        pdz_status st = start(v0, v1, zero);
+        if (st != PDZ_OK) return st;
+        Ctl h;
+        st = iterate(&h);
+        if (st != PDZ_OK) return st;
+        uint32_t word = 0;
+        PDZ_HIP(hipMemcpyAsync(&word, err, sizeof(word), hipMemcpyDeviceToHost, s));
+        PDZ_HIP(hipStreamSynchronize(s));
+        if (word & kErrNonFinite) {
+            hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, s, err, kErrNonFinite);
+            (void)hipStreamSynchronize(s);
+            return fail(PDZ_EINVAL, "non-finite Lanczos scalar (start vector or H)");
+        }
+        res->E0 = h.theta;
+        res->resid_est = h.resid;
+        res->iters = h.k;
+        res->converged = h.converged;
+        res->E0_refined = h.theta;
+        res->resid_refined = -1.0;
+        if (o->refine && h.k > 0) {
+            st = refine(v0, h.k, &res->E0_refined, &res->resid_refined);
+            if (st != PDZ_OK) return st;
+            if (ritz_out) PDZ_HIP(hipMemcpyAsync(ritz_out, y(), (size_t)D * 8, hipMemcpyDeviceToDevice, s));
+        }
+        PDZ_HIP(hipStreamSynchronize(s));
+        return h.converged ? ok() : fail(PDZ_ENOCONV, "max_iter reached before the tolerance");
+    }
+};
+
+pdz_status check_opts(const pdz_lanczos_opts* o) {
+    if (!o) return fail(PDZ_EINVAL, "opts is NULL");
+    if (o->max_iter < 1 || o->max_iter > kMaxIter) return fail(PDZ_EINVAL, "max_iter must be in [1, 2000]");
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(PDZ_EINVAL, "tol must be finite and >= 0");
+    if (o->storage != PDZ_F64 && o->storage != PDZ_F32) return fail(PDZ_EINVAL, "storage must be F64 or F32");
+    if (o->reorth != 0 && o->reorth != 1) return fail(PDZ_EINVAL, "reorth must be 0 or 1");
+    if (o->check_every < 1) return fail(PDZ_EINVAL, "check_every must be >= 1");
+    if (o->refine != 0 && o->refine != 1) return fail(PDZ_EINVAL, "refine must be 0 or 1");
+    return ok();
+}
+
+}  // namespace
+}  // namespace pdz
+
+using namespace pdz;
+
+extern "C" {
+
+pdz_status pdz_lanczos_default_opts(pdz_lanczos_opts* o) {
+    if (!o) return fail(PDZ_EINVAL, "opts is NULL");
+    std::memset(o, 0, sizeof(*o));
+    o->max_iter = 300;
+    o->tol = 1e-12;
+    o->storage = PDZ_F64;
+    o->reorth = 0;
+    o->seed = 1;
+    o->check_every = 10;
+    o->use_graph = 1;
+    o->refine = 0;
+    return ok();
+}
+
+pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, size_t* bytes) {
+    if (!p || !bytes) return fail(PDZ_EINVAL, "NULL argument");
+    pdz_status st = check_opts(o);
+    if (st != PDZ_OK) return st;
+    pdz_lanczos_opts oo = *o;
+    *bytes = make_layout(p->D, &oo).total;
+    return ok();
+}
+
+pdz_status pdz_lanczos(pdz_problem p, const pdz_lanczos_opts* o, const void* v0, void* ws, size_t ws_bytes,
+                       double* ritz_out, pdz_lanczos_result* res, void* stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!p || !res) return fail(PDZ_EINVAL, "NULL problem or result");
+    pdz_status st = check_opts(o);
+    if (st != PDZ_OK) return st;
+    std::memset(res, 0, sizeof(*res));
+    pdz_lanczos_opts oo = *o;
+    if (ritz_out) oo.refine = 1;
+    if (oo.reorth) oo.use_graph = 0;
+    const Layout L = make_layout(p->D, &oo);
+    if (!ws) return fail(PDZ_EINVAL, "workspace is NULL");
+    if (ws_bytes < L.total) return fail(PDZ_EINVAL, "workspace smaller than pdz_lanczos_workspace_size");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PDZ_EINVAL, "workspace must be 256-byte aligned");
+    int dev = 0;
+    PDZ_HIP(hipGetDevice(&dev));
+    if (dev != p->device) return fail(PDZ_EINVAL, "problem lives on another device");
+    DeviceCtx* ctx = nullptr;
+    st = device_ctx(&ctx);
+    if (st != PDZ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipStream_t own = nullptr;
+    if (!s && oo.use_graph) {
+        // capture needs a stream other than the legacy default stream
+        PDZ_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        PDZ_HIP(hipDeviceSynchronize());
+        s = own;
+    }
+    if (oo.storage == PDZ_F64) {
+        Run<double> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, p->D};
+        st = r.run(v0, ritz_out, res);
+    } else {
+        Run<float> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, p->D};
+        st = r.run(v0, ritz_out, res);
+    }
+    if (own) {
+        (void)hipStreamSynchronize(own);
+        (void)hipStreamDestroy(own);
+    }
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal declarations shared by the pdz host runtime and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pdz.h"
+
+namespace pdz {
+
+constexpr int kMaxSites = 32;
+constexpr int kBinomStride = kMaxSites + 1;          // C[i * 33 + m], i, m in [0, 32]
+constexpr uint32_t kTargetBits = 24;                   // hop-table entry: target | coef << 24
+constexpr uint32_t kTargetMask = (1u << kTargetBits) - 1u;
+constexpr int kMaxCoef = 256;                          // distinct signed hop amplitudes
+constexpr uint32_t kBadRank = 0xFFFFFFFFu;
+
+// Device error word bits.
+constexpr uint32_t kErrRankInput = 1u;     // pdz_rank: popcount or width mismatch
+constexpr uint32_t kErrUnrankInput = 2u;   // pdz_unrank: rank out of range
+constexpr uint32_t kErrTable = 4u;         // hop-table build: a target failed to rank
+constexpr uint32_t kErrNonFinite = 8u;     // Lanczos: non-finite scalar
+
+// One bond as the kernels see it.
+struct BondDev {
+    uint32_t mask;      // (1<<i) | (1<<j)
+    uint32_t between;   // bits strictly between min(i,j) and max(i,j)
+    int32_t coef_pos;   // index of -t in the coefficient table (even number of passed operators)
+    int32_t coef_neg;   // index of +t (odd number)
+};
+
+// Per-spin sector tables on the device (ELL layout, hop slot major).
+struct SectorTables {
+    uint64_t D = 0;             // sector size C(N, n)
+    int n = 0;                  // electrons of this spin
+    int max_hops = 0;           // most hops out of one state
+    uint64_t total_hops = 0;    // hops summed over the sector
+    uint32_t* states = nullptr; // D occupation strings (backward map of each rank)
+    uint8_t* count = nullptr;   // D hop counts
+    uint32_t* ell = nullptr;    // max_hops * D entries: ell[h * D + s] = target | coef << 24
+};
+
+// Kernel-side view of a problem for H.v.
+template <typename T>
+struct HvArgs {
+    uint64_t D_up, D_dn;
+    T U;
+    const uint32_t* up_states;
+    const uint8_t* up_count;
+    const uint32_t* up_ell;
+    const uint32_t* dn_states;
+    const uint8_t* dn_count;
+    const uint32_t* dn_ell;
+    const T* coef;         // signed hop amplitudes
+    int ncoef;
+    int rows_per_group;    // rows staged together in LDS
+    const int* skip;       // optional device flag: when non-zero the launch does nothing
+};
+
+}  // namespace pdz
+
+struct pdz_problem_s {
+    int device = 0;
+    int N = 0, n_up = 0, n_dn = 0, n_bonds = 0;
+    double U = 0.0;
+    std::vector<pdz_bond> bonds;
+    uint64_t D = 0, nnz = 0;
+    pdz::SectorTables up, dn;
+    bool same_sector = false;            // dn tables alias the up tables
+    uint32_t* d_binom = nullptr;         // 33 x 33 binomial table
+    pdz::BondDev* d_bonds = nullptr;
+    std::vector<double> coef_host;       // signed hop amplitudes
+    double* d_coef64 = nullptr;
+    float* d_coef32 = nullptr;
+    int hv_path = 0;                     // 0 tables, 1 on the fly
+};
+
+namespace pdz {
+
+// Error reporting (thread-local message).
+pdz_status fail(pdz_status code, const std::string& msg);
+pdz_status ok();
+pdz_status hip_fail(hipError_t e, const char* what);
+#define PDZ_HIP(call)                                        \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return pdz::hip_fail(e_, #call); \
+    } while (0)
+
+// Per-device context: error word and small scratch.
+struct DeviceCtx {
+    int device = -1;
+    uint32_t* err = nullptr;       // device error word
+    uint32_t* binom = nullptr;     // 33 x 33 binomial table
+    int cu_count = 0;
+    size_t lds_per_block = 0;
+};
+pdz_status device_ctx(DeviceCtx** out);
+
+// Host helpers.
+void binomial_table(std::vector<uint32_t>& C);   // Pascal's rule, 33 x 33
+uint64_t binom(int n, int k);
+
+// Kernel launchers (defined in the .hip files).
+pdz_status launch_rank(const uint32_t* d_binom, int N, int n, const uint32_t* bits, uint64_t count,
+                       uint32_t* ranks, uint32_t* err, hipStream_t s);
+pdz_status launch_unrank(const uint32_t* d_binom, int N, int n, const uint32_t* ranks, uint64_t count,
+                         uint32_t* bits, uint32_t* err, hipStream_t s);
+pdz_status build_sector_tables(const uint32_t* d_binom, int N, int n, const BondDev* d_bonds, int nb,
+                               SectorTables* st, uint32_t* err, hipStream_t s);
+pdz_status hv_prepare();   // per-device kernel attributes, called once outside any capture
+pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
+                     const int* skip = nullptr);
+
+}  // namespace pdz

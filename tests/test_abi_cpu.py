@@ -1,0 +1,84 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+entry point, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1707_03974_amd as pdz
+from paper_1707_03974_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pdz.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdz_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_expected_calls():
+    names = _declared()
+    for n in ["pdz_problem_create", "pdz_problem_destroy", "pdz_problem_info", "pdz_rank", "pdz_unrank",
+              "pdz_hv", "pdz_lanczos", "pdz_lanczos_workspace_size", "pdz_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(_declared()) <= set(_lib.exported_symbols()) | {"pdz_version"}
+
+
+def test_version():
+    assert _lib.load().pdz_version() == 100
+
+
+def _create(n_sites, bonds, U, n_up, n_dn):
+    lib = _lib.load()
+    arr = (_lib.Bond * max(1, len(bonds)))(*[_lib.Bond(i, j, t) for i, j, t in bonds])
+    h = ctypes.c_void_p()
+    st = lib.pdz_problem_create(n_sites, arr if bonds else None, len(bonds), U, n_up, n_dn, ctypes.byref(h))
+    return st, lib.pdz_last_error().decode()
+
+
+@pytest.mark.parametrize("args,code,words", [
+    ((0, [], 1.0, 0, 0), _lib.PDZ_ERANGE, "n_sites"),
+    ((33, [], 1.0, 1, 1), _lib.PDZ_ERANGE, "n_sites"),
+    ((4, [(0, 1, 1.0)], 1.0, 5, 1), _lib.PDZ_EINVAL, "n_up"),
+    ((4, [(0, 1, 1.0)], 1.0, 1, -1), _lib.PDZ_EINVAL, "n_up"),
+    ((4, [(0, 0, 1.0)], 1.0, 1, 1), _lib.PDZ_EINVAL, "itself"),
+    ((4, [(0, 4, 1.0)], 1.0, 1, 1), _lib.PDZ_EINVAL, "outside"),
+    ((4, [(-1, 2, 1.0)], 1.0, 1, 1), _lib.PDZ_EINVAL, "outside"),
+    ((4, [(0, 1, float("nan"))], 1.0, 1, 1), _lib.PDZ_EINVAL, "non-finite"),
+    ((4, [(0, 1, 1.0)], float("inf"), 1, 1), _lib.PDZ_EINVAL, "U"),
+])
+def test_problem_create_rejects_invalid_input(args, code, words):
+    st, msg = _create(*args)
+    assert st == code
+    assert words in msg
+
+
+def test_null_arguments_are_rejected():
+    lib = _lib.load()
+    assert lib.pdz_problem_info(None, None) == _lib.PDZ_EINVAL
+    assert lib.pdz_hv(None, 0, None, None, None) == _lib.PDZ_EINVAL
+    assert lib.pdz_problem_destroy(None) == _lib.PDZ_OK
+    assert lib.pdz_rank(0, 0, None, 0, None, None) == _lib.PDZ_ERANGE
+    assert lib.pdz_unrank(8, 9, None, 0, None, None) == _lib.PDZ_EINVAL
+    assert lib.pdz_rank(8, 2, None, 5, None, None) == _lib.PDZ_EINVAL
+    n = ctypes.c_size_t()
+    assert lib.pdz_lanczos_workspace_size(None, None, ctypes.byref(n)) == _lib.PDZ_EINVAL
+
+
+def test_lanczos_default_options_and_validation():
+    lib = _lib.load()
+    o = _lib.LanczosOpts()
+    assert lib.pdz_lanczos_default_opts(ctypes.byref(o)) == 0
+    assert (o.max_iter, o.tol, o.storage, o.reorth, o.seed, o.check_every, o.use_graph, o.refine) == \
+        (300, 1e-12, 0, 0, 1, 10, 1, 0)
+    res = _lib.LanczosResult()
+    # a NULL problem is rejected before the options or any device work
+    assert lib.pdz_lanczos(None, ctypes.byref(o), None, None, 0, None, ctypes.byref(res), None) == _lib.PDZ_EINVAL

@@ -115,6 +115,13 @@ def test_index_equals_count_of_smaller_states(N):
         assert list(idx) == brute
 
 
+@pytest.mark.parametrize("N", [4, 7, 10])
+def test_count_below_matches_brute_force(N):
+    for n in range(N + 1):
+        for x in range(1 << N):
+            assert oracle.count_below(x, n) == sum(1 for y in range(x) if bin(y).count("1") == n)
+
+
 # ---------------------------------------------------------------- Jordan-Wigner
 
 def _jw_ops(n_modes):

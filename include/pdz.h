@@ -165,13 +165,21 @@ pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, 
  * v0: device array of D elements in `storage` precision, or NULL for the
  *     seeded start vector; it is normalised internally (not modified).
  * ws: caller-owned device workspace of at least pdz_lanczos_workspace_size
- *     bytes.  ritz_out: NULL, or a device array of D doubles that receives the
- *     normalised Ritz vector (forces refine).  Synchronous.
+ *     bytes, 256-byte aligned.  ritz_out: NULL, or a device array of D doubles
+ *     that receives the normalised Ritz vector; it forces refine, so size the
+ *     workspace with refine = 1.  Synchronous.
  * Errors: PDZ_EINVAL (bad options, null handle/result, ws too small, zero or
  * non-finite start vector); PDZ_ENOCONV when max_iter is reached (res holds
  * the best estimate). */
 pdz_status pdz_lanczos(pdz_problem p, const pdz_lanczos_opts* o, const void* v0, void* ws, size_t ws_bytes,
                        double* ritz_out, pdz_lanczos_result* res, void* stream);
+
+/* Copy the Ritz values theta_1..theta_n of the last pdz_lanczos run that
+ * used this workspace with these options (n = min(max_n, steps taken)) into
+ * host memory; *n_out receives n.  Synchronous.  Errors: PDZ_EINVAL (NULL
+ * argument, ws too small). */
+pdz_status pdz_lanczos_history(pdz_problem p, const pdz_lanczos_opts* o, const void* ws, size_t ws_bytes,
+                               int32_t max_n, double* theta_host, int32_t* n_out);
 
 /* ------------------------------------------------------------------ misc */
 

@@ -107,13 +107,15 @@ class Problem:
         _lib.check(lib().pdz_lanczos_workspace_size(self._h, ctypes.byref(opts), ctypes.byref(n)))
         return n.value
 
-    def lanczos(self, v0=None, ritz=None, workspace=None, stream=None, allow_noconv=True, **kw):
+    def lanczos(self, v0=None, ritz=None, workspace=None, stream=None, allow_noconv=True, history=False, **kw):
         """Lowest eigenvalue by the device-resident Lanczos of libpdz.
 
         Returns a dict with E0, resid_est, E0_refined, resid_refined, seconds,
         iters, converged, status.
         """
         import torch
+        if ritz is not None:
+            kw["refine"] = 1
         o = self.lanczos_opts(**kw)
         nbytes = self.workspace_size(o)
         if workspace is None:
@@ -127,6 +129,12 @@ class Problem:
         _lib.check(st, allow=(_lib.PDZ_ENOCONV,) if allow_noconv else ())
         out = {f: getattr(res, f) for f, _ in LanczosResult._fields_}
         out["status"] = st
+        if history:
+            buf = (ctypes.c_double * max(1, o.max_iter))()
+            n = ctypes.c_int32()
+            _lib.check(lib().pdz_lanczos_history(self._h, ctypes.byref(o), ctypes.c_void_p(workspace.data_ptr()),
+                                                 workspace.numel(), o.max_iter, buf, ctypes.byref(n)))
+            out["thetas"] = list(buf[:n.value])
         return out
 
 

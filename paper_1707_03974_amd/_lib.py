@@ -70,6 +70,8 @@ _SIGNATURES = {
     "pdz_lanczos_workspace_size": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), ctypes.POINTER(ctypes.c_size_t)]),
     "pdz_lanczos": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, _P, ctypes.c_size_t, _P,
                                      ctypes.POINTER(LanczosResult), _P]),
+    "pdz_lanczos_history": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "pdz_last_error": (ctypes.c_char_p, []),
     "pdz_version": (ctypes.c_int32, []),
 }
@@ -89,6 +91,9 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1707_03974_amd.build` "
                           "(the HIP library is required; there is no fallback)")
+    # torch provides the device memory and streams, so its HIP runtime must be the
+    # process's runtime: load it before libpdz resolves libamdhip64.so.7.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGNATURES.items():
         fn = getattr(lib, name)

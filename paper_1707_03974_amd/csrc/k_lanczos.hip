@@ -454,6 +454,7 @@ struct Run {
     // v_1 = v0 / |v0| into dst; zero vector into zero_dst.
     pdz_status start(const void* v0, T* dst, T* zero_dst) {
         const unsigned g = grid_elems(D);
+        hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, s, err, kErrNonFinite);
         hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, ctl(), beta());
         if (v0)
             hipLaunchKernelGGL((k_copy<T, T>), dim3(g), dim3(kRedBlock), 0, s, static_cast<const T*>(v0), dst, D);
@@ -714,6 +715,26 @@ pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, 
     if (st != PDZ_OK) return st;
     pdz_lanczos_opts oo = *o;
     *bytes = make_layout(p->D, &oo).total;
+    return ok();
+}
+
+pdz_status pdz_lanczos_history(pdz_problem p, const pdz_lanczos_opts* o, const void* ws, size_t ws_bytes,
+                               int32_t max_n, double* theta_host, int32_t* n_out) {
+    if (!p || !ws || !theta_host || !n_out) return fail(PDZ_EINVAL, "NULL argument");
+    pdz_status st = check_opts(o);
+    if (st != PDZ_OK) return st;
+    pdz_lanczos_opts oo = *o;
+    if (oo.reorth) oo.use_graph = 0;
+    const Layout L = make_layout(p->D, &oo);
+    if (ws_bytes < L.total) return fail(PDZ_EINVAL, "workspace smaller than pdz_lanczos_workspace_size");
+    Ctl h;
+    PDZ_HIP(hipMemcpy(&h, static_cast<const char*>(ws) + L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    int n = h.k < max_n ? h.k : max_n;
+    if (n < 0) n = 0;
+    if (n > 0)
+        PDZ_HIP(hipMemcpy(theta_host, static_cast<const char*>(ws) + L.theta, (size_t)n * sizeof(double),
+                          hipMemcpyDeviceToHost));
+    *n_out = n;
     return ok();
 }
 

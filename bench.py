@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--check-every", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-e0", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of D floats (known bytes) to scale counter readings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -176,6 +178,13 @@ def main():
     D, nnz = g.D, g.nnz
     _log(f"workload {w.name}: D={D} nnz={nnz}")
 
+    # autotune the H.v launch plan for both precisions (libpdz times every valid plan)
+    tuned = {}
+    for dn in ("f32", "f64"):
+        best, trials = g.tune(dn, reps=3)
+        tuned[dn] = {"best": best, "trials": trials}
+        _log(f"tuned {dn}: {best} from {len(trials)} plans")
+
     # headline: FP32-storage Lanczos steps
     t32, r32 = lanczos_steps(torch, g, "f32", args.steps, args.warmup, args.check_every)
     _log(f"f32 lanczos: {args.steps} steps in {t32:.4f} s")
@@ -189,6 +198,24 @@ def main():
     bytes64 = 2.0 * D * 8
     ach32 = bytes32 / (ms32 * 1e-3) / 1e9
     ach64 = bytes64 / (ms64 * 1e-3) / 1e9
+
+    copy = None
+    if args.calibrate_copy:
+        src = torch.empty(D, dtype=torch.float32, device="cuda").uniform_(-1.0, 1.0)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        ev1.record()
+        ev1.synchronize()
+        cms = ev0.elapsed_time(ev1) / 5
+        copy = {"bytes_read": D * 4, "bytes_written": D * 4, "ms": cms, "GBs": 2 * D * 4 / (cms * 1e-3) / 1e9}
+        _log(f"copy calibration: {copy}")
+        del src, dst
 
     tte = None
     if not args.no_time_to_e0:
@@ -226,6 +253,8 @@ def main():
                  "hv_nnz_per_s": nnz / (ms64 * 1e-3)},
         "hv_nnz_per_s_f32": nnz / (ms32 * 1e-3),
         "time_to_E0_1e-8": tte,
+        "copy_calibration": copy,
+        "hv_plans": tuned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -128,6 +128,40 @@ pdz_status pdz_device_errors(uint32_t* word);
  * Errors: PDZ_EINVAL (null handle/pointer, overlapping x and y, bad dtype). */
 pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* stream);
 
+/* ------------------------------------------------------ H.v launch plans */
+
+/* Launch geometry of pdz_hv for one precision.  0 in a field = automatic.
+ * down: 1 one row per work group with the column's hop table loaded up front,
+ *       2 one row with the table read in a loop, 3 two rows per work group;
+ * up_cw: column-chunk width of the up-hop pass (F32: 16, 32, 64;
+ *       F64: 8, 16, 32).  Every plan computes the same y bit for bit. */
+typedef struct {
+    int32_t down;
+    int32_t up_cw;
+} pdz_hv_plan;
+
+typedef struct {
+    pdz_hv_plan plan;
+    double ms;           /* average duration of one pdz_hv with this plan */
+} pdz_hv_trial;
+
+/* Plan pdz_hv uses for precision dt (automatic fields resolved). */
+pdz_status pdz_hv_get_plan(pdz_problem p, pdz_dtype dt, pdz_hv_plan* out);
+
+/* Select a plan for precision dt.  The plan is the only mutable state of a
+ * handle: do not call this while another thread launches pdz_hv on p.
+ * Errors: PDZ_EINVAL for a plan this problem cannot run. */
+pdz_status pdz_hv_set_plan(pdz_problem p, pdz_dtype dt, const pdz_hv_plan* plan);
+
+/* Autotuner: time every valid plan for precision dt on the caller's device
+ * buffers x, y (D elements each, not overlapping; x is read, y overwritten),
+ * `reps` launches each after one warm-up launch, HIP events on `stream`;
+ * select the fastest with pdz_hv_set_plan and return it in *best.  trials
+ * (may be NULL) receives up to max_trials timings, *n_trials their count.
+ * Synchronous. */
+pdz_status pdz_hv_tune(pdz_problem p, pdz_dtype dt, const void* x, void* y, int32_t reps, pdz_hv_trial* trials,
+                       int32_t max_trials, int32_t* n_trials, pdz_hv_plan* best, void* stream);
+
 /* ---------------------------------------------------------------- Lanczos */
 
 typedef struct {

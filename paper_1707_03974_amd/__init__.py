@@ -93,6 +93,33 @@ class Problem:
                                 ctypes.c_void_p(y.data_ptr()), _stream_handle(stream)))
         return y
 
+    def get_plan(self, dtype):
+        pl = _lib.HvPlan()
+        _lib.check(lib().pdz_hv_get_plan(self._h, _dtype_code(dtype), ctypes.byref(pl)))
+        return {"down": pl.down, "up_cw": pl.up_cw}
+
+    def set_plan(self, dtype, down=0, up_cw=0):
+        pl = _lib.HvPlan(int(down), int(up_cw))
+        _lib.check(lib().pdz_hv_set_plan(self._h, _dtype_code(dtype), ctypes.byref(pl)))
+
+    def tune(self, dtype, reps=5, x=None, y=None, stream=None):
+        """Autotune the H.v plan for `dtype` (libpdz times every valid plan); returns (best, trials)."""
+        import torch
+        tdt = torch.float64 if _dtype_code(dtype) == PDZ_F64 else torch.float32
+        if x is None:
+            x = torch.empty(self.D, dtype=tdt, device="cuda").uniform_(-1.0, 1.0)
+        if y is None:
+            y = torch.empty_like(x)
+        trials = (_lib.HvTrial * 32)()
+        n = ctypes.c_int32()
+        best = _lib.HvPlan()
+        _lib.check(lib().pdz_hv_tune(self._h, _dtype_code(dtype), ctypes.c_void_p(x.data_ptr()),
+                                     ctypes.c_void_p(y.data_ptr()), int(reps), trials, 32, ctypes.byref(n),
+                                     ctypes.byref(best), _stream_handle(stream)))
+        out = [{"down": trials[k].plan.down, "up_cw": trials[k].plan.up_cw, "ms": trials[k].ms}
+               for k in range(n.value)]
+        return {"down": best.down, "up_cw": best.up_cw}, out
+
     def lanczos_opts(self, **kw):
         o = LanczosOpts()
         _lib.check(lib().pdz_lanczos_default_opts(ctypes.byref(o)))

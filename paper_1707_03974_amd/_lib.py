@@ -56,6 +56,14 @@ class LanczosResult(ctypes.Structure):
                 ("converged", ctypes.c_int32)]
 
 
+class HvPlan(ctypes.Structure):
+    _fields_ = [("down", ctypes.c_int32), ("up_cw", ctypes.c_int32)]
+
+
+class HvTrial(ctypes.Structure):
+    _fields_ = [("plan", HvPlan), ("ms", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "pdz_problem_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(Bond), ctypes.c_int32, ctypes.c_double,
@@ -66,6 +74,10 @@ _SIGNATURES = {
     "pdz_unrank": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]),
     "pdz_device_errors": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_uint32)]),
     "pdz_hv": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, _P]),
+    "pdz_hv_get_plan": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(HvPlan)]),
+    "pdz_hv_set_plan": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(HvPlan)]),
+    "pdz_hv_tune": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(HvTrial),
+                                     ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(HvPlan), _P]),
     "pdz_lanczos_default_opts": (ctypes.c_int32, [ctypes.POINTER(LanczosOpts)]),
     "pdz_lanczos_workspace_size": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), ctypes.POINTER(ctypes.c_size_t)]),
     "pdz_lanczos": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, _P, ctypes.c_size_t, _P,

@@ -142,6 +142,24 @@ __global__ __launch_bounds__(kHashBlock) void k_sector_fill(const uint32_t* __re
     if (bad) atomicOr(err, kErrTable);
 }
 
+// 16-bit table in slot-pair layout: slots 2k and 2k+1 of state s share one
+// 32-bit word, out[(k * D + s) * 2 + (h & 1)], so a column loads two slots
+// per access.  Slots past the state's count are zero.
+__global__ __launch_bounds__(kHashBlock) void k_compact(const uint32_t* __restrict__ ell, const uint8_t* __restrict__ cnt,
+                                                        uint64_t D, int slots, int tbits, uint16_t* __restrict__ out) {
+    const uint64_t n = (uint64_t)slots * D;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t h = (uint32_t)(k / D);
+        const uint64_t st = k - (uint64_t)h * D;
+        uint16_t v = 0;
+        if (h < cnt[st]) {
+            const uint32_t e = ell[k];
+            v = (uint16_t)((e & kTargetMask) | ((e >> kTargetBits) << tbits));
+        }
+        out[(((uint64_t)(h >> 1) * D + st) << 1) + (h & 1u)] = v;
+    }
+}
+
 int grid_for(uint64_t n, int block) {
     uint64_t g = (n + block - 1) / block;
     if (g > 65536) g = 65536;
@@ -150,6 +168,27 @@ int grid_for(uint64_t n, int block) {
 }
 
 }  // namespace
+
+// 16-bit form of a sector's hop table: target in the low tbits bits, amplitude
+// index above, when both fit.
+pdz_status build_compact_table(SectorTables* st, int ncoef, hipStream_t s) {
+    int cbits = 0;
+    while ((1 << cbits) < ncoef) ++cbits;
+    const int tbits = 16 - cbits;
+    if (cbits > 15 || st->D > (1ull << tbits) || st->max_hops == 0) {
+        st->tbits16 = 0;
+        return ok();
+    }
+    const int slots = (st->max_hops + 1) & ~1;   // even: whole slot pairs
+    const uint64_t n = (uint64_t)slots * st->D;
+    PDZ_HIP(hipMalloc(&st->ell16, n * sizeof(uint16_t)));
+    PDZ_HIP(hipMemsetAsync(st->ell16, 0, n * sizeof(uint16_t), s));
+    hipLaunchKernelGGL(k_compact, dim3(grid_for((uint64_t)st->max_hops * st->D, kHashBlock)), dim3(kHashBlock), 0, s,
+                       st->ell, st->count, st->D, st->max_hops, tbits, st->ell16);
+    PDZ_HIP(hipGetLastError());
+    st->tbits16 = tbits;
+    return ok();
+}
 
 pdz_status launch_rank(const uint32_t* d_binom, int N, int n, const uint32_t* bits, uint64_t count,
                        uint32_t* ranks, uint32_t* err, hipStream_t s) {

@@ -3,36 +3,207 @@
 // Vector layout: X[i_up][i_dn], index i_up * D_dn + i_dn (composite index of
 // Sec. III).  With this layout
 //     y[u,d] = U popc(phi_up(u) & phi_dn(d)) x[u,d]
-//            + sum_{up hops u->u'} a(u,u') x[u',d]      (rows of X, coalesced)
 //            + sum_{dn hops d->d'} a(d,d') x[u,d']      (gathers inside row u)
+//            + sum_{up hops u->u'} a(u,u') x[u',d]      (rows of X, coalesced)
 // where a = -t_b * sign.  Each hop target index comes from the forward map
-// (perfect hash) evaluated once per sector state when the problem is created
-// (hop tables, k_hash.hip) or, on the fallback path, per element here.
+// (perfect hash), evaluated once per sector state when the problem is created
+// (hop tables, k_hash.hip), or per element on the fallback path below.
 //
-// Each output element is summed by one thread in a fixed order (diagonal,
+// Two passes with opposite locality:
+//  1. down pass (k_hv_down_*): rows of x are staged in LDS and each thread
+//     gathers the down-hop targets of its column from LDS; writes
+//     diag + down term to y.
+//  2. up pass (k_hv_up): a column chunk of x stays L2-resident while the work
+//     groups of one XCD stream every row's up hops over it as coalesced row
+//     segments; adds the up term to y in place.
+// Every output element is summed by one thread in a fixed order (diagonal,
 // down hops in bond order, up hops in bond order): no atomics, bitwise
-// reproducible.
+// reproducible, and the same order as the fallback path.
 #include "pdz_internal.h"
 
 namespace pdz {
 
 namespace {
 
-constexpr int kHvBlock = 256;
+constexpr int kWideBlock = 1024;   // down pass, long rows
+constexpr int kNarrowBlock = 256;  // down pass, short rows
+constexpr int kUpBlock = 256;      // up pass
+constexpr int kFlyBlock = 256;
+constexpr size_t kLdsBytes = 160 * 1024;
 
-// Table path: a group of R consecutive rows of x is staged in LDS; every
-// thread walks the elements of the group.
-template <typename T, bool STAGE>
-__global__ __launch_bounds__(kHvBlock) void k_hv_table(const HvArgs<T> a, const T* __restrict__ x,
-                                                       T* __restrict__ y) {
+template <typename T, typename E>
+struct DownArgs {
+    uint64_t D_up, D_dn;
+    T U;
+    const uint32_t* up_states;
+    const uint32_t* dn_states;
+    const uint8_t* dn_count;
+    const E* dn_ell;
+    uint32_t tmask;   // target mask of an entry
+    int cshift;       // amplitude index = entry >> cshift
+    const T* coef;
+    int ncoef;
+    int rows;         // rows staged per group
+    const int* skip;
+};
+
+template <typename T, typename E>
+struct UpArgs {
+    uint64_t D_up, D_dn;
+    const uint8_t* up_count;
+    const E* up_ell;
+    uint32_t tmask;
+    int cshift;
+    const T* coef;
+    int ncoef;
+    uint32_t n_chunks;    // column chunks of width CW
+    uint32_t row_tiles;   // row tiles of ROWS_PER_TILE rows
+    int max_hops;         // hop slots per row in the table
+    const int* skip;
+};
+
+// Hop slot h of sector state s: 32-bit tables are slot major, 16-bit tables
+// keep slot pairs together (k_hash.hip).
+template <typename E>
+__device__ __forceinline__ uint32_t hop_entry(const E* ell, uint32_t h, uint64_t s, uint64_t D) {
+    if (sizeof(E) == 2) return ell[(((uint64_t)(h >> 1) * D + s) << 1) + (h & 1u)];
+    return ell[(uint64_t)h * D + s];
+}
+
+template <typename T>
+__device__ __forceinline__ void load_coef(T* sc, const T* __restrict__ g, int n) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) sc[k] = g[k];
+}
+
+// ---------------------------------------------------------------- down pass
+
+// Long rows: R (1 or 2) consecutive rows staged interleaved as
+// lds[d * R + r]; each thread owns columns d and accumulates R outputs, so one
+// table entry and one LDS gather serve R rows.  The rows of the next group are
+// loaded into registers (up to PER per thread) while the current group computes.
+template <typename T, typename E, int R, int MAXH>
+__global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E> a, const T* __restrict__ x,
+                                                             T* __restrict__ y) {
     if (a.skip && *a.skip) return;
     extern __shared__ __align__(16) unsigned char smem[];
     T* coef = reinterpret_cast<T*>(smem);
     T* rows = coef + kMaxCoef;
-    for (int k = threadIdx.x; k < a.ncoef; k += blockDim.x) coef[k] = a.coef[k];
-
+    load_coef(coef, a.coef, a.ncoef);
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
-    const int R = a.rows_per_group;
+    const uint32_t Dn = (uint32_t)D_dn;
+    const uint64_t ngroups = (D_up + R - 1) / R;
+    constexpr int PER = R == 2 ? (sizeof(T) == 8 ? 8 : 12) : (sizeof(T) == 8 ? 16 : 24);
+    T pre[PER];
+    auto fetch = [&](uint64_t g) {
+        const uint64_t u0 = g * R;
+        const uint64_t nelem = ((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * D_dn;
+        const T* base = x + u0 * D_dn;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint64_t k = threadIdx.x + (uint64_t)i * kWideBlock;
+            pre[i] = (k < nelem) ? base[k] : (T)0;
+        }
+    };
+    if (blockIdx.x < ngroups) fetch(blockIdx.x);
+    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const uint64_t u0 = g * R;
+        const int nr = (int)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t k = threadIdx.x + (uint32_t)i * kWideBlock;
+            if (k < (uint32_t)R * Dn) {
+                const uint32_t r = (R == 2 && k >= Dn) ? 1u : 0u;
+                rows[(size_t)(k - r * Dn) * R + r] = pre[i];
+            }
+        }
+        {   // elements beyond the register prefetch, loaded now
+            const uint64_t nelem = (uint64_t)nr * D_dn;
+            const T* base = x + u0 * D_dn;
+            for (uint32_t k = threadIdx.x + (uint32_t)PER * kWideBlock; k < (uint32_t)R * Dn; k += kWideBlock) {
+                const uint32_t r = (R == 2 && k >= Dn) ? 1u : 0u;
+                rows[(size_t)(k - r * Dn) * R + r] = (k < nelem) ? base[k] : (T)0;
+            }
+        }
+        __syncthreads();
+        if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
+        uint32_t pu[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) pu[r] = a.up_states[u0 + (r < nr ? r : 0)];
+        for (uint32_t d = threadIdx.x; d < Dn; d += kWideBlock) {
+            const uint32_t pd = a.dn_states[d];
+            T acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = a.U * (T)__builtin_popcount(pu[r] & pd) * rows[(size_t)d * R + r];
+            const int cnt = a.dn_count[d];
+            if (MAXH > 0) {
+                // issue every table load of the column before the first use:
+                // one L2 round trip per column instead of one per few hops
+                // (16-bit tables only: two slots per 32-bit word)
+                const uint32_t* w32 = reinterpret_cast<const uint32_t*>(a.dn_ell);
+                uint32_t w[MAXH > 0 ? MAXH / 2 : 1];
+#pragma unroll
+                for (int k = 0; k < MAXH / 2; ++k) w[k] = (2 * k < cnt) ? w32[(uint32_t)k * Dn + d] : 0u;
+#pragma unroll
+                for (int h = 0; h < MAXH; ++h) {
+                    if (h < cnt) {
+                        const uint32_t e = (h & 1) ? (w[h >> 1] >> 16) : (w[h >> 1] & 0xFFFFu);
+                        const T c = coef[e >> a.cshift];
+                        const T* sv = rows + (e & a.tmask) * R;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[r] += c * sv[r];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (r < nr) y[(u0 + r) * D_dn + d] = acc[r];
+                continue;
+            }
+            int h = 0;
+            for (; h + 4 <= cnt; h += 4) {
+                const uint32_t e0 = hop_entry(a.dn_ell, h + 0, d, D_dn), e1 = hop_entry(a.dn_ell, h + 1, d, D_dn);
+                const uint32_t e2 = hop_entry(a.dn_ell, h + 2, d, D_dn), e3 = hop_entry(a.dn_ell, h + 3, d, D_dn);
+                const T c0 = coef[e0 >> a.cshift], c1 = coef[e1 >> a.cshift];
+                const T c2 = coef[e2 >> a.cshift], c3 = coef[e3 >> a.cshift];
+                const T* s0 = rows + (size_t)(e0 & a.tmask) * R;
+                const T* s1 = rows + (size_t)(e1 & a.tmask) * R;
+                const T* s2 = rows + (size_t)(e2 & a.tmask) * R;
+                const T* s3 = rows + (size_t)(e3 & a.tmask) * R;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    acc[r] += c0 * s0[r];
+                    acc[r] += c1 * s1[r];
+                    acc[r] += c2 * s2[r];
+                    acc[r] += c3 * s3[r];
+                }
+            }
+            for (; h < cnt; ++h) {
+                const uint32_t e = hop_entry(a.dn_ell, h, d, D_dn);
+                const T c = coef[e >> a.cshift];
+                const T* sv = rows + (size_t)(e & a.tmask) * R;
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += c * sv[r];
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < nr) y[(u0 + r) * D_dn + d] = acc[r];
+        }
+    }
+}
+
+// Short rows: `rows` consecutive rows staged row-major; threads walk the
+// flattened (row, column) index of the group.  STAGE = false gathers from
+// global memory instead (rows too long for LDS).
+template <typename T, typename E, bool STAGE>
+__global__ __launch_bounds__(kNarrowBlock) void k_hv_down_narrow(const DownArgs<T, E> a, const T* __restrict__ x,
+                                                                 T* __restrict__ y) {
+    if (a.skip && *a.skip) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* coef = reinterpret_cast<T*>(smem);
+    T* rows = coef + kMaxCoef;
+    load_coef(coef, a.coef, a.ncoef);
+    const uint64_t D_up = a.D_up, D_dn = a.D_dn;
+    const int R = a.rows;
     const uint64_t ngroups = (D_up + R - 1) / R;
     for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const uint64_t u0 = g * (uint64_t)R;
@@ -40,35 +211,121 @@ __global__ __launch_bounds__(kHvBlock) void k_hv_table(const HvArgs<T> a, const 
         const uint64_t nelem = (uint64_t)nr * D_dn;
         const T* xg = x + u0 * D_dn;
         __syncthreads();
-        if (STAGE) {
+        if (STAGE)
             for (uint64_t k = threadIdx.x; k < nelem; k += blockDim.x) rows[k] = xg[k];
-        }
         __syncthreads();
         for (uint64_t k = threadIdx.x; k < nelem; k += blockDim.x) {
             const uint32_t r = (uint32_t)(k / D_dn);
             const uint32_t d = (uint32_t)(k - (uint64_t)r * D_dn);
-            const uint64_t u = u0 + r;
             const T* xrow = STAGE ? rows + (uint64_t)r * D_dn : xg + (uint64_t)r * D_dn;
-            const uint32_t pu = a.up_states[u];
+            const uint32_t pu = a.up_states[u0 + r];
             const uint32_t pd = a.dn_states[d];
             T acc = a.U * (T)__builtin_popcount(pu & pd) * xrow[d];
-            const int cd = a.dn_count[d];
-            for (int h = 0; h < cd; ++h) {
-                const uint32_t e = a.dn_ell[(uint64_t)h * D_dn + d];
-                acc += coef[e >> kTargetBits] * xrow[e & kTargetMask];
+            const int cnt = a.dn_count[d];
+            for (int h = 0; h < cnt; ++h) {
+                const uint32_t e = hop_entry(a.dn_ell, h, d, D_dn);
+                acc += coef[e >> a.cshift] * xrow[e & a.tmask];
             }
-            const int cu = a.up_count[u];
-            for (int h = 0; h < cu; ++h) {
-                const uint32_t e = a.up_ell[(uint64_t)h * D_up + u];
-                acc += coef[e >> kTargetBits] * x[(uint64_t)(e & kTargetMask) * D_dn + d];
-            }
-            y[u * D_dn + d] = acc;
+            y[(u0 + r) * D_dn + d] = acc;
         }
     }
 }
 
-// Fallback path: every sector rank and every hop target is computed per
-// element with the forward and backward maps (binomial table in LDS).
+// ------------------------------------------------------------------ up pass
+
+// One decoded up hop: element offset of the source row and its amplitude.
+template <typename T>
+struct UpHop;
+template <>
+struct __align__(8) UpHop<float> {
+    uint32_t off;
+    float c;
+};
+template <>
+struct __align__(16) UpHop<double> {
+    uint32_t off;
+    uint32_t pad;
+    double c;
+};
+
+// Tile = ROWS_PER_TILE rows x CW columns; a wave covers 64 / CW rows at once.
+// Work groups are dealt to the XCDs round robin (block b runs on XCD b % 8);
+// the tile order below gives each XCD a pair of neighbouring column chunks in
+// turn, so the slab x[:, chunk] that all up hops of the chunk read stays in
+// that XCD's L2, and both halves of every 128-byte line are used there.
+// The tile's hop lists are decoded once into LDS.  IDX64 selects 64-bit
+// element offsets (D >= 2^32).
+template <typename T, typename E, int CW, int ROWS_PER_TILE, bool IDX64>
+__global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const T* __restrict__ x, T* __restrict__ y) {
+    if (a.skip && *a.skip) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int maxh = a.max_hops;
+    UpHop<T>* s_hop = reinterpret_cast<UpHop<T>*>(smem);                    // ROWS * maxh
+    uint64_t* s_off64 = reinterpret_cast<uint64_t*>(s_hop + ROWS_PER_TILE * maxh);  // ROWS * maxh if IDX64
+    int* s_cnt = reinterpret_cast<int*>(s_off64 + (IDX64 ? ROWS_PER_TILE * maxh : 0));
+    constexpr int kXcd = 8;
+    const uint32_t b = blockIdx.x;
+    const uint32_t xcd = b % kXcd;
+    const uint32_t j = b / kXcd;
+    const uint32_t rt = a.row_tiles;
+    const uint32_t pair = j / (2 * rt);
+    const uint32_t half = (j / rt) & 1u;
+    const uint32_t tile = j % rt;
+    const uint32_t chunk = 2 * (xcd + kXcd * pair) + half;
+    if (chunk >= a.n_chunks) return;
+    const uint64_t D_up = a.D_up, D_dn = a.D_dn;
+    const uint64_t u_begin = (uint64_t)tile * ROWS_PER_TILE;
+    const int nrows = (int)((D_up - u_begin) < (uint64_t)ROWS_PER_TILE ? (D_up - u_begin) : (uint64_t)ROWS_PER_TILE);
+    for (int r = threadIdx.x; r < nrows; r += kUpBlock) s_cnt[r] = a.up_count[u_begin + r];
+    for (int k = threadIdx.x; k < nrows * maxh; k += kUpBlock) {
+        const int r = k / maxh, h = k - r * maxh;
+        const uint32_t e = hop_entry(a.up_ell, h, u_begin + r, D_up);   // slots past the count are never read
+        const uint32_t ci = e >> a.cshift;
+        s_hop[k].c = a.coef[ci < (uint32_t)a.ncoef ? ci : 0];
+        if (IDX64)
+            s_off64[k] = (uint64_t)(e & a.tmask) * D_dn;
+        else
+            s_hop[k].off = (e & a.tmask) * (uint32_t)D_dn;
+    }
+    __syncthreads();
+    const uint32_t col = threadIdx.x % CW;
+    const uint64_t d = (uint64_t)chunk * CW + col;
+    if (d >= D_dn) return;
+    constexpr int kSlots = kUpBlock / CW;
+    for (int r = threadIdx.x / CW; r < nrows; r += kSlots) {
+        const uint64_t u = u_begin + r;
+        const int cnt = s_cnt[r];
+        const UpHop<T>* hp = s_hop + r * maxh;
+        const uint64_t* o64 = s_off64 + r * maxh;
+        T acc = y[u * D_dn + d];
+        int h = 0;
+        for (; h + 8 <= cnt; h += 8) {
+            T v[8];
+            T c[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const UpHop<T> hq = hp[h + q];
+                c[q] = hq.c;
+                if (IDX64)
+                    v[q] = x[o64[h + q] + d];
+                else
+                    v[q] = x[hq.off + (uint32_t)d];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += c[q] * v[q];
+        }
+        for (; h < cnt; ++h) {
+            const UpHop<T> hq = hp[h];
+            acc += hq.c * (IDX64 ? x[o64[h] + d] : x[hq.off + (uint32_t)d]);
+        }
+        y[u * D_dn + d] = acc;
+    }
+}
+
+// ------------------------------------------------------------ fallback path
+
+// Every sector rank and every hop target computed per element with the
+// forward and backward maps (binomial table in LDS).
 struct FlyArgs {
     int N, n_up, n_dn, nb;
     uint64_t D_up, D_dn;
@@ -104,7 +361,7 @@ __device__ __forceinline__ uint32_t fly_unrank(uint32_t p, int n, int N, const u
 }
 
 template <typename T>
-__global__ __launch_bounds__(kHvBlock) void k_hv_fly(const FlyArgs f, T U, const T* __restrict__ coef_g,
+__global__ __launch_bounds__(kFlyBlock) void k_hv_fly(const FlyArgs f, T U, const T* __restrict__ coef_g,
                                                      const T* __restrict__ x, T* __restrict__ y) {
     if (f.skip && *f.skip) return;
     __shared__ uint32_t sC[kBinomStride * kBinomStride];
@@ -137,50 +394,198 @@ __global__ __launch_bounds__(kHvBlock) void k_hv_fly(const FlyArgs f, T U, const
     }
 }
 
+// ---------------------------------------------------------------- launches
+
+template <typename T, typename E>
+void fill_table_view(const SectorTables& t, bool compact, const E** ell, uint32_t* tmask, int* cshift) {
+    if (compact) {
+        *ell = reinterpret_cast<const E*>(t.ell16);
+        *tmask = (1u << t.tbits16) - 1u;
+        *cshift = t.tbits16;
+    } else {
+        *ell = reinterpret_cast<const E*>(t.ell);
+        *tmask = kTargetMask;
+        *cshift = (int)kTargetBits;
+    }
+}
+
+// Down-pass variant: 1 = one row, table loaded up front (compile-time bound
+// on the hop slots); 2 = one row, table in a loop; 3 = two rows, loop.
+template <typename T, typename E>
+void launch_wide(int variant, int max_hops, uint64_t grid, size_t lds, hipStream_t s, const DownArgs<T, E>& da,
+                 const T* x, T* y) {
+    const dim3 g((unsigned)grid), b(kWideBlock);
+    if (variant == 1 && sizeof(E) == 2 && max_hops <= 16)
+        hipLaunchKernelGGL((k_hv_down_wide<T, E, 1, 16>), g, b, lds, s, da, x, y);
+    else if (variant == 1 && sizeof(E) == 2 && max_hops <= 32)
+        hipLaunchKernelGGL((k_hv_down_wide<T, E, 1, 32>), g, b, lds, s, da, x, y);
+    else if (variant == 1 && sizeof(E) == 2 && max_hops <= 48)
+        hipLaunchKernelGGL((k_hv_down_wide<T, E, 1, 48>), g, b, lds, s, da, x, y);
+    else if (variant == 3)
+        hipLaunchKernelGGL((k_hv_down_wide<T, E, 2, 0>), g, b, lds, s, da, x, y);
+    else
+        hipLaunchKernelGGL((k_hv_down_wide<T, E, 1, 0>), g, b, lds, s, da, x, y);
+}
+
+template <typename T, typename E, int R, int MAXH>
+pdz_status set_wide_lds() {
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_wide<T, E, R, MAXH>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+    return ok();
+}
+
+// Up-pass geometry: the x[:, chunk] slab one XCD streams over is
+// D_up * CW * sizeof(T) bytes; narrower chunks stay in L2, wider ones issue
+// fewer, longer requests.  The plan (autotuned or default) picks CW.
+template <typename T>
+constexpr int up_rows() { return sizeof(T) == 8 ? 32 : 64; }
+
+template <typename T, typename E, int CW>
+void launch_up(bool idx64, uint64_t blocks, size_t lds, hipStream_t s, const UpArgs<T, E>& ua, const T* x, T* y) {
+    if (idx64)
+        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), true>), dim3((unsigned)blocks), dim3(kUpBlock), lds, s, ua,
+                           x, y);
+    else
+        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), false>), dim3((unsigned)blocks), dim3(kUpBlock), lds, s,
+                           ua, x, y);
+}
+
+// Chunk widths offered per precision (columns).
+constexpr int kUpCw32[] = {16, 32, 64};
+constexpr int kUpCw64[] = {8, 16, 32};
+
+bool row_fits(const pdz_problem_s* p, size_t es, int rows) {
+    const size_t lds_cap = kLdsBytes - kMaxCoef * es - 1024;
+    return (size_t)rows * p->dn.D * es <= lds_cap;
+}
+
+bool wide_down(const pdz_problem_s* p, size_t es) { return p->dn.D >= (uint64_t)kWideBlock && row_fits(p, es, 1); }
+
+HvPlan default_plan(const pdz_problem_s* p, pdz_dtype dt) {
+    const size_t es = dt == PDZ_F64 ? 8 : 4;
+    HvPlan d;
+    const bool compact = p->up.tbits16 > 0 && p->dn.tbits16 > 0;
+    if (dt == PDZ_F32 && row_fits(p, es, 2) && p->up.D >= 2)
+        d.down = 3;
+    else if (compact && p->dn.max_hops <= 48)
+        d.down = 1;
+    else
+        d.down = 2;
+    d.up_cw = dt == PDZ_F64 ? 16 : 32;
+    return d;
+}
+
+HvPlan hv_resolve(const pdz_problem_s* p, pdz_dtype dt) {
+    HvPlan pl = p->plan[dt == PDZ_F64 ? 0 : 1];
+    const HvPlan d = default_plan(p, dt);
+    if (pl.down == 0) pl.down = d.down;
+    if (pl.up_cw == 0) pl.up_cw = d.up_cw;
+    return pl;
+}
+
+template <typename T, typename E>
+pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coef, const T* x, T* y, hipStream_t s,
+                      const int* skip, bool compact) {
+    const uint64_t D_up = p->up.D, D_dn = p->dn.D;
+    const int ncoef = (int)p->coef_host.size();
+    // ---- down pass
+    DownArgs<T, E> da;
+    da.D_up = D_up;
+    da.D_dn = D_dn;
+    da.U = (T)p->U;
+    da.up_states = p->up.states;
+    da.dn_states = p->dn.states;
+    da.dn_count = p->dn.count;
+    fill_table_view<T, E>(p->dn, compact, &da.dn_ell, &da.tmask, &da.cshift);
+    da.coef = coef;
+    da.ncoef = ncoef;
+    da.skip = skip;
+    const size_t lds_cap = kLdsBytes - kMaxCoef * sizeof(T) - 1024;
+    const size_t row_bytes = (size_t)D_dn * sizeof(T);
+    const unsigned cu = (unsigned)ctx->cu_count;
+    const HvPlan plan = hv_resolve(p, sizeof(T) == 8 ? PDZ_F64 : PDZ_F32);
+    if (D_dn >= (uint64_t)kWideBlock && row_bytes <= lds_cap) {
+        const bool two = plan.down == 3;
+        da.rows = two ? 2 : 1;
+        const size_t lds = kMaxCoef * sizeof(T) + (size_t)da.rows * row_bytes;
+        const uint64_t ngroups = (D_up + da.rows - 1) / da.rows;
+        const unsigned per_cu = (unsigned)(kLdsBytes / (lds + 256));
+        uint64_t grid = (uint64_t)cu * (per_cu < 1 ? 1 : per_cu);
+        if (grid > ngroups) grid = ngroups;
+        launch_wide<T, E>(plan.down, p->dn.max_hops, grid, lds, s, da, x, y);
+    } else {
+        const bool stage = row_bytes <= lds_cap;
+        int R = 1;
+        if (D_dn < 2 * (uint64_t)kNarrowBlock) R = (int)((2 * kNarrowBlock + D_dn - 1) / D_dn);
+        if (stage) {
+            const int rmax = (int)(lds_cap / row_bytes);
+            if (R > rmax) R = rmax;
+        }
+        if ((uint64_t)R > D_up) R = (int)D_up;
+        if (R < 1) R = 1;
+        da.rows = R;
+        const size_t lds = kMaxCoef * sizeof(T) + (stage ? (size_t)R * row_bytes : 0);
+        const uint64_t ngroups = (D_up + R - 1) / R;
+        const unsigned per_cu = stage ? (unsigned)(kLdsBytes / (lds + 256)) : 8u;
+        uint64_t grid = (uint64_t)cu * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
+        if (grid > ngroups) grid = ngroups;
+        if (stage)
+            hipLaunchKernelGGL((k_hv_down_narrow<T, E, true>), dim3((unsigned)grid), dim3(kNarrowBlock), lds, s, da,
+                               x, y);
+        else
+            hipLaunchKernelGGL((k_hv_down_narrow<T, E, false>), dim3((unsigned)grid), dim3(kNarrowBlock), lds, s, da,
+                               x, y);
+    }
+    PDZ_HIP(hipGetLastError());
+    if (p->up.max_hops == 0) return ok();
+    // ---- up pass
+    UpArgs<T, E> ua;
+    ua.D_up = D_up;
+    ua.D_dn = D_dn;
+    ua.up_count = p->up.count;
+    fill_table_view<T, E>(p->up, compact, &ua.up_ell, &ua.tmask, &ua.cshift);
+    ua.coef = coef;
+    ua.ncoef = ncoef;
+    ua.skip = skip;
+    constexpr int ROWS = up_rows<T>();
+    const int CW = plan.up_cw;
+    constexpr int kXcd = 8;
+    const bool idx64 = p->D > 0xFFFFFFFFull;
+    ua.row_tiles = (uint32_t)((D_up + ROWS - 1) / ROWS);
+    ua.max_hops = p->up.max_hops;
+    ua.n_chunks = (uint32_t)((D_dn + CW - 1) / CW);
+    const size_t lds = (size_t)ROWS * ua.max_hops * (sizeof(UpHop<T>) + (idx64 ? 8 : 0)) + ROWS * sizeof(int);
+    const uint64_t pairs = (ua.n_chunks + 1) / 2;
+    const uint64_t pairs_per_xcd = (pairs + kXcd - 1) / kXcd;
+    const uint64_t blocks = kXcd * pairs_per_xcd * 2 * ua.row_tiles;
+    if (sizeof(T) == 8) {
+        if (CW == 8)
+            launch_up<T, E, 8>(idx64, blocks, lds, s, ua, x, y);
+        else if (CW == 16)
+            launch_up<T, E, 16>(idx64, blocks, lds, s, ua, x, y);
+        else
+            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, y);
+    } else {
+        if (CW == 16)
+            launch_up<T, E, 16>(idx64, blocks, lds, s, ua, x, y);
+        else if (CW == 32)
+            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, y);
+        else
+            launch_up<T, E, 64>(idx64, blocks, lds, s, ua, x, y);
+    }
+    PDZ_HIP(hipGetLastError());
+    return ok();
+}
+
 template <typename T>
 pdz_status run_hv(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipStream_t s, const int* skip) {
     DeviceCtx* ctx = nullptr;
     pdz_status st = device_ctx(&ctx);
     if (st != PDZ_OK) return st;
     if (p->hv_path == 0) {
-        HvArgs<T> a;
-        a.D_up = p->up.D;
-        a.D_dn = p->dn.D;
-        a.U = (T)p->U;
-        a.up_states = p->up.states;
-        a.up_count = p->up.count;
-        a.up_ell = p->up.ell;
-        a.dn_states = p->dn.states;
-        a.dn_count = p->dn.count;
-        a.dn_ell = p->dn.ell;
-        a.coef = coef;
-        a.ncoef = (int)p->coef_host.size();
-        a.skip = skip;
-        const size_t lds_cap = 160 * 1024 - kMaxCoef * sizeof(T) - 1024;
-        const size_t row_bytes = (size_t)a.D_dn * sizeof(T);
-        const bool stage = row_bytes <= lds_cap;
-        int R = 1;
-        if (a.D_dn < 2 * (uint64_t)kHvBlock) R = (int)((2 * kHvBlock + a.D_dn - 1) / a.D_dn);
-        if (stage) {
-            int rmax = (int)(lds_cap / row_bytes);
-            if (R > rmax) R = rmax;
-        }
-        if ((uint64_t)R > a.D_up) R = (int)a.D_up;
-        if (R < 1) R = 1;
-        a.rows_per_group = R;
-        const size_t lds = kMaxCoef * sizeof(T) + (stage ? (size_t)R * row_bytes : 0);
-        const uint64_t ngroups = (a.D_up + R - 1) / R;
-        const int per_cu = stage ? (int)((160 * 1024) / (lds + 512)) : 4;
-        uint64_t grid = (uint64_t)ctx->cu_count * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
-        if (grid > ngroups) grid = ngroups;
-        if (grid < 1) grid = 1;
-        if (stage) {
-            hipLaunchKernelGGL((k_hv_table<T, true>), dim3((unsigned)grid), dim3(kHvBlock), lds, s, a, x, y);
-        } else {
-            hipLaunchKernelGGL((k_hv_table<T, false>), dim3((unsigned)grid), dim3(kHvBlock), lds, s, a, x, y);
-        }
-        PDZ_HIP(hipGetLastError());
-        return ok();
+        const bool compact = p->up.tbits16 > 0 && p->dn.tbits16 > 0;
+        if (compact) return run_tables<T, uint16_t>(p, ctx, coef, x, y, s, skip, true);
+        return run_tables<T, uint32_t>(p, ctx, coef, x, y, s, skip, false);
     }
     FlyArgs f;
     f.N = p->N;
@@ -192,23 +597,83 @@ pdz_status run_hv(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipSt
     f.binom = p->d_binom;
     f.bonds = p->d_bonds;
     f.skip = skip;
-    uint64_t grid = (p->D + kHvBlock - 1) / kHvBlock;
+    uint64_t grid = (p->D + kFlyBlock - 1) / kFlyBlock;
     const uint64_t gmax = (uint64_t)ctx->cu_count * 16;
     if (grid > gmax) grid = gmax;
-    hipLaunchKernelGGL(k_hv_fly<T>, dim3((unsigned)grid), dim3(kHvBlock), 0, s, f, (T)p->U, coef, x, y);
+    hipLaunchKernelGGL(k_hv_fly<T>, dim3((unsigned)grid), dim3(kFlyBlock), 0, s, f, (T)p->U, coef, x, y);
     PDZ_HIP(hipGetLastError());
     return ok();
+}
+
+template <typename T, typename E, int CW>
+pdz_status set_up_lds() {
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+    return ok();
+}
+
+template <typename T, typename E>
+pdz_status prepare_one() {
+    const int lds = (int)kLdsBytes;
+    pdz_status st = set_wide_lds<T, E, 1, 0>();
+    if (st == PDZ_OK) st = set_wide_lds<T, E, 2, 0>();
+    if (sizeof(E) == 2) {
+        if (st == PDZ_OK) st = set_wide_lds<T, E, 1, 16>();
+        if (st == PDZ_OK) st = set_wide_lds<T, E, 1, 32>();
+        if (st == PDZ_OK) st = set_wide_lds<T, E, 1, 48>();
+    }
+    if (st != PDZ_OK) return st;
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_narrow<T, E, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 8 : 16>();
+    if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 16 : 32>();
+    if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 32 : 64>();
+    return st;
 }
 
 }  // namespace
 
 pdz_status hv_prepare() {
-    const int lds = 160 * 1024;
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_table<double, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_table<float, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    return ok();
+    pdz_status st = prepare_one<double, uint16_t>();
+    if (st == PDZ_OK) st = prepare_one<double, uint32_t>();
+    if (st == PDZ_OK) st = prepare_one<float, uint16_t>();
+    if (st == PDZ_OK) st = prepare_one<float, uint32_t>();
+    return st;
+}
+
+std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
+    std::vector<HvPlan> out;
+    const HvPlan d = default_plan(p, dt);
+    out.push_back(d);
+    if (p->hv_path != 0) return out;
+    const size_t es = dt == PDZ_F64 ? 8 : 4;
+    const bool compact = p->up.tbits16 > 0 && p->dn.tbits16 > 0;
+    std::vector<int> downs;
+    if (wide_down(p, es)) {
+        if (compact && p->dn.max_hops <= 48) downs.push_back(1);
+        downs.push_back(2);
+        if (row_fits(p, es, 2) && p->up.D >= 2) downs.push_back(3);
+    } else {
+        downs.push_back(d.down);
+    }
+    const int* cws = dt == PDZ_F64 ? kUpCw64 : kUpCw32;
+    for (int dv : downs)
+        for (int k = 0; k < 3; ++k) {
+            HvPlan c;
+            c.down = dv;
+            c.up_cw = cws[k];
+            if (c.down != d.down || c.up_cw != d.up_cw) out.push_back(c);
+        }
+    return out;
+}
+
+bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan) {
+    if (plan.down == 0 && plan.up_cw == 0) return true;
+    for (const HvPlan& c : hv_candidates(p, dt))
+        if ((plan.down == 0 || plan.down == c.down) && (plan.up_cw == 0 || plan.up_cw == c.up_cw)) return true;
+    return false;
 }
 
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,

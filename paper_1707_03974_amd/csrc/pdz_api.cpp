@@ -79,6 +79,8 @@ static void free_tables(SectorTables& t) {
     if (t.states) (void)hipFree(t.states);
     if (t.count) (void)hipFree(t.count);
     if (t.ell) (void)hipFree(t.ell);
+    if (t.ell16) (void)hipFree(t.ell16);
+    t.ell16 = nullptr;
     t.states = nullptr;
     t.count = nullptr;
     t.ell = nullptr;
@@ -153,15 +155,33 @@ pdz_status pdz_problem_create(int32_t n_sites, const pdz_bond* bonds, int32_t n_
         p->coef_host.push_back(v);
         return (int)p->coef_host.size() - 1;
     };
-    for (int b = 0; b < n_bonds; ++b) {
+    // Kernel bond order: bonds inside the upper half of the sites first, then
+    // bonds across the halves, then bonds inside the lower half (stable).
+    // States that share their upper half sit next to each other in a sector,
+    // so their first hop slots name the same bond and land at one common
+    // offset.  The sum over bonds is unchanged.
+    std::vector<int> order(n_bonds);
+    {
+        const int half = n_sites / 2;
+        auto cls = [&](int b) {
+            const int hi_i = bonds[b].i >= half, hi_j = bonds[b].j >= half;
+            return hi_i && hi_j ? 0 : (hi_i || hi_j ? 1 : 2);
+        };
+        int k = 0;
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < n_bonds; ++b)
+                if (cls(b) == c) order[k++] = b;
+    }
+    for (int k = 0; k < n_bonds; ++k) {
+        const int b = order[k];
         const int i = bonds[b].i, j = bonds[b].j;
         const int lo = i < j ? i : j, hi = i < j ? j : i;
-        bd[b].mask = (1u << i) | (1u << j);
+        bd[k].mask = (1u << i) | (1u << j);
         uint32_t between = 0;
-        for (int k = lo + 1; k < hi; ++k) between |= 1u << k;
-        bd[b].between = between;
-        bd[b].coef_pos = coef_index(-bonds[b].t);
-        bd[b].coef_neg = coef_index(bonds[b].t);
+        for (int s = lo + 1; s < hi; ++s) between |= 1u << s;
+        bd[k].between = between;
+        bd[k].coef_pos = coef_index(-bonds[b].t);
+        bd[k].coef_neg = coef_index(bonds[b].t);
     }
     if (p->coef_host.empty()) p->coef_host.push_back(0.0);
     if ((int)p->coef_host.size() > kMaxCoef) {
@@ -207,11 +227,15 @@ pdz_status pdz_problem_create(int32_t n_sites, const pdz_bond* bonds, int32_t n_
         p->hv_path = 0;
         st = build_sector_tables(p->d_binom, n_sites, n_up, p->d_bonds, n_bonds, &p->up, ctx->err, s);
         if (st != PDZ_OK) return cleanup(st);
+        st = build_compact_table(&p->up, (int)p->coef_host.size(), s);
+        if (st != PDZ_OK) return cleanup(st);
         if (n_dn == n_up) {
             p->dn = p->up;
             p->same_sector = true;
         } else {
             st = build_sector_tables(p->d_binom, n_sites, n_dn, p->d_bonds, n_bonds, &p->dn, ctx->err, s);
+            if (st != PDZ_OK) return cleanup(st);
+            st = build_compact_table(&p->dn, (int)p->coef_host.size(), s);
             if (st != PDZ_OK) return cleanup(st);
         }
         hipError_t e = hipStreamSynchronize(s);

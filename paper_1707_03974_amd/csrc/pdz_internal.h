@@ -41,25 +41,20 @@ struct SectorTables {
     uint32_t* states = nullptr; // D occupation strings (backward map of each rank)
     uint8_t* count = nullptr;   // D hop counts
     uint32_t* ell = nullptr;    // max_hops * D entries: ell[h * D + s] = target | coef << 24
+    uint16_t* ell16 = nullptr;  // target | coef << tbits16 when that fits 16 bits, slot-pair layout:
+                                // slot h of state s at ((h / 2) * D + s) * 2 + h % 2
+    int tbits16 = 0;            // target bits of a 16-bit entry (0: no 16-bit table)
 };
 
-// Kernel-side view of a problem for H.v.
-template <typename T>
-struct HvArgs {
-    uint64_t D_up, D_dn;
-    T U;
-    const uint32_t* up_states;
-    const uint8_t* up_count;
-    const uint32_t* up_ell;
-    const uint32_t* dn_states;
-    const uint8_t* dn_count;
-    const uint32_t* dn_ell;
-    const T* coef;         // signed hop amplitudes
-    int ncoef;
-    int rows_per_group;    // rows staged together in LDS
-    const int* skip;       // optional device flag: when non-zero the launch does nothing
-};
+}  // namespace pdz
 
+namespace pdz {
+// H.v launch plan for one precision (0 = automatic choice).
+struct HvPlan {
+    int down = 0;    // 1: one row per group, hop table loaded up front; 2: one row, table in a loop;
+                     // 3: two rows per group, table in a loop
+    int up_cw = 0;   // up-pass chunk width in columns
+};
 }  // namespace pdz
 
 struct pdz_problem_s {
@@ -76,6 +71,7 @@ struct pdz_problem_s {
     double* d_coef64 = nullptr;
     float* d_coef32 = nullptr;
     int hv_path = 0;                     // 0 tables, 1 on the fly
+    pdz::HvPlan plan[2];                 // per pdz_dtype
 };
 
 namespace pdz {
@@ -111,7 +107,11 @@ pdz_status launch_unrank(const uint32_t* d_binom, int N, int n, const uint32_t* 
                          uint32_t* bits, uint32_t* err, hipStream_t s);
 pdz_status build_sector_tables(const uint32_t* d_binom, int N, int n, const BondDev* d_bonds, int nb,
                                SectorTables* st, uint32_t* err, hipStream_t s);
+pdz_status build_compact_table(SectorTables* st, int ncoef, hipStream_t s);
 pdz_status hv_prepare();   // per-device kernel attributes, called once outside any capture
+// Candidate plans valid for this problem and precision; the first is the default.
+std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt);
+bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan);
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                      const int* skip = nullptr);
 

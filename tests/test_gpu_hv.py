@@ -166,3 +166,26 @@ def test_hv_full_size_sampled_rows(name, dtype_name):
     err = np.abs(y - y_ref)
     assert np.all(err <= bound), float(err.max())
     del xd, yd
+
+
+@pytest.mark.parametrize("name", ["ring8", "torus4x3", "torus4x4_n7"])
+def test_every_plan_gives_identical_results(name):
+    """All launch plans the autotuner may pick sum each element in the same order."""
+    torch = torch_cuda()
+    g = _gpu_problem(synth.workload(name))
+    for dt in (torch.float64, torch.float32):
+        x = to_dev(synth.random_vector(g.D, 5), dt)
+        ref = g.hv(x)
+        best, trials = g.tune(dt, reps=1, x=x, y=torch.empty_like(x))
+        assert len(trials) >= 1 and best in [{"down": t["down"], "up_cw": t["up_cw"]} for t in trials]
+        for t in trials:
+            g.set_plan(dt, t["down"], t["up_cw"])
+            assert g.get_plan(dt) == {"down": t["down"], "up_cw": t["up_cw"]}
+            assert torch.equal(g.hv(x), ref), (name, dt, t)
+
+
+def test_invalid_plan_is_rejected():
+    import paper_1707_03974_amd as pdz
+    g = _gpu_problem(synth.workload("torus4x3"))
+    with pytest.raises(pdz.PdzError):
+        g.set_plan("f32", 1, 7)

@@ -133,11 +133,19 @@ pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* str
 /* Launch geometry of pdz_hv for one precision.  0 in a field = automatic.
  * down: 1 one row per work group with the column's hop table loaded up front,
  *       2 one row with the table read in a loop, 3 two rows per work group;
- * up_cw: column-chunk width of the up-hop pass (F32: 16, 32, 64;
- *       F64: 8, 16, 32).  Every plan computes the same y bit for bit. */
+ * up_cw: column-chunk width of the up-hop pass (F32: 32, 64, 128, 256;
+ *       F64: 16, 32, 64, 128);
+ * up: 1 the hops of a row are loaded in batches of 8, 2 all hops of a row are
+ *       loaded before the first multiply-add (up_cw <= 64);
+ * map: order of the up-pass tiles: 1 each XCD walks a pair of neighbouring
+ *       column chunks at a time (blocks are dealt to XCDs round robin),
+ *       2 chunk-major over all blocks.
+ * Every plan computes the same y bit for bit. */
 typedef struct {
     int32_t down;
     int32_t up_cw;
+    int32_t up;
+    int32_t map;
 } pdz_hv_plan;
 
 typedef struct {

@@ -96,10 +96,10 @@ class Problem:
     def get_plan(self, dtype):
         pl = _lib.HvPlan()
         _lib.check(lib().pdz_hv_get_plan(self._h, _dtype_code(dtype), ctypes.byref(pl)))
-        return {"down": pl.down, "up_cw": pl.up_cw}
+        return {"down": pl.down, "up_cw": pl.up_cw, "up": pl.up, "map": pl.map}
 
-    def set_plan(self, dtype, down=0, up_cw=0):
-        pl = _lib.HvPlan(int(down), int(up_cw))
+    def set_plan(self, dtype, down=0, up_cw=0, up=0, map=0):
+        pl = _lib.HvPlan(int(down), int(up_cw), int(up), int(map))
         _lib.check(lib().pdz_hv_set_plan(self._h, _dtype_code(dtype), ctypes.byref(pl)))
 
     def tune(self, dtype, reps=5, x=None, y=None, stream=None):
@@ -110,15 +110,15 @@ class Problem:
             x = torch.empty(self.D, dtype=tdt, device="cuda").uniform_(-1.0, 1.0)
         if y is None:
             y = torch.empty_like(x)
-        trials = (_lib.HvTrial * 32)()
+        trials = (_lib.HvTrial * 64)()
         n = ctypes.c_int32()
         best = _lib.HvPlan()
         _lib.check(lib().pdz_hv_tune(self._h, _dtype_code(dtype), ctypes.c_void_p(x.data_ptr()),
-                                     ctypes.c_void_p(y.data_ptr()), int(reps), trials, 32, ctypes.byref(n),
+                                     ctypes.c_void_p(y.data_ptr()), int(reps), trials, 64, ctypes.byref(n),
                                      ctypes.byref(best), _stream_handle(stream)))
-        out = [{"down": trials[k].plan.down, "up_cw": trials[k].plan.up_cw, "ms": trials[k].ms}
-               for k in range(n.value)]
-        return {"down": best.down, "up_cw": best.up_cw}, out
+        out = [{"down": trials[k].plan.down, "up_cw": trials[k].plan.up_cw, "up": trials[k].plan.up,
+                "map": trials[k].plan.map, "ms": trials[k].ms} for k in range(n.value)]
+        return {"down": best.down, "up_cw": best.up_cw, "up": best.up, "map": best.map}, out
 
     def lanczos_opts(self, **kw):
         o = LanczosOpts()

@@ -57,7 +57,7 @@ class LanczosResult(ctypes.Structure):
 
 
 class HvPlan(ctypes.Structure):
-    _fields_ = [("down", ctypes.c_int32), ("up_cw", ctypes.c_int32)]
+    _fields_ = [("down", ctypes.c_int32), ("up_cw", ctypes.c_int32), ("up", ctypes.c_int32), ("map", ctypes.c_int32)]
 
 
 class HvTrial(ctypes.Structure):

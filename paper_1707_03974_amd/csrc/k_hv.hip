@@ -59,6 +59,7 @@ struct UpArgs {
     uint32_t n_chunks;    // column chunks of width CW
     uint32_t row_tiles;   // row tiles of ROWS_PER_TILE rows
     int max_hops;         // hop slots per row in the table
+    int map;              // block -> tile order (up_tile)
     const int* skip;
 };
 
@@ -68,6 +69,33 @@ template <typename E>
 __device__ __forceinline__ uint32_t hop_entry(const E* ell, uint32_t h, uint64_t s, uint64_t D) {
     if (sizeof(E) == 2) return ell[(((uint64_t)(h >> 1) * D + s) << 1) + (h & 1u)];
     return ell[(uint64_t)h * D + s];
+}
+
+// VEC consecutive elements at element alignment (the ISA's multi-dword loads
+// need only 4-byte alignment).
+template <typename T, int VEC>
+__device__ __forceinline__ void vec_load(const T* p, T (&out)[VEC]) {
+    if constexpr (VEC == 1) {
+        out[0] = p[0];
+    } else {
+        typedef T vt __attribute__((ext_vector_type(VEC), aligned(sizeof(T))));
+        const vt t = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) out[i] = t[i];
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void vec_store(T* p, const T (&in)[VEC]) {
+    if constexpr (VEC == 1) {
+        p[0] = in[0];
+    } else {
+        typedef T vt __attribute__((ext_vector_type(VEC), aligned(sizeof(T))));
+        vt t;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) t[i] = in[i];
+        *reinterpret_cast<vt*>(p) = t;
+    }
 }
 
 template <typename T>
@@ -101,7 +129,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const uint64_t k = threadIdx.x + (uint64_t)i * kWideBlock;
-            pre[i] = (k < nelem) ? base[k] : (T)0;
+            pre[i] = (k < nelem) ? __builtin_nontemporal_load(base + k) : (T)0;
         }
     };
     if (blockIdx.x < ngroups) fetch(blockIdx.x);
@@ -156,7 +184,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    if (r < nr) y[(u0 + r) * D_dn + d] = acc[r];
+                    if (r < nr) __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
                 continue;
             }
             int h = 0;
@@ -186,7 +214,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
             }
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (r < nr) y[(u0 + r) * D_dn + d] = acc[r];
+                if (r < nr) __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
         }
     }
 }
@@ -233,6 +261,25 @@ __global__ __launch_bounds__(kNarrowBlock) void k_hv_down_narrow(const DownArgs<
 
 // ------------------------------------------------------------------ up pass
 
+// Block -> (column chunk, row tile).  map 1: blocks are dealt to the XCDs
+// round robin (block b on XCD b % 8), so each XCD walks a pair of
+// neighbouring chunks at a time through every row tile and keeps their slab
+// in its L2; map 2: chunk-major order over all blocks.
+__device__ __forceinline__ void up_tile(uint32_t b, uint32_t rt, int map, uint32_t* chunk, uint32_t* tile) {
+    if (map == 2) {
+        *chunk = b / rt;
+        *tile = b % rt;
+        return;
+    }
+    constexpr int kXcd = 8;
+    const uint32_t xcd = b % kXcd;
+    const uint32_t j = b / kXcd;
+    const uint32_t pair = j / (2 * rt);
+    const uint32_t half = (j / rt) & 1u;
+    *tile = j % rt;
+    *chunk = 2 * (xcd + kXcd * pair) + half;
+}
+
 // One decoded up hop: element offset of the source row and its amplitude.
 template <typename T>
 struct UpHop;
@@ -263,15 +310,8 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
     UpHop<T>* s_hop = reinterpret_cast<UpHop<T>*>(smem);                    // ROWS * maxh
     uint64_t* s_off64 = reinterpret_cast<uint64_t*>(s_hop + ROWS_PER_TILE * maxh);  // ROWS * maxh if IDX64
     int* s_cnt = reinterpret_cast<int*>(s_off64 + (IDX64 ? ROWS_PER_TILE * maxh : 0));
-    constexpr int kXcd = 8;
-    const uint32_t b = blockIdx.x;
-    const uint32_t xcd = b % kXcd;
-    const uint32_t j = b / kXcd;
-    const uint32_t rt = a.row_tiles;
-    const uint32_t pair = j / (2 * rt);
-    const uint32_t half = (j / rt) & 1u;
-    const uint32_t tile = j % rt;
-    const uint32_t chunk = 2 * (xcd + kXcd * pair) + half;
+    uint32_t chunk, tile;
+    up_tile(blockIdx.x, a.row_tiles, a.map, &chunk, &tile);
     if (chunk >= a.n_chunks) return;
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
     const uint64_t u_begin = (uint64_t)tile * ROWS_PER_TILE;
@@ -288,6 +328,92 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
             s_hop[k].off = (e & a.tmask) * (uint32_t)D_dn;
     }
     __syncthreads();
+    // each lane owns VEC consecutive columns: CW / VEC lanes per row segment
+    constexpr int VEC = (CW >= 256 && sizeof(T) == 4) ? 4 : (CW >= 128 ? 2 : 1);
+    constexpr int LANES = CW / VEC;
+    const uint32_t lane = threadIdx.x % LANES;
+    const uint64_t d = (uint64_t)chunk * CW + (uint64_t)lane * VEC;
+    if (d >= D_dn) return;
+    const int nv = (d + VEC <= D_dn) ? VEC : (int)(D_dn - d);   // valid columns of this lane
+    constexpr int kSlots = kUpBlock / LANES;
+    for (int r = threadIdx.x / LANES; r < nrows; r += kSlots) {
+        const uint64_t u = u_begin + r;
+        const int cnt = s_cnt[r];
+        const UpHop<T>* hp = s_hop + r * maxh;
+        const uint64_t* o64 = s_off64 + r * maxh;
+        T* yr = y + u * D_dn + d;
+        T acc[VEC];
+        if (VEC == 1) {
+            acc[0] = __builtin_nontemporal_load(yr);   // streamed: keep the x slab in L2
+        } else if (nv == VEC) {
+            vec_load<T, VEC>(yr, acc);
+        } else {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[i] = (i < nv) ? yr[i] : (T)0;
+        }
+        int h = 0;
+        if (nv == VEC) {
+            for (; h + 8 <= cnt; h += 8) {
+                T v[8][VEC];
+                T c[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const UpHop<T> hq = hp[h + q];
+                    c[q] = hq.c;
+                    const T* src = IDX64 ? x + o64[h + q] + d : x + (uint32_t)(hq.off + (uint32_t)d);
+                    vec_load<T, VEC>(src, v[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) acc[i] += c[q] * v[q][i];
+            }
+        }
+        for (; h < cnt; ++h) {
+            const UpHop<T> hq = hp[h];
+            const T* src = IDX64 ? x + o64[h] + d : x + (uint32_t)(hq.off + (uint32_t)d);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i)
+                if (i < nv) acc[i] += hq.c * src[i];
+        }
+        if (VEC == 1) {
+            __builtin_nontemporal_store(acc[0], yr);
+        } else if (nv == VEC) {
+            vec_store<T, VEC>(yr, acc);
+        } else {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i)
+                if (i < nv) yr[i] = acc[i];
+        }
+    }
+}
+
+// Same tile order and decoded hop lists as k_hv_up, but every hop load of a
+// row is issued before the first multiply-add (MAXH bounds the row's hop
+// count): one memory round trip per row.  One column per lane, 32-bit offsets.
+template <typename T, typename E, int CW, int ROWS_PER_TILE, int MAXH>
+__global__ __launch_bounds__(kUpBlock) void k_hv_up_pre(const UpArgs<T, E> a, const T* __restrict__ x,
+                                                        T* __restrict__ y) {
+    if (a.skip && *a.skip) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int maxh = a.max_hops;
+    UpHop<T>* s_hop = reinterpret_cast<UpHop<T>*>(smem);
+    int* s_cnt = reinterpret_cast<int*>(s_hop + ROWS_PER_TILE * maxh);
+    uint32_t chunk, tile;
+    up_tile(blockIdx.x, a.row_tiles, a.map, &chunk, &tile);
+    if (chunk >= a.n_chunks) return;
+    const uint64_t D_up = a.D_up, D_dn = a.D_dn;
+    const uint64_t u_begin = (uint64_t)tile * ROWS_PER_TILE;
+    const int nrows = (int)((D_up - u_begin) < (uint64_t)ROWS_PER_TILE ? (D_up - u_begin) : (uint64_t)ROWS_PER_TILE);
+    for (int r = threadIdx.x; r < nrows; r += kUpBlock) s_cnt[r] = a.up_count[u_begin + r];
+    for (int k = threadIdx.x; k < nrows * maxh; k += kUpBlock) {
+        const int r = k / maxh, h = k - r * maxh;
+        const uint32_t e = hop_entry(a.up_ell, h, u_begin + r, D_up);
+        const uint32_t ci = e >> a.cshift;
+        s_hop[k].c = a.coef[ci < (uint32_t)a.ncoef ? ci : 0];
+        s_hop[k].off = (e & a.tmask) * (uint32_t)D_dn;
+    }
+    __syncthreads();
     const uint32_t col = threadIdx.x % CW;
     const uint64_t d = (uint64_t)chunk * CW + col;
     if (d >= D_dn) return;
@@ -296,29 +422,14 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
         const uint64_t u = u_begin + r;
         const int cnt = s_cnt[r];
         const UpHop<T>* hp = s_hop + r * maxh;
-        const uint64_t* o64 = s_off64 + r * maxh;
-        T acc = y[u * D_dn + d];
-        int h = 0;
-        for (; h + 8 <= cnt; h += 8) {
-            T v[8];
-            T c[8];
+        T v[MAXH];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const UpHop<T> hq = hp[h + q];
-                c[q] = hq.c;
-                if (IDX64)
-                    v[q] = x[o64[h + q] + d];
-                else
-                    v[q] = x[hq.off + (uint32_t)d];
-            }
+        for (int h = 0; h < MAXH; ++h) v[h] = (h < cnt) ? x[(uint32_t)(hp[h].off + (uint32_t)d)] : (T)0;
+        T acc = __builtin_nontemporal_load(y + u * D_dn + d);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc += c[q] * v[q];
-        }
-        for (; h < cnt; ++h) {
-            const UpHop<T> hq = hp[h];
-            acc += hq.c * (IDX64 ? x[o64[h] + d] : x[hq.off + (uint32_t)d]);
-        }
-        y[u * D_dn + d] = acc;
+        for (int h = 0; h < MAXH; ++h)
+            if (h < cnt) acc += hp[h].c * v[h];
+        __builtin_nontemporal_store(acc, y + u * D_dn + d);
     }
 }
 
@@ -450,9 +561,22 @@ void launch_up(bool idx64, uint64_t blocks, size_t lds, hipStream_t s, const UpA
                            ua, x, y);
 }
 
+template <typename T, typename E, int CW>
+void launch_up_pre(int max_hops, uint64_t blocks, size_t lds, hipStream_t s, const UpArgs<T, E>& ua, const T* x,
+                   T* y) {
+    const dim3 g((unsigned)blocks), b(kUpBlock);
+    if (max_hops <= 16)
+        hipLaunchKernelGGL((k_hv_up_pre<T, E, CW, up_rows<T>(), 16>), g, b, lds, s, ua, x, y);
+    else if (max_hops <= 32)
+        hipLaunchKernelGGL((k_hv_up_pre<T, E, CW, up_rows<T>(), 32>), g, b, lds, s, ua, x, y);
+    else
+        hipLaunchKernelGGL((k_hv_up_pre<T, E, CW, up_rows<T>(), 48>), g, b, lds, s, ua, x, y);
+}
+
 // Chunk widths offered per precision (columns).
-constexpr int kUpCw32[] = {16, 32, 64};
-constexpr int kUpCw64[] = {8, 16, 32};
+constexpr int kUpCw32[] = {32, 64, 128, 256};
+constexpr int kUpCw64[] = {16, 32, 64, 128};
+constexpr int kNumCw = 4;
 
 bool row_fits(const pdz_problem_s* p, size_t es, int rows) {
     const size_t lds_cap = kLdsBytes - kMaxCoef * es - 1024;
@@ -471,7 +595,9 @@ HvPlan default_plan(const pdz_problem_s* p, pdz_dtype dt) {
         d.down = 1;
     else
         d.down = 2;
-    d.up_cw = dt == PDZ_F64 ? 16 : 32;
+    d.up_cw = dt == PDZ_F64 ? 32 : 64;
+    d.up = 1;
+    d.map = 1;
     return d;
 }
 
@@ -480,6 +606,8 @@ HvPlan hv_resolve(const pdz_problem_s* p, pdz_dtype dt) {
     const HvPlan d = default_plan(p, dt);
     if (pl.down == 0) pl.down = d.down;
     if (pl.up_cw == 0) pl.up_cw = d.up_cw;
+    if (pl.up == 0) pl.up = d.up;
+    if (pl.map == 0) pl.map = d.map;
     return pl;
 }
 
@@ -555,23 +683,39 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     ua.max_hops = p->up.max_hops;
     ua.n_chunks = (uint32_t)((D_dn + CW - 1) / CW);
     const size_t lds = (size_t)ROWS * ua.max_hops * (sizeof(UpHop<T>) + (idx64 ? 8 : 0)) + ROWS * sizeof(int);
-    const uint64_t pairs = (ua.n_chunks + 1) / 2;
-    const uint64_t pairs_per_xcd = (pairs + kXcd - 1) / kXcd;
-    const uint64_t blocks = kXcd * pairs_per_xcd * 2 * ua.row_tiles;
-    if (sizeof(T) == 8) {
-        if (CW == 8)
-            launch_up<T, E, 8>(idx64, blocks, lds, s, ua, x, y);
-        else if (CW == 16)
-            launch_up<T, E, 16>(idx64, blocks, lds, s, ua, x, y);
+    ua.map = plan.map;
+    uint64_t blocks = (uint64_t)ua.n_chunks * ua.row_tiles;
+    if (plan.map == 1) {
+        const uint64_t pairs = (ua.n_chunks + 1) / 2;
+        const uint64_t pairs_per_xcd = (pairs + kXcd - 1) / kXcd;
+        blocks = kXcd * pairs_per_xcd * 2 * ua.row_tiles;
+    }
+    if (plan.up == 2 && !idx64) {
+        // preloaded rows: one column per lane (CW <= 64)
+        if (sizeof(T) == 8 && CW == 16)
+            launch_up_pre<T, E, 16>(ua.max_hops, blocks, lds, s, ua, x, y);
+        else if (CW == 32)
+            launch_up_pre<T, E, 32>(ua.max_hops, blocks, lds, s, ua, x, y);
         else
-            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, y);
-    } else {
+            launch_up_pre<T, E, 64>(ua.max_hops, blocks, lds, s, ua, x, y);
+    } else if (sizeof(T) == 8) {
         if (CW == 16)
             launch_up<T, E, 16>(idx64, blocks, lds, s, ua, x, y);
         else if (CW == 32)
             launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, y);
-        else
+        else if (CW == 64)
             launch_up<T, E, 64>(idx64, blocks, lds, s, ua, x, y);
+        else
+            launch_up<T, E, 128>(idx64, blocks, lds, s, ua, x, y);
+    } else {
+        if (CW == 32)
+            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, y);
+        else if (CW == 64)
+            launch_up<T, E, 64>(idx64, blocks, lds, s, ua, x, y);
+        else if (CW == 128)
+            launch_up<T, E, 128>(idx64, blocks, lds, s, ua, x, y);
+        else
+            launch_up<T, E, 256>(idx64, blocks, lds, s, ua, x, y);
     }
     PDZ_HIP(hipGetLastError());
     return ok();
@@ -614,6 +758,17 @@ pdz_status set_up_lds() {
     return ok();
 }
 
+template <typename T, typename E, int CW>
+pdz_status set_up_pre_lds() {
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up_pre<T, E, CW, up_rows<T>(), 16>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up_pre<T, E, CW, up_rows<T>(), 32>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up_pre<T, E, CW, up_rows<T>(), 48>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+    return ok();
+}
+
 template <typename T, typename E>
 pdz_status prepare_one() {
     const int lds = (int)kLdsBytes;
@@ -627,9 +782,13 @@ pdz_status prepare_one() {
     if (st != PDZ_OK) return st;
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_narrow<T, E, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 8 : 16>();
     if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 16 : 32>();
     if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 32 : 64>();
+    if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 64 : 128>();
+    if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 128 : 256>();
+    if (sizeof(T) == 8 && st == PDZ_OK) st = set_up_pre_lds<T, E, 16>();
+    if (st == PDZ_OK) st = set_up_pre_lds<T, E, 32>();
+    if (st == PDZ_OK) st = set_up_pre_lds<T, E, 64>();
     return st;
 }
 
@@ -659,20 +818,28 @@ std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
         downs.push_back(d.down);
     }
     const int* cws = dt == PDZ_F64 ? kUpCw64 : kUpCw32;
+    const bool pre_ok = p->up.max_hops <= 48 && p->D <= 0xFFFFFFFFull;
     for (int dv : downs)
-        for (int k = 0; k < 3; ++k) {
-            HvPlan c;
-            c.down = dv;
-            c.up_cw = cws[k];
-            if (c.down != d.down || c.up_cw != d.up_cw) out.push_back(c);
-        }
+        for (int k = 0; k < kNumCw; ++k)
+            for (int um = 1; um <= 2; ++um)
+                for (int mp = 1; mp <= 2; ++mp) {
+                    HvPlan c;
+                    c.down = dv;
+                    c.up_cw = cws[k];
+                    c.up = um;
+                    c.map = mp;
+                    if (um == 2 && (!pre_ok || cws[k] > 64)) continue;
+                    if (c.down != d.down || c.up_cw != d.up_cw || c.up != d.up || c.map != d.map) out.push_back(c);
+                }
     return out;
 }
 
 bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan) {
-    if (plan.down == 0 && plan.up_cw == 0) return true;
+    if (plan.down == 0 && plan.up_cw == 0 && plan.up == 0 && plan.map == 0) return true;
     for (const HvPlan& c : hv_candidates(p, dt))
-        if ((plan.down == 0 || plan.down == c.down) && (plan.up_cw == 0 || plan.up_cw == c.up_cw)) return true;
+        if ((plan.down == 0 || plan.down == c.down) && (plan.up_cw == 0 || plan.up_cw == c.up_cw) &&
+            (plan.up == 0 || plan.up == c.up) && (plan.map == 0 || plan.map == c.map))
+            return true;
     return false;
 }
 

@@ -54,6 +54,8 @@ struct HvPlan {
     int down = 0;    // 1: one row per group, hop table loaded up front; 2: one row, table in a loop;
                      // 3: two rows per group, table in a loop
     int up_cw = 0;   // up-pass chunk width in columns
+    int up = 0;      // 1: hops of a row loaded in batches of 8; 2: all hops of a row loaded up front
+    int map = 0;     // up-pass tile order: 1 XCD-aware chunk pairs, 2 chunk-major
 };
 }  // namespace pdz
 

@@ -28,8 +28,12 @@ pdz_status pdz_hv_get_plan(pdz_problem p, pdz_dtype dt, pdz_hv_plan* out) {
     HvPlan pl = p->plan[dt];
     if (pl.down == 0) pl.down = c[0].down;
     if (pl.up_cw == 0) pl.up_cw = c[0].up_cw;
+    if (pl.up == 0) pl.up = c[0].up;
+    if (pl.map == 0) pl.map = c[0].map;
     out->down = pl.down;
     out->up_cw = pl.up_cw;
+    out->up = pl.up;
+    out->map = pl.map;
     return ok();
 }
 
@@ -40,6 +44,8 @@ pdz_status pdz_hv_set_plan(pdz_problem p, pdz_dtype dt, const pdz_hv_plan* plan)
     HvPlan pl;
     pl.down = plan->down;
     pl.up_cw = plan->up_cw;
+    pl.up = plan->up;
+    pl.map = plan->map;
     if (!hv_plan_valid(p, dt, pl)) return fail(PDZ_EINVAL, "plan not available for this problem and precision");
     p->plan[dt] = pl;
     return ok();
@@ -81,6 +87,8 @@ pdz_status pdz_hv_tune(pdz_problem p, pdz_dtype dt, const void* x, void* y, int3
         if (n < max_trials) {
             trials[n].plan.down = c.down;
             trials[n].plan.up_cw = c.up_cw;
+            trials[n].plan.up = c.up;
+            trials[n].plan.map = c.map;
             trials[n].ms = avg;
         }
         ++n;
@@ -100,6 +108,8 @@ pdz_status pdz_hv_tune(pdz_problem p, pdz_dtype dt, const void* x, void* y, int3
     if (best) {
         best->down = best_plan.down;
         best->up_cw = best_plan.up_cw;
+        best->up = best_plan.up;
+        best->map = best_plan.map;
     }
     return ok();
 }

@@ -39,7 +39,7 @@ def tuned_plan(problem, dtype_name, reps=5, path=None, retune=False):
     cache = _load(path)
     if not retune and key in cache:
         entry = cache[key]
-        problem.set_plan(dtype_name, entry["down"], entry["up_cw"])
+        problem.set_plan(dtype_name, entry["down"], entry["up_cw"], entry.get("up", 0), entry.get("map", 0))
         return entry, None
     best, trials = problem.tune(dtype_name, reps=reps)
     entry = dict(best, ms=min(t["ms"] for t in trials))

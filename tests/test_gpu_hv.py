@@ -177,10 +177,11 @@ def test_every_plan_gives_identical_results(name):
         x = to_dev(synth.random_vector(g.D, 5), dt)
         ref = g.hv(x)
         best, trials = g.tune(dt, reps=1, x=x, y=torch.empty_like(x))
-        assert len(trials) >= 1 and best in [{"down": t["down"], "up_cw": t["up_cw"]} for t in trials]
+        keys = ("down", "up_cw", "up", "map")
+        assert len(trials) >= 1 and best in [{k: t[k] for k in keys} for t in trials]
         for t in trials:
-            g.set_plan(dt, t["down"], t["up_cw"])
-            assert g.get_plan(dt) == {"down": t["down"], "up_cw": t["up_cw"]}
+            g.set_plan(dt, *[t[k] for k in keys])
+            assert g.get_plan(dt) == {k: t[k] for k in keys}
             assert torch.equal(g.hv(x), ref), (name, dt, t)
 
 

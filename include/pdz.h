@@ -223,6 +223,84 @@ pdz_status pdz_lanczos(pdz_problem p, const pdz_lanczos_opts* o, const void* v0,
 pdz_status pdz_lanczos_history(pdz_problem p, const pdz_lanczos_opts* o, const void* ws, size_t ws_bytes,
                                int32_t max_n, double* theta_host, int32_t* n_out);
 
+/* ---------------------------------------------------------------- batches */
+
+/* Many independent problems (each the H of Eq. 1 on its own sites, bonds, U
+ * and electron numbers) solved together.  Their vectors are packed into one
+ * device array: problem i occupies elements [off_i, off_i + D_i), off_i a
+ * multiple of 64, and the gaps between problems are ignored on input and left
+ * untouched on output by pdz_batch_hv.  Within its slice each vector has the
+ * single-problem layout (idx = C(N, n_dn) idx_up + idx_dn, Sec. III). */
+typedef struct pdz_batch_s* pdz_batch;
+
+/* Batched H.v launch plan (0 = default for that field). */
+typedef struct {
+    int32_t tile_elems;   /* about this many vector elements per tile: 1024, 2048, 4096 or 8192      */
+    int32_t block;        /* threads per work group: 256, 512 or 1024                                */
+    int32_t wgs_per_cu;   /* persistent work groups per compute unit, 1..8                           */
+    int32_t order;        /* tile queue order: 1 largest problems first, 2 problem order             */
+} pdz_batch_plan;
+
+typedef struct {
+    pdz_batch_plan plan;
+    double ms;            /* mean time of one pdz_batch_hv with this plan */
+} pdz_batch_trial;
+
+/* Group n >= 1 problems created on the current device.  The problems must
+ * outlive the batch and use sector hop tables (every sector of at most 2^24
+ * states); one row of the down sector (C(N, n_dn) values in FP64) must fit the
+ * 160 KiB of LDS of one work group.  Errors: PDZ_EINVAL (NULL argument,
+ * problem on another device), PDZ_ERANGE (a problem without hop tables or
+ * with too long rows), PDZ_EHIP. */
+pdz_status pdz_batch_create(const pdz_problem* problems, int32_t n, pdz_batch* out);
+
+/* Release the batch (not its problems).  NULL is a no-op.  Synchronises the device. */
+pdz_status pdz_batch_destroy(pdz_batch b);
+
+/* Host array of n + 1 element offsets: offsets[i] = start of problem i,
+ * offsets[n] = length of the packed array. */
+pdz_status pdz_batch_offsets(pdz_batch b, uint64_t* offsets);
+
+/* y_i = H_i x_i for every problem i of the batch, in one persistent launch:
+ * work groups take tiles (problem, group of rows) from a device queue, so the
+ * uneven sizes balance across the chip.  x, y: packed device arrays
+ * (offsets[n] elements of precision dt), not overlapping.  Each output is
+ * summed in the same order as pdz_hv on its problem, so results are bitwise
+ * identical to n single calls.  Asynchronous on `stream`; capturable in a
+ * HIP graph.  Calls on one batch must not overlap (they share its queue
+ * counter).  Errors: PDZ_EINVAL. */
+pdz_status pdz_batch_hv(pdz_batch b, pdz_dtype dt, const void* x, void* y, void* stream);
+
+pdz_status pdz_batch_get_plan(pdz_batch b, pdz_batch_plan* out);
+/* Errors: PDZ_EINVAL for a plan outside the ranges above. */
+pdz_status pdz_batch_set_plan(pdz_batch b, const pdz_batch_plan* plan);
+
+/* Autotuner: time every plan of the search space on x, y (packed arrays as
+ * in pdz_batch_hv; y is overwritten), `reps` launches each after a warm-up,
+ * select the fastest and return it in *best.  trials (may be NULL) receives
+ * up to max_trials timings, *n_trials their count.  Synchronous. */
+pdz_status pdz_batch_tune(pdz_batch b, pdz_dtype dt, const void* x, void* y, int32_t reps, pdz_batch_trial* trials,
+                          int32_t max_trials, int32_t* n_trials, pdz_batch_plan* best, void* stream);
+
+/* Bytes of device workspace pdz_batch_lanczos needs for these options. */
+pdz_status pdz_batch_lanczos_workspace_size(pdz_batch b, const pdz_lanczos_opts* o, size_t* bytes);
+
+/* Lowest eigenvalue of every problem of the batch by the Lanczos recurrence
+ * of pdz_lanczos, all problems in lockstep: one batched H.v per step, FP64
+ * alpha, beta, Ritz value and convergence flag per problem on the device, and
+ * a converged problem skipped by every later kernel.  With use_graph, blocks
+ * of check_every steps (rounded up to a multiple of 3) are replayed as one
+ * captured HIP graph.  Problem i starts from the seeded vector of seed + i
+ * (the pdz_lanczos start vector of that seed), so its result equals a
+ * pdz_lanczos run with that seed up to summation order.  reorth and refine
+ * must be 0.  ws: caller-owned device workspace, 256-byte aligned.
+ * results: host array of n entries.  Synchronous.
+ * Errors: PDZ_EINVAL (bad options, workspace too small, non-finite scalar);
+ * PDZ_ENOCONV when some problem reached max_iter (results still hold every
+ * problem's best estimate). */
+pdz_status pdz_batch_lanczos(pdz_batch b, const pdz_lanczos_opts* o, void* ws, size_t ws_bytes,
+                             pdz_lanczos_result* results, void* stream);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Message of the last failing call on this thread ("" if none).  Valid until

@@ -8,7 +8,7 @@ import ctypes
 from . import _lib
 from ._lib import PdzError, PDZ_F64, PDZ_F32, LanczosOpts, LanczosResult
 
-__all__ = ["Problem", "rank", "unrank", "device_errors", "PdzError", "PDZ_F64", "PDZ_F32", "lib",
+__all__ = ["Problem", "Batch", "rank", "unrank", "device_errors", "PdzError", "PDZ_F64", "PDZ_F32", "lib",
            "LanczosOpts", "LanczosResult"]
 
 
@@ -163,6 +163,108 @@ class Problem:
                                                  workspace.numel(), o.max_iter, buf, ctypes.byref(n)))
             out["thetas"] = list(buf[:n.value])
         return out
+
+
+class Batch:
+    """Several problems solved together (pdz_batch handle); vectors are packed at `offsets`."""
+
+    def __init__(self, problems):
+        L = lib()
+        self.problems = list(problems)   # the batch refers to them: keep them alive
+        arr = (ctypes.c_void_p * len(self.problems))(*[q.handle.value for q in self.problems])
+        h = ctypes.c_void_p()
+        _lib.check(L.pdz_batch_create(arr, len(self.problems), ctypes.byref(h)))
+        self._h = h
+        offs = (ctypes.c_uint64 * (len(self.problems) + 1))()
+        _lib.check(L.pdz_batch_offsets(h, offs))
+        self.offsets = list(offs)
+
+    @property
+    def n(self):
+        return len(self.problems)
+
+    @property
+    def total(self):
+        return self.offsets[-1]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().pdz_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, vectors, dtype=None):
+        """Packed device array holding the given per-problem device vectors."""
+        import torch
+        dt = dtype or vectors[0].dtype
+        out = torch.zeros(self.total, dtype=dt, device="cuda")
+        for i, v in enumerate(vectors):
+            out[self.offsets[i]:self.offsets[i] + v.numel()].copy_(v)
+        return out
+
+    def unpack(self, x):
+        return [x[self.offsets[i]:self.offsets[i] + q.D] for i, q in enumerate(self.problems)]
+
+    def hv(self, x, y=None, stream=None):
+        """y_i = H_i x_i for every problem, one launch (packed contiguous device tensors)."""
+        import torch
+        if not x.is_cuda or not x.is_contiguous() or x.numel() != self.total:
+            raise ValueError("x must be a contiguous packed device tensor")
+        if y is None:
+            y = torch.zeros_like(x)
+        if y.dtype != x.dtype or y.numel() != self.total or not y.is_contiguous():
+            raise ValueError("y must match x")
+        _lib.check(lib().pdz_batch_hv(self._h, _dtype_code(x.dtype), ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(y.data_ptr()), _stream_handle(stream)))
+        return y
+
+    def get_plan(self):
+        pl = _lib.BatchPlan()
+        _lib.check(lib().pdz_batch_get_plan(self._h, ctypes.byref(pl)))
+        return {f: getattr(pl, f) for f, _ in _lib.BatchPlan._fields_}
+
+    def set_plan(self, tile_elems=0, block=0, wgs_per_cu=0, order=0):
+        pl = _lib.BatchPlan(int(tile_elems), int(block), int(wgs_per_cu), int(order))
+        _lib.check(lib().pdz_batch_set_plan(self._h, ctypes.byref(pl)))
+
+    def tune(self, dtype, reps=5, stream=None):
+        """Autotune the batched H.v plan (libpdz times the search space); returns (best, trials)."""
+        import torch
+        tdt = torch.float64 if _dtype_code(dtype) == PDZ_F64 else torch.float32
+        x = torch.empty(self.total, dtype=tdt, device="cuda").uniform_(-1.0, 1.0)
+        y = torch.empty_like(x)
+        trials = (_lib.BatchTrial * 128)()
+        n = ctypes.c_int32()
+        best = _lib.BatchPlan()
+        _lib.check(lib().pdz_batch_tune(self._h, _dtype_code(dtype), ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(y.data_ptr()), int(reps), trials, 128, ctypes.byref(n),
+                                        ctypes.byref(best), _stream_handle(stream)))
+        fields = [f for f, _ in _lib.BatchPlan._fields_]
+        out = [dict({f: getattr(trials[k].plan, f) for f in fields}, ms=trials[k].ms) for k in range(n.value)]
+        return {f: getattr(best, f) for f in fields}, out
+
+    def lanczos(self, workspace=None, stream=None, allow_noconv=True, **kw):
+        """Lowest eigenvalue of every problem; returns (list of result dicts, status)."""
+        import torch
+        o = self.problems[0].lanczos_opts(**kw)
+        n = ctypes.c_size_t()
+        _lib.check(lib().pdz_batch_lanczos_workspace_size(self._h, ctypes.byref(o), ctypes.byref(n)))
+        if workspace is None:
+            workspace = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+        res = (LanczosResult * self.n)()
+        st = lib().pdz_batch_lanczos(self._h, ctypes.byref(o), ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel(), res, _stream_handle(stream))
+        _lib.check(st, allow=(_lib.PDZ_ENOCONV,) if allow_noconv else ())
+        return [{f: getattr(r, f) for f, _ in LanczosResult._fields_} for r in res], st
 
 
 def rank(n_sites, n, bits, stream=None):

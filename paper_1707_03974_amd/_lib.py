@@ -64,6 +64,15 @@ class HvTrial(ctypes.Structure):
     _fields_ = [("plan", HvPlan), ("ms", ctypes.c_double)]
 
 
+class BatchPlan(ctypes.Structure):
+    _fields_ = [("tile_elems", ctypes.c_int32), ("block", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
+
+
+class BatchTrial(ctypes.Structure):
+    _fields_ = [("plan", BatchPlan), ("ms", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "pdz_problem_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(Bond), ctypes.c_int32, ctypes.c_double,
@@ -84,6 +93,19 @@ _SIGNATURES = {
                                      ctypes.POINTER(LanczosResult), _P]),
     "pdz_lanczos_history": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
+    "pdz_batch_create": (ctypes.c_int32, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "pdz_batch_destroy": (ctypes.c_int32, [_P]),
+    "pdz_batch_offsets": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    "pdz_batch_hv": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, _P]),
+    "pdz_batch_get_plan": (ctypes.c_int32, [_P, ctypes.POINTER(BatchPlan)]),
+    "pdz_batch_set_plan": (ctypes.c_int32, [_P, ctypes.POINTER(BatchPlan)]),
+    "pdz_batch_tune": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(BatchTrial),
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(BatchPlan),
+                                        _P]),
+    "pdz_batch_lanczos_workspace_size": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts),
+                                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "pdz_batch_lanczos": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t,
+                                           ctypes.POINTER(LanczosResult), _P]),
     "pdz_last_error": (ctypes.c_char_p, []),
     "pdz_version": (ctypes.c_int32, []),
 }

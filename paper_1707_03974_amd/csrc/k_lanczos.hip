@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "pdz_internal.h"
+#include "tridiag.h"
 
 namespace pdz {
 
@@ -48,15 +49,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     const double r = red[0];
     __syncthreads();
     return r;
-}
-
-// SplitMix64, output r of the generator seeded with `seed`, as a double in [-1, 1).
-__device__ __forceinline__ double splitmix_uniform(uint64_t seed, uint64_t r) {
-    uint64_t z = seed + (r + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z = z ^ (z >> 31);
-    return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
 }
 
 template <typename T>
@@ -235,19 +227,6 @@ __global__ __launch_bounds__(kRedBlock) void k_resid_partial(const double* __res
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-// Number of eigenvalues of T below x (Sturm sequence via the LDL^T pivots).
-__device__ int sturm_count(const double* a, const double* e, int k, double x) {
-    int cnt = 0;
-    double q = a[0] - x;
-    if (q < 0.0) ++cnt;
-    for (int i = 1; i < k; ++i) {
-        if (q == 0.0) q = 1e-300;
-        q = (a[i] - x) - e[i] * e[i] / q;
-        if (q < 0.0) ++cnt;
-    }
-    return cnt;
-}
-
 // One block: theta = lambda_min(T_k), s = its normalised eigenvector, the
 // convergence test, and the step counter.  alpha[0..k-1] is the diagonal,
 // beta[1..k-1] the off-diagonal, beta[k] = beta_{k+1}.
@@ -266,80 +245,11 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiag(const double* alpha, cons
         e[i] = (i == 0) ? 0.0 : beta[i];
     }
     __syncthreads();
-    // Gershgorin interval
-    double lo = 1e300, hi = -1e300;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) {
-        const double r = fabs(e[i]) + (i + 1 < k ? fabs(e[i + 1]) : 0.0);
-        lo = fmin(lo, a[i] - r);
-        hi = fmax(hi, a[i] + r);
-    }
-    lo_s[threadIdx.x] = lo;
-    hi_s[threadIdx.x] = hi;
-    __syncthreads();
-    for (int st = kRedBlock / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
-            lo_s[threadIdx.x] = fmin(lo_s[threadIdx.x], lo_s[threadIdx.x + st]);
-            hi_s[threadIdx.x] = fmax(hi_s[threadIdx.x], hi_s[threadIdx.x + st]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double pad = 1e-12 * fmax(1.0, fmax(fabs(lo_s[0]), fabs(hi_s[0])));
-        bounds[0] = lo_s[0] - pad;
-        bounds[1] = hi_s[0] + pad;
-    }
-    __syncthreads();
-    // multisection: each round splits [lo, hi] into blockDim+1 pieces
-    for (int round = 0; round < 64; ++round) {
-        lo = bounds[0];
-        hi = bounds[1];
-        if (!(hi - lo > 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
-        const double x = lo + (hi - lo) * (double)(threadIdx.x + 1) / (double)(blockDim.x + 1);
-        if (threadIdx.x == 0) found = blockDim.x;
-        __syncthreads();
-        const int c = sturm_count(a, e, k, x);
-        if (c >= 1) atomicMin(&found, (int)threadIdx.x);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int t = found;
-            const double nlo = (t == 0) ? lo : lo + (hi - lo) * (double)t / (double)(blockDim.x + 1);
-            const double nhi = (t == (int)blockDim.x) ? hi : lo + (hi - lo) * (double)(t + 1) / (double)(blockDim.x + 1);
-            bounds[0] = nlo;
-            bounds[1] = nhi;
-        }
-        __syncthreads();
-    }
+    tridiag_bracket_min(a, e, k, lo_s, hi_s, &found, bounds);
     if (threadIdx.x == 0) {
         const double theta = 0.5 * (bounds[0] + bounds[1]);
-        // inverse iteration with shift below the eigenvalue: T - sigma I is positive semidefinite
-        const double sigma = bounds[0] - 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(bounds[0]));
         double* z = s_out;
-        for (int i = 0; i < k; ++i) z[i] = 1.0;
-        double nrm = 0.0;
-        for (int it = 0; it < 3; ++it) {
-            // LDL^T solve of (T - sigma I) z = z; d and l reuse lo_s/hi_s only when k fits, else recompute
-            double dprev = a[0] - sigma;
-            if (dprev == 0.0) dprev = 1e-300;
-            // forward: L y = b  (store y in z), with pivots d_i
-            // we need d_i again in the backward pass; keep them in e-shaped storage of theta_hist tail
-            double* dpiv = theta_hist + max_iter;   // scratch of length max_iter
-            dpiv[0] = dprev;
-            for (int i = 1; i < k; ++i) {
-                const double l = e[i] / dpiv[i - 1];
-                double di = (a[i] - sigma) - l * e[i];
-                if (di == 0.0) di = 1e-300;
-                dpiv[i] = di;
-                z[i] -= l * z[i - 1];
-            }
-            // D x = y, L^T z = x
-            z[k - 1] /= dpiv[k - 1];
-            for (int i = k - 2; i >= 0; --i) z[i] = z[i] / dpiv[i] - (e[i + 1] / dpiv[i]) * z[i + 1];
-            nrm = 0.0;
-            for (int i = 0; i < k; ++i) nrm += z[i] * z[i];
-            nrm = sqrt(nrm);
-            if (!(nrm > 0.0) || !isfinite(nrm)) break;
-            for (int i = 0; i < k; ++i) z[i] /= nrm;
-        }
+        tridiag_min_vector(a, e, k, bounds[0], z, theta_hist + max_iter);   // pivots in the history tail
         const double bk1 = beta[k];
         const double resid = fabs(bk1 * z[k - 1]);
         theta_hist[k - 1] = theta;

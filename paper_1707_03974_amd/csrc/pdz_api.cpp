@@ -44,6 +44,7 @@ pdz_status device_ctx(DeviceCtx** out) {
         PDZ_HIP(hipMalloc(&c.binom, C.size() * sizeof(uint32_t)));
         PDZ_HIP(hipMemcpy(c.binom, C.data(), C.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         pdz_status hs = hv_prepare();
+        if (hs == PDZ_OK) hs = batch_prepare();
         if (hs != PDZ_OK) return hs;
         c.cu_count = prop.multiProcessorCount;
         c.lds_per_block = prop.sharedMemPerBlock;

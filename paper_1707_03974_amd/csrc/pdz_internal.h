@@ -98,6 +98,15 @@ struct DeviceCtx {
 };
 pdz_status device_ctx(DeviceCtx** out);
 
+// SplitMix64, output r of the generator seeded with `seed`, as a double in [-1, 1).
+__device__ inline double splitmix_uniform(uint64_t seed, uint64_t r) {
+    uint64_t z = seed + (r + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+}
+
 // Host helpers.
 void binomial_table(std::vector<uint32_t>& C);   // Pascal's rule, 33 x 33
 uint64_t binom(int n, int k);
@@ -111,6 +120,7 @@ pdz_status build_sector_tables(const uint32_t* d_binom, int N, int n, const Bond
                                SectorTables* st, uint32_t* err, hipStream_t s);
 pdz_status build_compact_table(SectorTables* st, int ncoef, hipStream_t s);
 pdz_status hv_prepare();   // per-device kernel attributes, called once outside any capture
+pdz_status batch_prepare();   // the same for the batched H.v kernels
 // Candidate plans valid for this problem and precision; the first is the default.
 std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt);
 bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan);

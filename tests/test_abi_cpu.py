@@ -82,3 +82,23 @@ def test_lanczos_default_options_and_validation():
     res = _lib.LanczosResult()
     # a NULL problem is rejected before the options or any device work
     assert lib.pdz_lanczos(None, ctypes.byref(o), None, None, 0, None, ctypes.byref(res), None) == _lib.PDZ_EINVAL
+
+
+def test_batch_calls_reject_null_arguments_without_a_device():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.pdz_batch_create(None, 0, ctypes.byref(h)) == _lib.PDZ_EINVAL
+    assert lib.pdz_batch_create(None, 2, None) == _lib.PDZ_EINVAL
+    assert lib.pdz_batch_destroy(None) == _lib.PDZ_OK
+    offs = (ctypes.c_uint64 * 2)()
+    assert lib.pdz_batch_offsets(None, offs) == _lib.PDZ_EINVAL
+    assert lib.pdz_batch_hv(None, 0, None, None, None) == _lib.PDZ_EINVAL
+    pl = _lib.BatchPlan()
+    assert lib.pdz_batch_get_plan(None, ctypes.byref(pl)) == _lib.PDZ_EINVAL
+    assert lib.pdz_batch_set_plan(None, ctypes.byref(pl)) == _lib.PDZ_EINVAL
+    o = _lib.LanczosOpts()
+    lib.pdz_lanczos_default_opts(ctypes.byref(o))
+    n = ctypes.c_size_t()
+    assert lib.pdz_batch_lanczos_workspace_size(None, ctypes.byref(o), ctypes.byref(n)) == _lib.PDZ_EINVAL
+    res = (_lib.LanczosResult * 1)()
+    assert lib.pdz_batch_lanczos(None, ctypes.byref(o), None, 0, res, None) == _lib.PDZ_EINVAL

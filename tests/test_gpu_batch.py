@@ -1,0 +1,228 @@
+"""Batched H.v and batched Lanczos (libpdz) against the oracle and against single-problem calls.
+
+The batch packs the clusters' vectors at offsets; each output of the batched
+H.v is summed in the order of the single-problem H.v, so the two agree
+bitwise, and both are held to the oracle with the row bound of tests/_gpu.py.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._gpu import torch_cuda, to_dev, to_host, hv_error_bound, EPS64, EPS32
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+SMALL_MIX = [
+    (2, [(0, 1, 1.0)], 4.0, 1, 1),
+    (5, [(0, 1, 1.0), (3, 4, 1.0)], 2.0, 0, 0),                  # D = 1
+    (4, [], 3.0, 2, 2),                                          # no bonds
+    (7, [(i, (i + 1) % 7, 1.0) for i in range(7)], 4.0, 3, 5),   # ragged rows
+    (6, [(0, 5, 1.0), (2, 3, 0.7)], 1.0, 3, 0),                  # D_dn = 1
+    (5, [(0, 1, 1.0), (1, 4, -0.5)], 2.0, 5, 2),                 # full up sector
+]
+
+
+def _pdz():
+    import paper_1707_03974_amd as pdz
+    return pdz
+
+
+def _bonds(args):
+    return [synth.Bond(i, j, t) for i, j, t in args[1]]
+
+
+def _oracle(args):
+    N, bonds, U, nu, nd = args
+    return oracle.Problem(N, [b[0] for b in bonds], [b[1] for b in bonds], [b[2] for b in bonds], U, nu, nd)
+
+
+def _args(w):
+    return (w.n_sites, [(b.i, b.j, b.t) for b in w.bonds], w.U, w.n_up, w.n_dn)
+
+
+def _small_batch_args():
+    out = list(SMALL_MIX)
+    out.append(_args(synth.workload("ring8")))
+    out += [_args(w) for w in synth.batched_workloads() if w.n_sites == 9][:6]
+    return out
+
+
+def _make(args_list):
+    pdz = _pdz()
+    probs = [pdz.Problem(a[0], _bonds(a), a[2], a[3], a[4]) for a in args_list]
+    return probs, pdz.Batch(probs)
+
+
+def _energies():
+    with open(os.path.join(GOLD, "energies.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_batched_hv_matches_oracle_elementwise(dtype_name):
+    torch = torch_cuda()
+    args = _small_batch_args()
+    probs, b = _make(args)
+    dt = torch.float64 if dtype_name == "f64" else torch.float32
+    xs = [synth.random_vector(q.D, 100 + i) for i, q in enumerate(probs)]
+    X = b.pack([to_dev(x, dt) for x in xs])
+    Y = b.hv(X)
+    eps = EPS64 if dtype_name == "f64" else EPS32
+    for a, x, y in zip(args, xs, b.unpack(Y)):
+        H = oracle.build_csr(_oracle(a))
+        err = np.abs(to_host(y).astype(np.float64) - H @ x)
+        assert np.all(err <= hv_error_bound(H, x, eps)), (a, float(err.max()))
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_batched_hv_of_32_clusters_equals_single_calls_bitwise(dtype_name):
+    torch = torch_cuda()
+    ws = synth.batched_workloads()
+    probs, b = _make([_args(w) for w in ws])
+    assert b.n == 32 and all(o % 64 == 0 for o in b.offsets)
+    dt = torch.float64 if dtype_name == "f64" else torch.float32
+    xs = [to_dev(synth.random_vector(q.D, 7 + i), dt) for i, q in enumerate(probs)]
+    Y = b.hv(b.pack(xs))
+    for q, x, y in zip(probs, xs, b.unpack(Y)):
+        assert torch.equal(q.hv(x), y)
+
+
+def test_batched_hv_of_32_clusters_sampled_rows_match_oracle():
+    """Full batch in the benchmark's launch configuration, rows checked one by one."""
+    torch = torch_cuda()
+    ws = synth.batched_workloads()
+    probs, b = _make([_args(w) for w in ws])
+    xs = [synth.random_vector(q.D, 300 + i) for i, q in enumerate(probs)]
+    Y = b.hv(b.pack([to_dev(x, torch.float64) for x in xs]))
+    rng = np.random.default_rng(9)
+    for w, q, x, y in zip(ws, probs, xs, b.unpack(Y)):
+        D, Ddn = q.D, q.info["D_dn"]
+        rows = np.unique(np.concatenate([rng.integers(0, D, 200), [0, Ddn - 1, Ddn, D - Ddn, D - 1]]))
+        got = to_host(y[torch.from_numpy(rows).cuda()])
+        ref = oracle.hv_rows(oracle.Problem.from_workload(w), x, rows)
+        nterms = q.info["max_hops_up"] + q.info["max_hops_dn"] + 1
+        abs_sum = abs(w.U) * min(w.n_up, w.n_dn) + (nterms - 1)
+        bound = (nterms + 2) * EPS64 * abs_sum + nterms * EPS64 * abs_sum
+        assert np.all(np.abs(got - ref) <= bound), w.name
+
+
+def test_every_batch_plan_gives_identical_results_and_gaps_stay_untouched():
+    torch = torch_cuda()
+    ws = synth.batched_workloads()[:12]
+    probs, b = _make([_args(w) for w in ws])
+    X = b.pack([to_dev(synth.random_vector(q.D, i), torch.float32) for i, q in enumerate(probs)])
+    ref = None
+    for te in (1024, 2048, 4096, 8192):
+        for blk in (256, 512, 1024):
+            for wg, order in ((1, 1), (4, 2), (8, 1)):
+                b.set_plan(te, blk, wg, order)
+                assert b.get_plan() == {"tile_elems": te, "block": blk, "wgs_per_cu": wg, "order": order}
+                Y = torch.full_like(X, 1234.5)
+                b.hv(X, Y)
+                if ref is None:
+                    ref = Y.clone()
+                assert torch.equal(Y, ref), (te, blk, wg, order)
+    for i, q in enumerate(probs):   # padding between clusters is not written
+        gap = ref[b.offsets[i] + q.D:b.offsets[i + 1]]
+        assert bool(torch.all(gap == 1234.5))
+    with pytest.raises(_pdz().PdzError):
+        b.set_plan(3000, 256, 4, 1)
+    with pytest.raises(_pdz().PdzError):
+        b.set_plan(4096, 128, 4, 1)
+
+
+def test_batch_autotuner_picks_a_measured_plan():
+    torch = torch_cuda()
+    probs, b = _make([_args(w) for w in synth.batched_workloads()])
+    best, trials = b.tune("f32", reps=2)
+    assert len(trials) >= 10 and all(t["ms"] > 0 for t in trials)
+    assert best == b.get_plan()
+    assert min(trials, key=lambda t: t["ms"])["ms"] == min(t["ms"] for t in trials)
+    X = b.pack([to_dev(synth.random_vector(q.D, 1), torch.float32) for q in probs])
+    Y = b.hv(X)
+    assert torch.equal(Y[:probs[0].D], probs[0].hv(X[:probs[0].D].contiguous()))
+
+
+def test_batched_lanczos_fp64_energies_match_oracle():
+    E = _energies()["batched"]
+    ws = synth.batched_workloads()
+    probs, b = _make([_args(w) for w in ws])
+    res, st = b.lanczos(tol=1e-12, max_iter=600, seed=11)
+    assert st == 0
+    for w, r in zip(ws, res):
+        assert r["converged"] == 1
+        assert abs(r["E0"] - E[w.name]["E0"]) <= 1e-9 * abs(E[w.name]["E0"]), (w.name, r)
+    iters = [r["iters"] for r in res]
+    assert len(set(iters)) > 1   # clusters finish at different steps
+
+
+def test_batched_lanczos_equals_single_runs():
+    ws = synth.batched_workloads()[:8]
+    probs, b = _make([_args(w) for w in ws])
+    res, _ = b.lanczos(tol=1e-10, max_iter=400, seed=5)
+    for i, (q, r) in enumerate(zip(probs, res)):
+        s = q.lanczos(tol=1e-10, max_iter=400, seed=5 + i)
+        assert abs(r["iters"] - s["iters"]) <= 1, (i, r, s)
+        assert abs(r["E0"] - s["E0"]) <= 1e-10 * abs(s["E0"]), (i, r, s)
+
+
+def test_batched_lanczos_graph_and_stream_agree_bitwise():
+    probs, b = _make(_small_batch_args())
+    a, _ = b.lanczos(use_graph=1, check_every=6, tol=1e-12)
+    c, _ = b.lanczos(use_graph=0, check_every=6, tol=1e-12)
+    d, _ = b.lanczos(use_graph=1, check_every=30, tol=1e-12)
+    assert [r["E0"] for r in a] == [r["E0"] for r in c] == [r["E0"] for r in d]
+    assert [r["iters"] for r in a] == [r["iters"] for r in c] == [r["iters"] for r in d]
+
+
+def test_batched_lanczos_small_mix_and_degenerate_clusters():
+    args = _small_batch_args()
+    probs, b = _make(args)
+    res, st = b.lanczos(tol=1e-12, max_iter=300)
+    assert st == 0
+    for a, r in zip(args, res):
+        H = oracle.build_csr(_oracle(a)).toarray()
+        E = float(np.linalg.eigvalsh(H)[0])
+        assert r["converged"] == 1
+        assert abs(r["E0"] - E) <= 1e-9 * max(1.0, abs(E)), (a, r, E)
+    assert res[1]["iters"] == 1   # D = 1: the Krylov space is invariant after one step
+
+
+def test_batched_lanczos_fp32_storage():
+    E = _energies()["batched"]
+    ws = synth.batched_workloads()[:10]
+    probs, b = _make([_args(w) for w in ws])
+    res, st = b.lanczos(storage="f32", tol=1e-7, max_iter=600)
+    for w, r in zip(ws, res):
+        assert abs(r["E0"] - E[w.name]["E0"]) <= 2e-6 * abs(E[w.name]["E0"]), (w.name, r)
+
+
+def test_batched_errors_and_noconv():
+    torch = torch_cuda()
+    pdz = _pdz()
+    from paper_1707_03974_amd import _lib
+    import ctypes
+    probs, b = _make(_small_batch_args())
+    lib = pdz.lib()
+    x = torch.zeros(b.total, dtype=torch.float64, device="cuda")
+    assert lib.pdz_batch_hv(b.handle, 0, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr() + 8),
+                            None) == _lib.PDZ_EINVAL
+    assert lib.pdz_batch_hv(b.handle, 5, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                            None) == _lib.PDZ_EINVAL
+    with pytest.raises(pdz.PdzError):
+        b.lanczos(reorth=1)
+    with pytest.raises(pdz.PdzError):
+        b.lanczos(refine=1)
+    with pytest.raises(pdz.PdzError):
+        b.lanczos(workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    res, st = b.lanczos(max_iter=4, tol=1e-15)
+    assert st == _lib.PDZ_ENOCONV
+    assert all(r["iters"] <= 4 for r in res) and res[-1]["converged"] == 0
+    arr = (ctypes.c_void_p * 1)(None)
+    h = ctypes.c_void_p()
+    assert lib.pdz_batch_create(arr, 1, ctypes.byref(h)) == _lib.PDZ_EINVAL

@@ -25,6 +25,35 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 
 
+KERNEL_NAMES = {"down": "k_hv_down_wide", "up": "k_hv_up / k_hv_up_pre"}
+
+
+def recorded_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None.
+
+    The summary (profiles/hv_traffic_<workload>.txt) holds FETCH_SIZE and
+    WRITE_SIZE per dispatch scaled by a plain copy's reading, and the SHA-1 of
+    the H.v kernel source it was taken with; a changed source gives None.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hv_traffic_{workload}.txt")
+    src = os.path.join(ROOT, "paper_1707_03974_amd", "csrc", "k_hv.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        body = "".join(l for l in f if not l.startswith("#"))
+    try:
+        rec = json.loads(body)
+    except ValueError:
+        return None
+    with open(src, "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()
+    k = rec.get("kernels", {}).get(kernel)
+    if rec.get("source_sha1") != sha or not k:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -99,6 +128,72 @@ def time_to_e0(torch, g, rel=1e-8, max_iter=600):
     return out
 
 
+def _tol_to_rel(run, E_ref, rel, tols=(1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8)):
+    """Loosest residual tolerance whose energies all meet `rel`; returns (tol, seconds, max_rel_err, iters)."""
+    last = None
+    for tol in tols:
+        secs, E, iters = run(tol)
+        err = max(abs(a - b) / abs(b) for a, b in zip(E, E_ref))
+        last = (tol, secs, err, iters)
+        if err <= rel:
+            return last
+    return last
+
+
+def batched_bench(torch, pdz, synth, reps, rel=1e-8):
+    """32 clusters of uneven D: batched H.v and batched Lanczos against 32 single solves."""
+    ws = synth.batched_workloads()
+    probs = [pdz.Problem.from_workload(w) for w in ws]
+    b = pdz.Batch(probs)
+    nnz = sum(q.nnz for q in probs)
+    out = {"clusters": len(ws), "sum_D": sum(q.D for q in probs), "D_min": min(q.D for q in probs),
+           "D_max": max(q.D for q in probs), "nnz_per_batched_hv": nnz}
+    for dn in ("f32", "f64"):
+        # the autotuner times each plan with HIP events around `reps` back-to-back launches in libpdz
+        best, trials = b.tune(dn, reps=reps)
+        ms = min(t["ms"] for t in trials)
+        # the same 32 products as single pdz_hv calls, each with its own tuned plan, timed back to back in libpdz
+        for q in probs:
+            q.tune(dn, reps=3)
+        ms_single = sum(q.kernel_times(dn, reps=reps)["hv"] for q in probs)
+        out["hv_" + dn] = {"ms": ms, "nnz_per_s": nnz / (ms * 1e-3), "plan": best, "plans_timed": len(trials),
+                           "ms_32_single_calls": ms_single, "speedup_vs_single": ms_single / ms}
+    ref, _ = b.lanczos(storage="f64", tol=1e-12, max_iter=800)
+    E_ref = [r["E0"] for r in ref]
+    out["E0_ref_iters_max"] = max(r["iters"] for r in ref)
+
+    def run_batch(storage):
+        def run(tol):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, _ = b.lanczos(storage=storage, tol=tol, max_iter=800)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, [r["E0"] for r in res], max(r["iters"] for r in res)
+        return run
+
+    def run_single(storage):
+        def run(tol):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            E, it = [], 0
+            for i, q in enumerate(probs):
+                r = q.lanczos(storage=storage, tol=tol, max_iter=800, seed=1 + i)
+                E.append(r["E0"])
+                it = max(it, r["iters"])
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, E, it
+        return run
+
+    b.lanczos(storage="f64", tol=1e-6, max_iter=800)   # warm-up (graph instantiation paths)
+    for key, fn in (("batched_f64", run_batch("f64")), ("batched_f32", run_batch("f32")),
+                    ("single_f64", run_single("f64")), ("single_f32", run_single("f32"))):
+        tol, secs, err, iters = _tol_to_rel(fn, E_ref, rel)
+        out["time_to_E0_1e-8_" + key] = {"seconds": secs, "tol": tol, "max_rel_err": err, "max_iters": iters,
+                                         "met": err <= rel}
+        _log(f"batched {key}: {out['time_to_E0_1e-8_' + key]}")
+    return out
+
+
 def cpu_baseline(w, target_s=12.0):
     """The plain-C oracle (binary search, explicit operator algebra) on a bounded row sample."""
     import numpy as np
@@ -160,6 +255,9 @@ def main():
     ap.add_argument("--check-every", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-e0", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 32-cluster batched section and print its JSON object")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of D floats (known bytes) to scale counter readings")
     args = ap.parse_args()
@@ -173,6 +271,9 @@ def main():
     import paper_1707_03974_amd as pdz
 
     torch.cuda.set_device(0)
+    if args.batched_only:
+        print(json.dumps({"batched": batched_bench(torch, pdz, synth, args.hv_reps)}), flush=True)
+        return
     w = synth.workload(args.workload)
     g = pdz.Problem.from_workload(w)
     D, nnz = g.D, g.nnz
@@ -194,10 +295,20 @@ def main():
     ms32 = hv_timing(torch, g, torch.float32, args.hv_reps)
     ms64 = hv_timing(torch, g, torch.float64, args.hv_reps)
     _log(f"hv f32 {ms32:.4f} ms, f64 {ms64:.4f} ms")
+    # whole H.v: x read once, y written once
     bytes32 = 2.0 * D * 4
     bytes64 = 2.0 * D * 8
     ach32 = bytes32 / (ms32 * 1e-3) / 1e9
     ach64 = bytes64 / (ms64 * 1e-3) / 1e9
+    # per kernel (each launched alone, HIP events on its stream inside libpdz):
+    # down pass reads x and writes y (2 D s bytes); up pass reads x, reads y, writes y (3 D s)
+    kt32 = g.kernel_times("f32", reps=args.hv_reps)
+    kt64 = g.kernel_times("f64", reps=args.hv_reps)
+    _log(f"kernel times f32 {kt32}, f64 {kt64}")
+    dom = "up" if kt32["up"] >= kt32["down"] else "down"
+    kbytes = {"down": 2.0 * D * 4, "up": 3.0 * D * 4}
+    ach_dom = kbytes[dom] / (kt32[dom] * 1e-3) / 1e9
+    traffic = recorded_traffic(w.name, dom + "_f32")
 
     copy = None
     if args.calibrate_copy:
@@ -222,6 +333,11 @@ def main():
         tte = time_to_e0(torch, g)
         _log(f"time to E0: {tte}")
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_bench(torch, pdz, synth, args.hv_reps)
+        _log(f"batched: hv f32 {batched['hv_f32']['ms']:.4f} ms, f64 {batched['hv_f64']['ms']:.4f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -244,15 +360,21 @@ def main():
         "config": {"workload": w.name, "lattice": "4x4 periodic, NN t=1 + NNN t'=-0.3" if w.name == "torus4x4_nnn"
                    else w.note, "U": w.U, "n_up": w.n_up, "n_dn": w.n_dn, "D": D, "nnz_per_hv": nnz,
                    "storage": "f32", "step": "one Lanczos step (H.v + recurrence + tridiagonal solve)"},
-        "roofline": {"bound": "hbm", "achieved": ach32, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": ach32 / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "k_hv_table<float,true>", "avg_ms": ms32,
-                     "algorithmic_bytes": bytes32},
+        "roofline": {"bound": "hbm", "achieved": ach_dom, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": ach_dom / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": f"{dom} pass of H.v, FP32 ({KERNEL_NAMES[dom]}, plan {tuned['f32']['best']})",
+                     "avg_ms": kt32[dom], "algorithmic_bytes": kbytes[dom],
+                     "other_kernel": {"name": "up" if dom == "down" else "down",
+                                      "avg_ms": kt32["up" if dom == "down" else "down"]},
+                     "whole_hv": {"ms": ms32, "algorithmic_bytes": bytes32, "achieved": ach32,
+                                  "frac": ach32 / PEAK_HBM_GBS}},
         "fp64": {"value": nnz * args.steps / t64, "ms_per_step": t64 / args.steps * 1e3,
                  "hv_ms": ms64, "hv_achieved_GBs": ach64, "hv_frac": ach64 / PEAK_HBM_GBS,
+                 "kernel_ms": kt64,
                  "hv_nnz_per_s": nnz / (ms64 * 1e-3)},
         "hv_nnz_per_s_f32": nnz / (ms32 * 1e-3),
         "time_to_E0_1e-8": tte,
+        "batched": batched,
         "copy_calibration": copy,
         "hv_plans": tuned,
         "cpu_baseline": cpu,

@@ -170,6 +170,17 @@ pdz_status pdz_hv_set_plan(pdz_problem p, pdz_dtype dt, const pdz_hv_plan* plan)
 pdz_status pdz_hv_tune(pdz_problem p, pdz_dtype dt, const void* x, void* y, int32_t reps, pdz_hv_trial* trials,
                        int32_t max_trials, int32_t* n_trials, pdz_hv_plan* best, void* stream);
 
+/* Per-kernel profile of pdz_hv: after one warm-up, `reps` products y = H x
+ * with a HIP event on `stream` before, between and after its two kernels,
+ * then `reps` products back to back.  ms[0]: mean duration of the down pass
+ * (diagonal and down-spin hops, writes y); ms[1]: of the up pass (up-spin
+ * hops added onto y; 0 when the up sector has no hops); ms[2]: of one whole
+ * pdz_hv in the back-to-back run.  A problem on the on-the-fly path has one
+ * kernel: ms[0] is its duration, ms[1] = 0.  x, y as in pdz_hv (y = H x on
+ * return).  reps in [1, 1000].  Synchronous.  Errors: PDZ_EINVAL. */
+pdz_status pdz_hv_kernel_times(pdz_problem p, pdz_dtype dt, const void* x, void* y, int32_t reps, double* ms,
+                               void* stream);
+
 /* ---------------------------------------------------------------- Lanczos */
 
 typedef struct {

@@ -120,6 +120,17 @@ class Problem:
                 "map": trials[k].plan.map, "ms": trials[k].ms} for k in range(n.value)]
         return {"down": best.down, "up_cw": best.up_cw, "up": best.up, "map": best.map}, out
 
+    def kernel_times(self, dtype, reps=10, stream=None):
+        """Mean ms of each H.v kernel launched alone: {"down", "up", "hv"} (HIP events in libpdz)."""
+        import torch
+        tdt = torch.float64 if _dtype_code(dtype) == PDZ_F64 else torch.float32
+        x = torch.empty(self.D, dtype=tdt, device="cuda").uniform_(-1.0, 1.0)
+        y = torch.empty_like(x)
+        ms = (ctypes.c_double * 3)()
+        _lib.check(lib().pdz_hv_kernel_times(self._h, _dtype_code(dtype), ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(y.data_ptr()), int(reps), ms, _stream_handle(stream)))
+        return {"down": ms[0], "up": ms[1], "hv": ms[2]}
+
     def lanczos_opts(self, **kw):
         o = LanczosOpts()
         _lib.check(lib().pdz_lanczos_default_opts(ctypes.byref(o)))

@@ -87,6 +87,8 @@ _SIGNATURES = {
     "pdz_hv_set_plan": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(HvPlan)]),
     "pdz_hv_tune": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(HvTrial),
                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(HvPlan), _P]),
+    "pdz_hv_kernel_times": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_double), _P]),
     "pdz_lanczos_default_opts": (ctypes.c_int32, [ctypes.POINTER(LanczosOpts)]),
     "pdz_lanczos_workspace_size": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), ctypes.POINTER(ctypes.c_size_t)]),
     "pdz_lanczos": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, _P, ctypes.c_size_t, _P,

@@ -69,7 +69,7 @@ struct BCtl {                      // per-cluster Lanczos state
     double theta;
     double resid;
     double norm0;
-    double pad;
+    double theta_prev;   // Ritz value of the step before
 };
 
 __global__ void k_clear_bits1(uint32_t* w, uint32_t bits) {
@@ -259,14 +259,13 @@ __global__ void k_binit(BCtl* ctl, double* beta, int ld, uint32_t n) {
     c.theta = 0.0;
     c.resid = 0.0;
     c.norm0 = 0.0;
-    c.pad = 0.0;
+    c.theta_prev = 0.0;
     ctl[p] = c;
     beta[(size_t)p * ld] = 0.0;
 }
 
 // One block per cluster: lowest eigenpair of its T_k, convergence test, step
-// counter.  svec rows hold the eigenvector (first k slots) and the pivots of
-// the inverse iteration (next k slots).
+// counter.  Row p of svec receives the eigenvector.
 __global__ __launch_bounds__(kRed) void k_btridiag(BCtl* ctl, const double* alpha, const double* beta, double* svec,
                                                    int ld, double tol, int max_iter, uint32_t* err) {
     const uint32_t p = blockIdx.x;
@@ -274,6 +273,8 @@ __global__ __launch_bounds__(kRed) void k_btridiag(BCtl* ctl, const double* alph
     if (st->done) return;
     __shared__ double a[kBatchMaxIter];
     __shared__ double e[kBatchMaxIter];
+    __shared__ double zs[kBatchMaxIter];
+    __shared__ double rp[kBatchMaxIter];
     __shared__ double lo_s[kRed], hi_s[kRed];
     __shared__ int found;
     __shared__ double bounds[2];
@@ -285,13 +286,18 @@ __global__ __launch_bounds__(kRed) void k_btridiag(BCtl* ctl, const double* alph
         e[i] = (i == 0) ? 0.0 : be[i];
     }
     __syncthreads();
-    tridiag_bracket_min(a, e, k, lo_s, hi_s, &found, bounds);
+    double hint_lo = 0.0, hint_hi = 0.0;
+    if (k >= 3) ritz_hint(st->theta, st->theta_prev, &hint_lo, &hint_hi);
+    tridiag_bracket_min(a, e, k, lo_s, hi_s, &found, bounds, hint_lo, hint_hi);
+    if (threadIdx.x == 0) tridiag_min_vector(a, e, k, bounds[0], zs, rp);
+    __syncthreads();
+    double* z = svec + (size_t)p * ld;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) z[i] = zs[i];
     if (threadIdx.x == 0) {
         const double theta = 0.5 * (bounds[0] + bounds[1]);
-        double* z = svec + (size_t)p * ld;
-        tridiag_min_vector(a, e, k, bounds[0], z, z + k);
         const double bk1 = be[k];
-        const double resid = fabs(bk1 * z[k - 1]);
+        const double resid = fabs(bk1 * zs[k - 1]);
+        st->theta_prev = st->theta;
         st->theta = theta;
         st->resid = resid;
         st->k = k;

@@ -613,7 +613,7 @@ HvPlan hv_resolve(const pdz_problem_s* p, pdz_dtype dt) {
 
 template <typename T, typename E>
 pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coef, const T* x, T* y, hipStream_t s,
-                      const int* skip, bool compact) {
+                      const int* skip, bool compact, unsigned passes) {
     const uint64_t D_up = p->up.D, D_dn = p->dn.D;
     const int ncoef = (int)p->coef_host.size();
     // ---- down pass
@@ -632,7 +632,9 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     const size_t row_bytes = (size_t)D_dn * sizeof(T);
     const unsigned cu = (unsigned)ctx->cu_count;
     const HvPlan plan = hv_resolve(p, sizeof(T) == 8 ? PDZ_F64 : PDZ_F32);
-    if (D_dn >= (uint64_t)kWideBlock && row_bytes <= lds_cap) {
+    if (!(passes & kPassDown)) {
+        // up pass only
+    } else if (D_dn >= (uint64_t)kWideBlock && row_bytes <= lds_cap) {
         const bool two = plan.down == 3;
         da.rows = two ? 2 : 1;
         const size_t lds = kMaxCoef * sizeof(T) + (size_t)da.rows * row_bytes;
@@ -665,7 +667,7 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
                                x, y);
     }
     PDZ_HIP(hipGetLastError());
-    if (p->up.max_hops == 0) return ok();
+    if (p->up.max_hops == 0 || !(passes & kPassUp)) return ok();
     // ---- up pass
     UpArgs<T, E> ua;
     ua.D_up = D_up;
@@ -722,14 +724,15 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
 }
 
 template <typename T>
-pdz_status run_hv(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipStream_t s, const int* skip) {
+pdz_status run_hv(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipStream_t s, const int* skip,
+                  unsigned passes) {
     DeviceCtx* ctx = nullptr;
     pdz_status st = device_ctx(&ctx);
     if (st != PDZ_OK) return st;
     if (p->hv_path == 0) {
         const bool compact = p->up.tbits16 > 0 && p->dn.tbits16 > 0;
-        if (compact) return run_tables<T, uint16_t>(p, ctx, coef, x, y, s, skip, true);
-        return run_tables<T, uint32_t>(p, ctx, coef, x, y, s, skip, false);
+        if (compact) return run_tables<T, uint16_t>(p, ctx, coef, x, y, s, skip, true, passes);
+        return run_tables<T, uint32_t>(p, ctx, coef, x, y, s, skip, false, passes);
     }
     FlyArgs f;
     f.N = p->N;
@@ -844,10 +847,11 @@ bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan) {
 }
 
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
-                     const int* skip) {
+                     const int* skip, unsigned passes) {
     if (dt == PDZ_F64)
-        return run_hv<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip);
-    return run_hv<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip);
+        return run_hv<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip,
+                              passes);
+    return run_hv<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip, passes);
 }
 
 }  // namespace pdz

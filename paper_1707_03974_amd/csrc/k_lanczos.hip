@@ -236,6 +236,8 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiag(const double* alpha, cons
     if (ctl->done) return;
     __shared__ double a[kMaxIter];
     __shared__ double e[kMaxIter];
+    __shared__ double zs[kMaxIter];
+    __shared__ double rp[kMaxIter];
     __shared__ double lo_s[kRedBlock], hi_s[kRedBlock];
     __shared__ int found;
     __shared__ double bounds[2];
@@ -245,13 +247,16 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiag(const double* alpha, cons
         e[i] = (i == 0) ? 0.0 : beta[i];
     }
     __syncthreads();
-    tridiag_bracket_min(a, e, k, lo_s, hi_s, &found, bounds);
+    double hint_lo = 0.0, hint_hi = 0.0;
+    if (k >= 3) ritz_hint(theta_hist[k - 2], theta_hist[k - 3], &hint_lo, &hint_hi);
+    tridiag_bracket_min(a, e, k, lo_s, hi_s, &found, bounds, hint_lo, hint_hi);
+    if (threadIdx.x == 0) tridiag_min_vector(a, e, k, bounds[0], zs, rp);
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += blockDim.x) s_out[i] = zs[i];
     if (threadIdx.x == 0) {
         const double theta = 0.5 * (bounds[0] + bounds[1]);
-        double* z = s_out;
-        tridiag_min_vector(a, e, k, bounds[0], z, theta_hist + max_iter);   // pivots in the history tail
         const double bk1 = beta[k];
-        const double resid = fabs(bk1 * z[k - 1]);
+        const double resid = fabs(bk1 * zs[k - 1]);
         theta_hist[k - 1] = theta;
         ctl->theta = theta;
         ctl->resid = resid;

@@ -124,7 +124,10 @@ pdz_status batch_prepare();   // the same for the batched H.v kernels
 // Candidate plans valid for this problem and precision; the first is the default.
 std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt);
 bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan);
+// passes: kPassDown | kPassUp for y = H x; one bit alone launches only that
+// pass of the table path (the up pass then adds onto y).
+constexpr unsigned kPassDown = 1u, kPassUp = 2u;
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
-                     const int* skip = nullptr);
+                     const int* skip = nullptr, unsigned passes = kPassDown | kPassUp);
 
 }  // namespace pdz

@@ -114,4 +114,70 @@ pdz_status pdz_hv_tune(pdz_problem p, pdz_dtype dt, const void* x, void* y, int3
     return ok();
 }
 
+pdz_status pdz_hv_kernel_times(pdz_problem p, pdz_dtype dt, const void* x, void* y, int32_t reps, double* ms,
+                               void* stream) {
+    pdz_status st = check_dt(p, dt);
+    if (st != PDZ_OK) return st;
+    if (!x || !y || !ms) return fail(PDZ_EINVAL, "NULL argument");
+    if (reps < 1 || reps > 1000) return fail(PDZ_EINVAL, "reps must be in [1, 1000]");
+    hipStream_t s = (hipStream_t)stream;
+    ms[0] = ms[1] = ms[2] = 0.0;
+    // ev[3r], ev[3r+1], ev[3r+2] bracket the down and the up launch of H.v number r
+    std::vector<hipEvent_t> ev(3 * (size_t)reps + 2, nullptr);
+    for (auto& e : ev) {
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) {
+            st = hip_fail(he, "hipEventCreate");
+            break;
+        }
+    }
+    const bool two = p->hv_path == 0;
+    if (st == PDZ_OK) st = launch_hv(p, dt, x, y, s);   // warm-up
+    for (int r = 0; r < reps && st == PDZ_OK; ++r) {
+        hipError_t he = hipEventRecord(ev[3 * r], s);
+        if (two) {
+            if (he == hipSuccess) st = launch_hv(p, dt, x, y, s, nullptr, kPassDown);
+            if (st == PDZ_OK && he == hipSuccess) he = hipEventRecord(ev[3 * r + 1], s);
+            if (st == PDZ_OK && he == hipSuccess) st = launch_hv(p, dt, x, y, s, nullptr, kPassUp);
+        } else {
+            if (he == hipSuccess) st = launch_hv(p, dt, x, y, s);
+            if (st == PDZ_OK && he == hipSuccess) he = hipEventRecord(ev[3 * r + 1], s);
+        }
+        if (st == PDZ_OK && he == hipSuccess) he = hipEventRecord(ev[3 * r + 2], s);
+        if (he != hipSuccess && st == PDZ_OK) st = hip_fail(he, "hipEventRecord");
+    }
+    // whole H.v, back to back
+    const size_t w0 = 3 * (size_t)reps, w1 = w0 + 1;
+    if (st == PDZ_OK) {
+        hipError_t he = hipEventRecord(ev[w0], s);
+        for (int r = 0; r < reps && st == PDZ_OK && he == hipSuccess; ++r) st = launch_hv(p, dt, x, y, s);
+        if (st == PDZ_OK && he == hipSuccess) he = hipEventRecord(ev[w1], s);
+        if (he == hipSuccess) he = hipEventSynchronize(ev[w1]);
+        if (he != hipSuccess && st == PDZ_OK) st = hip_fail(he, "kernel timing");
+    }
+    if (st == PDZ_OK) {
+        double sd = 0.0, su = 0.0;
+        float t = 0.f;
+        for (int r = 0; r < reps && st == PDZ_OK; ++r) {
+            hipError_t he = hipEventElapsedTime(&t, ev[3 * r], ev[3 * r + 1]);
+            sd += t;
+            if (he == hipSuccess) he = hipEventElapsedTime(&t, ev[3 * r + 1], ev[3 * r + 2]);
+            su += t;
+            if (he != hipSuccess) st = hip_fail(he, "hipEventElapsedTime");
+        }
+        if (st == PDZ_OK) {
+            hipError_t he = hipEventElapsedTime(&t, ev[w0], ev[w1]);
+            if (he != hipSuccess) st = hip_fail(he, "hipEventElapsedTime");
+        }
+        if (st == PDZ_OK) {
+            ms[0] = sd / reps;
+            ms[1] = two ? su / reps : 0.0;
+            ms[2] = (double)t / reps;
+        }
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
+}
+
 }  // extern "C"

@@ -27,11 +27,62 @@ __device__ inline int tridiag_sturm_count(const double* a, const double* e, int 
     return cnt;
 }
 
+// Whole work group: shrink [bounds[0], bounds[1]], which holds lambda_min,
+// by splitting it into blockDim + 1 pieces per round.
+__device__ inline void tridiag_multisect(const double* a, const double* e, int k, int* found, double* bounds) {
+    double lo, hi;
+    for (int round = 0; round < 64; ++round) {
+        lo = bounds[0];
+        hi = bounds[1];
+        if (!(hi - lo > 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
+        const double x = lo + (hi - lo) * (double)(threadIdx.x + 1) / (double)(blockDim.x + 1);
+        if (threadIdx.x == 0) *found = blockDim.x;
+        __syncthreads();
+        if (tridiag_sturm_count(a, e, k, x) >= 1) atomicMin(found, (int)threadIdx.x);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int t = *found;
+            const double nlo = (t == 0) ? lo : lo + (hi - lo) * (double)t / (double)(blockDim.x + 1);
+            const double nhi = (t == (int)blockDim.x) ? hi : lo + (hi - lo) * (double)(t + 1) / (double)(blockDim.x + 1);
+            bounds[0] = nlo;
+            bounds[1] = nhi;
+        }
+        __syncthreads();
+    }
+}
+
 // Whole work group: bracket [bounds[0], bounds[1]] of lambda_min(T_k) to a
 // few ulps.  a, e in LDS; lo_s, hi_s: blockDim doubles of LDS; found, bounds
 // in LDS.  Every thread must call it; bounds is valid for all on return.
+// A hint [hint_lo, hint_hi] (hint_lo < hint_hi) replaces the Gershgorin
+// interval when two Sturm counts confirm that it holds exactly the lowest
+// eigenvalue's side: none below hint_lo, at least one below hint_hi.  In
+// Lanczos the previous Ritz value bounds the new one from above (Cauchy
+// interlacing), and the last change estimates how far it moves.
 __device__ inline void tridiag_bracket_min(const double* a, const double* e, int k, double* lo_s, double* hi_s,
-                                           int* found, double* bounds) {
+                                           int* found, double* bounds, double hint_lo = 0.0,
+                                           double hint_hi = 0.0) {
+    if (hint_lo < hint_hi) {
+        if (threadIdx.x == 0) *found = 0;
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            const int c = tridiag_sturm_count(a, e, k, threadIdx.x == 0 ? hint_lo : hint_hi);
+            const bool good = threadIdx.x == 0 ? (c == 0) : (c >= 1);
+            if (good) atomicAdd(found, 1);
+        }
+        __syncthreads();
+        const bool use = *found == 2;
+        __syncthreads();
+        if (use) {
+            if (threadIdx.x == 0) {
+                bounds[0] = hint_lo;
+                bounds[1] = hint_hi;
+            }
+            __syncthreads();
+            tridiag_multisect(a, e, k, found, bounds);
+            return;
+        }
+    }
     double lo = 1e300, hi = -1e300;
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
         const double r = fabs(e[i]) + (i + 1 < k ? fabs(e[i + 1]) : 0.0);
@@ -54,51 +105,59 @@ __device__ inline void tridiag_bracket_min(const double* a, const double* e, int
         bounds[1] = hi_s[0] + pad;
     }
     __syncthreads();
-    for (int round = 0; round < 64; ++round) {
-        lo = bounds[0];
-        hi = bounds[1];
-        if (!(hi - lo > 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
-        const double x = lo + (hi - lo) * (double)(threadIdx.x + 1) / (double)(blockDim.x + 1);
-        if (threadIdx.x == 0) *found = blockDim.x;
-        __syncthreads();
-        if (tridiag_sturm_count(a, e, k, x) >= 1) atomicMin(found, (int)threadIdx.x);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int t = *found;
-            const double nlo = (t == 0) ? lo : lo + (hi - lo) * (double)t / (double)(blockDim.x + 1);
-            const double nhi = (t == (int)blockDim.x) ? hi : lo + (hi - lo) * (double)(t + 1) / (double)(blockDim.x + 1);
-            bounds[0] = nlo;
-            bounds[1] = nhi;
-        }
-        __syncthreads();
-    }
+    tridiag_multisect(a, e, k, found, bounds);
+}
+
+// Bracket hint for lambda_min(T_k) from the Ritz values of the two previous
+// steps: the new value lies below theta1 (interlacing; the pad covers the
+// rounding of theta1) and, once the iteration settles, within a few times the
+// last change of it.
+__device__ inline void ritz_hint(double theta1, double theta2, double* lo, double* hi) {
+    const double scale = fmax(1.0, fabs(theta1));
+    const double w = fmax(8.0 * fabs(theta1 - theta2), 1e-12 * scale);
+    *hi = theta1 + 8.0 * 2.220446049250313e-16 * scale;
+    *lo = theta1 - w;
 }
 
 // One thread: normalised eigenvector z[0..k-1] for the eigenvalue bracketed
-// below by `lower`, by three steps of inverse iteration; dpiv holds k pivots.
+// below by `lower`.  T - sigma I = L D L^T is factored once (reciprocal
+// pivots in rp), then three steps of inverse iteration reuse it.  a, e, z, rp
+// should live in LDS: the sweeps are serial recurrences, so only the carried
+// value stays on the critical path.
 __device__ inline void tridiag_min_vector(const double* a, const double* e, int k, double lower, double* z,
-                                          double* dpiv) {
+                                          double* rp) {
     const double sigma = lower - 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(lower));
-    for (int i = 0; i < k; ++i) z[i] = 1.0;
+    double d = a[0] - sigma;
+    if (d == 0.0) d = 1e-300;
+    double r = 1.0 / d;
+    rp[0] = r;
+    z[0] = 1.0;
+    for (int i = 1; i < k; ++i) {
+        d = (a[i] - sigma) - (e[i] * r) * e[i];
+        if (d == 0.0) d = 1e-300;
+        r = 1.0 / d;
+        rp[i] = r;
+        z[i] = 1.0;
+    }
     for (int it = 0; it < 3; ++it) {
-        // (T - sigma I) = L D L^T: forward solve with L, then D, then L^T
-        double d0 = a[0] - sigma;
-        if (d0 == 0.0) d0 = 1e-300;
-        dpiv[0] = d0;
+        // L y = z (forward), then D L^T x = y (backward); x overwrites z
+        double c = z[0];
         for (int i = 1; i < k; ++i) {
-            const double l = e[i] / dpiv[i - 1];
-            double di = (a[i] - sigma) - l * e[i];
-            if (di == 0.0) di = 1e-300;
-            dpiv[i] = di;
-            z[i] -= l * z[i - 1];
+            c = z[i] - (e[i] * rp[i - 1]) * c;
+            z[i] = c;
         }
-        z[k - 1] /= dpiv[k - 1];
-        for (int i = k - 2; i >= 0; --i) z[i] = z[i] / dpiv[i] - (e[i + 1] / dpiv[i]) * z[i + 1];
-        double nrm = 0.0;
-        for (int i = 0; i < k; ++i) nrm += z[i] * z[i];
+        c = z[k - 1] * rp[k - 1];
+        z[k - 1] = c;
+        double nrm = c * c;
+        for (int i = k - 2; i >= 0; --i) {
+            c = rp[i] * (z[i] - e[i + 1] * c);
+            z[i] = c;
+            nrm += c * c;
+        }
         nrm = sqrt(nrm);
         if (!(nrm > 0.0) || !isfinite(nrm)) break;
-        for (int i = 0; i < k; ++i) z[i] /= nrm;
+        const double inv = 1.0 / nrm;
+        for (int i = 0; i < k; ++i) z[i] *= inv;
     }
 }
 

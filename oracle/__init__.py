@@ -26,5 +26,6 @@ from .hamiltonian import (Problem, build_csr, hv_rows, diag_values, nnz_structur
                           one_body_matrix)
 from .lanczos import lanczos, LanczosResult
 from .splitmix import splitmix64_mix, splitmix64_outputs, start_vector
+from . import mlp
 
 __all__ = [n for n in dir() if not n.startswith("_")]

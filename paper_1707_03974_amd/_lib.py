@@ -108,6 +108,21 @@ _SIGNATURES = {
                                                           ctypes.POINTER(ctypes.c_size_t)]),
     "pdz_batch_lanczos": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t,
                                            ctypes.POINTER(LanczosResult), _P]),
+    "pdz_mlp_param_count": (ctypes.c_int32, []),
+    "pdz_mlp_init": (ctypes.c_int32, [_P, _P, ctypes.c_uint64]),
+    "pdz_mlp_to_bf16": (ctypes.c_int32, [_P, _P, _P]),
+    "pdz_mlp_forward": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P, _P, _P]),
+    "pdz_mlp_workspace_size": (ctypes.c_int32, [ctypes.c_uint64, ctypes.POINTER(ctypes.c_size_t)]),
+    "pdz_mlp_loss": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pdz_mlp_backward": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pdz_adam_step": (ctypes.c_int32, [_P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]),
+    "pdz_sampler_workspace_size": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "pdz_sampler_prepare": (ctypes.c_int32, [_P, _P, _P, ctypes.c_size_t, _P]),
+    "pdz_sample": (ctypes.c_int32, [_P, _P, _P, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_double, _P, _P, _P, _P]),
+    "pdz_start_vector": (ctypes.c_int32, [_P, _P, ctypes.c_int32, _P, _P]),
+    "pdz_dot": (ctypes.c_int32, [ctypes.c_int32, _P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), _P]),
     "pdz_last_error": (ctypes.c_char_p, []),
     "pdz_version": (ctypes.c_int32, []),
 }

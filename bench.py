@@ -194,6 +194,49 @@ def batched_bench(torch, pdz, synth, reps, rel=1e-8):
     return out
 
 
+def learned_bench(torch, pdz, synth, steps=3000):
+    """Learned start on the 4x4 cluster with 7 + 7 electrons at U = 5 against random starts (time to E0 at 1e-8)."""
+    import statistics
+    from paper_1707_03974_amd import learned, mlp
+    w = synth.workload("torus4x4_n7")
+    bonds = w.bonds
+
+    def make(U):
+        return pdz.Problem(w.n_sites, bonds, U, w.n_up, w.n_dn)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    states = learned.ground_states(make, [2.0, 3.0, 4.0, 6.0, 7.0, 8.0], 4.0, tol=1e-10)
+    torch.cuda.synchronize()
+    t_gs = time.perf_counter() - t0
+    net, losses, t_train = learned.train(states, 4.0, steps=steps, batch=4096, lr=2e-3)
+    del states
+    p = make(w.U)
+    ref = p.lanczos(tol=1e-12, max_iter=800)
+    E_ref = ref["E0"]
+    res, v0 = learned.compare(p, net, E_ref, seeds=(1, 2, 3, 4, 5))
+    y = torch.empty(p.D, dtype=torch.float64, device="cuda")
+    p.lanczos(ritz=y, tol=1e-10, max_iter=800)
+    ov = abs(mlp.dot(v0, y)) / mlp.dot(v0, v0) ** 0.5
+    rv = torch.empty(p.D, dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0)
+    ov_r = abs(mlp.dot(rv, y)) / mlp.dot(rv, rv) ** 0.5
+    rnd_t = [r["solve_s"] for r in res["random"] if "solve_s" in r]
+    rnd_k = [r["iters"] for r in res["random"] if r["iters"] is not None]
+    out = {"workload": w.name, "D": p.D, "U": w.U, "train_U": [2, 3, 4, 6, 7, 8], "E0_ref": E_ref,
+           "ground_states_s": t_gs, "train_steps": steps, "train_batch": 4096, "train_s": t_train,
+           "loss_first_last": [losses[0][1], losses[-1][1]], "overlap_learned": ov, "overlap_random": ov_r,
+           "compare": res}
+    if rnd_t and "total_s" in res["learned"]:
+        med = statistics.median(rnd_t)
+        out["random_median_iters"] = statistics.median(rnd_k)
+        out["random_median_s"] = med
+        out["learned_speedup"] = med / res["learned"]["total_s"]
+        gain = med - res["learned"]["total_s"]
+        out["break_even_solves"] = (t_gs + t_train) / gain if gain > 0 else None
+    del y, rv, v0
+    return out
+
+
 def cpu_baseline(w, target_s=12.0):
     """The plain-C oracle (binary search, explicit operator algebra) on a bounded row sample."""
     import numpy as np
@@ -256,6 +299,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-e0", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 32-cluster batched section and print its JSON object")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -338,6 +382,11 @@ def main():
         batched = batched_bench(torch, pdz, synth, args.hv_reps)
         _log(f"batched: hv f32 {batched['hv_f32']['ms']:.4f} ms, f64 {batched['hv_f64']['ms']:.4f} ms")
 
+    learned_res = None
+    if not args.no_learned:
+        learned_res = learned_bench(torch, pdz, synth)
+        _log(f"learned start: {json.dumps({k: v for k, v in learned_res.items() if k != 'compare'})}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -375,6 +424,7 @@ def main():
         "hv_nnz_per_s_f32": nnz / (ms32 * 1e-3),
         "time_to_E0_1e-8": tte,
         "batched": batched,
+        "learned_start": learned_res,
         "copy_calibration": copy,
         "hv_plans": tuned,
         "cpu_baseline": cpu,

@@ -312,6 +312,89 @@ pdz_status pdz_batch_lanczos_workspace_size(pdz_batch b, const pdz_lanczos_opts*
 pdz_status pdz_batch_lanczos(pdz_batch b, const pdz_lanczos_opts* o, void* ws, size_t ws_bytes,
                              pdz_lanczos_result* results, void* stream);
 
+/* ----------------------------------------------------------- learned start */
+
+/* A small network proposes the Lanczos start vector; nothing of the paper's
+ * method is learned, and a seeded random start (pdz_lanczos with v0 = NULL)
+ * stays the fallback.  Network: 32 inputs x_i = 2 n_i - 1 (n_i the up
+ * occupation of site i for i < 16, the down occupation of site i - 16
+ * otherwise), two tanh layers of 128 units, 2 linear outputs: o_0 = ln|psi|,
+ * o_1 = logit of P(psi > 0).  Parameters: one vector of pdz_mlp_param_count()
+ * = 20,994 values in the order W1 (128 x 32, row = unit), b1 (128), W2
+ * (128 x 128), b2 (128), W3 (2 x 128), b3 (2).  The caller owns an FP32
+ * master copy and a BF16 copy (uint16 bit patterns, round to nearest even)
+ * of it; the kernels read the BF16 copy and multiply on the BF16 matrix cores
+ * with FP32 accumulation.  Occupations are passed as pairs of uint32 (up
+ * bits, down bits), n pairs for n states. */
+int32_t pdz_mlp_param_count(void);
+
+/* Initialise params (device, FP32) and params_bf16 (device): weights uniform
+ * in +-1/sqrt(fan_in) from SplitMix64(seed) output k for parameter k, biases
+ * zero.  Synchronous.  Errors: PDZ_EINVAL. */
+pdz_status pdz_mlp_init(float* params, uint16_t* params_bf16, uint64_t seed);
+
+/* params_bf16 = BF16 rounding of params.  Asynchronous. */
+pdz_status pdz_mlp_to_bf16(const float* params, uint16_t* params_bf16, void* stream);
+
+/* out (n x 2 FP32, device) = network outputs for the n states in occ.  act:
+ * NULL, or 768 n bytes (16-byte aligned) that receive the BF16 activations a
+ * training step needs: h1 (n x 128), h1 transposed (128 x n), h2 (n x 128).
+ * Asynchronous.  Errors: PDZ_EINVAL. */
+pdz_status pdz_mlp_forward(const uint16_t* params_bf16, const uint32_t* occ, uint64_t n, float* out, void* act,
+                           void* stream);
+
+/* Bytes of device workspace pdz_mlp_loss and pdz_mlp_backward need for a batch of n. */
+pdz_status pdz_mlp_workspace_size(uint64_t n, size_t* bytes);
+
+/* Loss of a batch: target (n x 2 FP32) holds ln|psi| and the sign (+1/-1) of
+ * each state; loss = (1/n) sum (o_0 - ln|psi|)^2 + softplus(o_1) - y o_1 with
+ * y = 1 for a positive sign.  dout (n x 2) receives d loss / d out; *loss (one
+ * device double) the loss.  Asynchronous.  Errors: PDZ_EINVAL. */
+pdz_status pdz_mlp_loss(const float* out, const float* target, uint64_t n, float* dout, double* loss, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* grad (20,994 FP32, device) = d(sum dout . out)/d params for the batch whose
+ * forward pass stored `act`.  n a multiple of 32, at most 2^24.  ws: 256-byte
+ * aligned, pdz_mlp_workspace_size(n) bytes.  Products on the matrix cores;
+ * per-slice partial sums reduced in a fixed order (deterministic).
+ * Asynchronous.  Errors: PDZ_EINVAL, PDZ_ERANGE. */
+pdz_status pdz_mlp_backward(const uint16_t* params_bf16, const uint32_t* occ, uint64_t n, const void* act,
+                            const float* dout, float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma and Ba 2015, Algorithm 1; step counts from 1) on
+ * `count` FP32 parameters with moments m, v; refreshes params_bf16.
+ * Asynchronous.  Errors: PDZ_EINVAL (step < 1, betas outside [0, 1)). */
+pdz_status pdz_adam_step(float* params, uint16_t* params_bf16, const float* grad, float* m, float* v, uint64_t count,
+                         float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* Bytes of device workspace of the |psi|^2 sampler of problem p (8 D + small). */
+pdz_status pdz_sampler_workspace_size(pdz_problem p, size_t* bytes);
+
+/* Prepare sampling from psi (D doubles, device, not all zero): integer weights
+ * w_r = floor(2^32 psi_r^2 / max psi^2) and their inclusive prefix sums,
+ * exact in any order.  Asynchronous. */
+pdz_status pdz_sampler_prepare(pdz_problem p, const double* psi, void* ws, size_t ws_bytes, void* stream);
+
+/* Draw `count` states with probability w_r / sum w: draw j takes SplitMix64
+ * output first + j of `seed`, scales it to t = floor(z W / 2^64) and returns
+ * the first r whose prefix sum exceeds t.  occ (count pairs) receives the
+ * occupations, target (count x 2 FP32) ln|psi_r| and the sign of gauge *
+ * psi_r (gauge = +1 or -1), idx (NULL or count uint32) the indices r.
+ * Asynchronous.  Errors: PDZ_EINVAL. */
+pdz_status pdz_sample(pdz_problem p, const double* psi, const void* ws, size_t ws_bytes, uint64_t seed, uint64_t first,
+                      uint64_t count, double gauge, uint32_t* occ, float* target, uint32_t* idx, void* stream);
+
+/* Learned start vector over the whole basis of p: v0[r] = s exp(min(o_0, 60))
+ * with s = +1 if o_1 >= 0 else -1, for the state of index r (backward maps of
+ * Sec. III on both spins).  v0: D elements of precision dt (device).  The
+ * vector is not normalised (pdz_lanczos normalises its start vector).  N <= 16.
+ * Asynchronous.  Errors: PDZ_EINVAL, PDZ_ERANGE (N > 16). */
+pdz_status pdz_start_vector(pdz_problem p, const uint16_t* params_bf16, pdz_dtype dt, void* v0, void* stream);
+
+/* *result = sum a_i b_i over n device elements of precision dt, products and
+ * sums in FP64.  Synchronous.  Errors: PDZ_EINVAL. */
+pdz_status pdz_dot(pdz_dtype dt, const void* a, const void* b, uint64_t n, double* result, void* stream);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Message of the last failing call on this thread ("" if none).  Valid until

@@ -139,7 +139,7 @@ pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* str
  *       loaded before the first multiply-add (up_cw <= 64);
  * map: order of the up-pass tiles: 1 each XCD walks a pair of neighbouring
  *       column chunks at a time (blocks are dealt to XCDs round robin),
- *       2 chunk-major over all blocks.
+ *       2 chunk-major over all blocks, 3 each XCD walks one chunk at a time.
  * Every plan computes the same y bit for bit. */
 typedef struct {
     int32_t down;

@@ -264,7 +264,8 @@ __global__ __launch_bounds__(kNarrowBlock) void k_hv_down_narrow(const DownArgs<
 // Block -> (column chunk, row tile).  map 1: blocks are dealt to the XCDs
 // round robin (block b on XCD b % 8), so each XCD walks a pair of
 // neighbouring chunks at a time through every row tile and keeps their slab
-// in its L2; map 2: chunk-major order over all blocks.
+// in its L2; map 2: chunk-major order over all blocks; map 3: like map 1 with
+// one chunk per XCD at a time (half the slab held in L2).
 __device__ __forceinline__ void up_tile(uint32_t b, uint32_t rt, int map, uint32_t* chunk, uint32_t* tile) {
     if (map == 2) {
         *chunk = b / rt;
@@ -272,6 +273,12 @@ __device__ __forceinline__ void up_tile(uint32_t b, uint32_t rt, int map, uint32
         return;
     }
     constexpr int kXcd = 8;
+    if (map == 3) {
+        const uint32_t j = b / kXcd;
+        *tile = j % rt;
+        *chunk = (b % kXcd) + kXcd * (j / rt);
+        return;
+    }
     const uint32_t xcd = b % kXcd;
     const uint32_t j = b / kXcd;
     const uint32_t pair = j / (2 * rt);
@@ -548,8 +555,11 @@ pdz_status set_wide_lds() {
 // Up-pass geometry: the x[:, chunk] slab one XCD streams over is
 // D_up * CW * sizeof(T) bytes; narrower chunks stay in L2, wider ones issue
 // fewer, longer requests.  The plan (autotuned or default) picks CW.
+// Rows per tile: small tiles keep the rows in flight on one XCD to a small
+// part of the chunk, so that the XCD's work groups stay on one column chunk
+// at a time and its slab stays in that XCD's L2.
 template <typename T>
-constexpr int up_rows() { return sizeof(T) == 8 ? 32 : 64; }
+constexpr int up_rows() { return 8; }
 
 template <typename T, typename E, int CW>
 void launch_up(bool idx64, uint64_t blocks, size_t lds, hipStream_t s, const UpArgs<T, E>& ua, const T* x, T* y) {
@@ -595,9 +605,9 @@ HvPlan default_plan(const pdz_problem_s* p, pdz_dtype dt) {
         d.down = 1;
     else
         d.down = 2;
-    d.up_cw = dt == PDZ_F64 ? 32 : 64;
+    d.up_cw = 128;
     d.up = 1;
-    d.map = 1;
+    d.map = 3;
     return d;
 }
 
@@ -691,6 +701,8 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
         const uint64_t pairs = (ua.n_chunks + 1) / 2;
         const uint64_t pairs_per_xcd = (pairs + kXcd - 1) / kXcd;
         blocks = kXcd * pairs_per_xcd * 2 * ua.row_tiles;
+    } else if (plan.map == 3) {
+        blocks = kXcd * ((ua.n_chunks + kXcd - 1) / kXcd) * ua.row_tiles;
     }
     if (plan.up == 2 && !idx64) {
         // preloaded rows: one column per lane (CW <= 64)
@@ -825,7 +837,7 @@ std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
     for (int dv : downs)
         for (int k = 0; k < kNumCw; ++k)
             for (int um = 1; um <= 2; ++um)
-                for (int mp = 1; mp <= 2; ++mp) {
+                for (int mp = 1; mp <= 3; ++mp) {
                     HvPlan c;
                     c.down = dv;
                     c.up_cw = cws[k];

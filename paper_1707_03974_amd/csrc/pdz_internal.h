@@ -55,7 +55,7 @@ struct HvPlan {
                      // 3: two rows per group, table in a loop
     int up_cw = 0;   // up-pass chunk width in columns
     int up = 0;      // 1: hops of a row loaded in batches of 8; 2: all hops of a row loaded up front
-    int map = 0;     // up-pass tile order: 1 XCD-aware chunk pairs, 2 chunk-major
+    int map = 0;     // up-pass tile order: 1 XCD-aware chunk pairs, 2 chunk-major, 3 XCD-aware single chunks
 };
 }  // namespace pdz
 

@@ -30,6 +30,7 @@ constexpr int kNarrowBlock = 256;  // down pass, short rows
 constexpr int kUpBlock = 256;      // up pass
 constexpr int kFlyBlock = 256;
 constexpr size_t kLdsBytes = 160 * 1024;
+constexpr size_t kDynLds = kLdsBytes - 1024;   // kernels also hold a few static words
 
 template <typename T, typename E>
 struct DownArgs {
@@ -44,6 +45,7 @@ struct DownArgs {
     const T* coef;
     int ncoef;
     int rows;         // rows staged per group
+    double* dotp;     // NULL, or one partial sum of x . y (this pass's output) per work group
     const int* skip;
 };
 
@@ -60,6 +62,8 @@ struct UpArgs {
     uint32_t row_tiles;   // row tiles of ROWS_PER_TILE rows
     int max_hops;         // hop slots per row in the table
     int map;              // block -> tile order (up_tile)
+    int add_y;            // 1: out = y + up term (y from the down pass); 0: out = up term
+    double* dotp;         // NULL, or one partial sum of x . out per work group
     const int* skip;
 };
 
@@ -103,6 +107,22 @@ __device__ __forceinline__ void load_coef(T* sc, const T* __restrict__ g, int n)
     for (int k = threadIdx.x; k < n; k += blockDim.x) sc[k] = g[k];
 }
 
+// Sum of one double per thread over the work group (fixed order) into
+// *out by thread 0; BLOCK threads, a multiple of 64.
+template <int BLOCK>
+__device__ __forceinline__ void block_dot_store(double v, double* out) {
+    __shared__ double wsum[BLOCK / 64];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < BLOCK / 64; ++i) t += wsum[i];
+        *out = t;
+    }
+}
+
 // ---------------------------------------------------------------- down pass
 
 // Long rows: R (1 or 2) consecutive rows staged interleaved as
@@ -122,6 +142,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
     const uint64_t ngroups = (D_up + R - 1) / R;
     constexpr int PER = R == 2 ? (sizeof(T) == 8 ? 8 : 12) : (sizeof(T) == 8 ? 16 : 24);
     T pre[PER];
+    double dsum = 0.0;   // x . y over this work group's elements (when a.dotp is set)
     auto fetch = [&](uint64_t g) {
         const uint64_t u0 = g * R;
         const uint64_t nelem = ((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * D_dn;
@@ -184,7 +205,10 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    if (r < nr) __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                    if (r < nr) {
+                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                        dsum += (double)rows[(size_t)d * R + r] * (double)acc[r];
+                    }
                 continue;
             }
             int h = 0;
@@ -214,9 +238,13 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
             }
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (r < nr) __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                if (r < nr) {
+                    __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                    dsum += (double)rows[(size_t)d * R + r] * (double)acc[r];
+                }
         }
     }
+    if (a.dotp) block_dot_store<kWideBlock>(dsum, a.dotp + blockIdx.x);
 }
 
 // Short rows: `rows` consecutive rows staged row-major; threads walk the
@@ -233,6 +261,7 @@ __global__ __launch_bounds__(kNarrowBlock) void k_hv_down_narrow(const DownArgs<
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
     const int R = a.rows;
     const uint64_t ngroups = (D_up + R - 1) / R;
+    double dsum = 0.0;
     for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const uint64_t u0 = g * (uint64_t)R;
         const int nr = (int)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
@@ -255,8 +284,10 @@ __global__ __launch_bounds__(kNarrowBlock) void k_hv_down_narrow(const DownArgs<
                 acc += coef[e >> a.cshift] * xrow[e & a.tmask];
             }
             y[(u0 + r) * D_dn + d] = acc;
+            dsum += (double)xrow[d] * (double)acc;
         }
     }
+    if (a.dotp) block_dot_store<kNarrowBlock>(dsum, a.dotp + blockIdx.x);
 }
 
 // ------------------------------------------------------------------ up pass
@@ -319,7 +350,10 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
     int* s_cnt = reinterpret_cast<int*>(s_off64 + (IDX64 ? ROWS_PER_TILE * maxh : 0));
     uint32_t chunk, tile;
     up_tile(blockIdx.x, a.row_tiles, a.map, &chunk, &tile);
-    if (chunk >= a.n_chunks) return;
+    if (chunk >= a.n_chunks) {   // padding block of the tile order
+        if (a.dotp && threadIdx.x == 0) a.dotp[blockIdx.x] = 0.0;
+        return;
+    }
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
     const uint64_t u_begin = (uint64_t)tile * ROWS_PER_TILE;
     const int nrows = (int)((D_up - u_begin) < (uint64_t)ROWS_PER_TILE ? (D_up - u_begin) : (uint64_t)ROWS_PER_TILE);
@@ -340,17 +374,21 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
     constexpr int LANES = CW / VEC;
     const uint32_t lane = threadIdx.x % LANES;
     const uint64_t d = (uint64_t)chunk * CW + (uint64_t)lane * VEC;
-    if (d >= D_dn) return;
-    const int nv = (d + VEC <= D_dn) ? VEC : (int)(D_dn - d);   // valid columns of this lane
+    const bool active = d < D_dn;   // lanes past the last column idle (no early exit: a barrier follows)
+    const int nv = !active ? 0 : ((d + VEC <= D_dn) ? VEC : (int)(D_dn - d));   // valid columns of this lane
     constexpr int kSlots = kUpBlock / LANES;
-    for (int r = threadIdx.x / LANES; r < nrows; r += kSlots) {
+    double dsum = 0.0;
+    for (int r = threadIdx.x / LANES; active && r < nrows; r += kSlots) {
         const uint64_t u = u_begin + r;
         const int cnt = s_cnt[r];
         const UpHop<T>* hp = s_hop + r * maxh;
         const uint64_t* o64 = s_off64 + r * maxh;
         T* yr = y + u * D_dn + d;
         T acc[VEC];
-        if (VEC == 1) {
+        if (!a.add_y) {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[i] = (T)0;
+        } else if (VEC == 1) {
             acc[0] = __builtin_nontemporal_load(yr);   // streamed: keep the x slab in L2
         } else if (nv == VEC) {
             vec_load<T, VEC>(yr, acc);
@@ -392,7 +430,14 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
             for (int i = 0; i < VEC; ++i)
                 if (i < nv) yr[i] = acc[i];
         }
+        if (a.dotp) {
+            const T* xr = x + u * D_dn + d;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i)
+                if (i < nv) dsum += (double)xr[i] * (double)acc[i];
+        }
     }
+    if (a.dotp) block_dot_store<kUpBlock>(dsum, a.dotp + blockIdx.x);
 }
 
 // Same tile order and decoded hop lists as k_hv_up, but every hop load of a
@@ -408,7 +453,10 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up_pre(const UpArgs<T, E> a, co
     int* s_cnt = reinterpret_cast<int*>(s_hop + ROWS_PER_TILE * maxh);
     uint32_t chunk, tile;
     up_tile(blockIdx.x, a.row_tiles, a.map, &chunk, &tile);
-    if (chunk >= a.n_chunks) return;
+    if (chunk >= a.n_chunks) {   // padding block of the tile order
+        if (a.dotp && threadIdx.x == 0) a.dotp[blockIdx.x] = 0.0;
+        return;
+    }
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
     const uint64_t u_begin = (uint64_t)tile * ROWS_PER_TILE;
     const int nrows = (int)((D_up - u_begin) < (uint64_t)ROWS_PER_TILE ? (D_up - u_begin) : (uint64_t)ROWS_PER_TILE);
@@ -423,21 +471,24 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up_pre(const UpArgs<T, E> a, co
     __syncthreads();
     const uint32_t col = threadIdx.x % CW;
     const uint64_t d = (uint64_t)chunk * CW + col;
-    if (d >= D_dn) return;
+    const bool active = d < D_dn;   // no early exit: a barrier follows
     constexpr int kSlots = kUpBlock / CW;
-    for (int r = threadIdx.x / CW; r < nrows; r += kSlots) {
+    double dsum = 0.0;
+    for (int r = threadIdx.x / CW; active && r < nrows; r += kSlots) {
         const uint64_t u = u_begin + r;
         const int cnt = s_cnt[r];
         const UpHop<T>* hp = s_hop + r * maxh;
         T v[MAXH];
 #pragma unroll
         for (int h = 0; h < MAXH; ++h) v[h] = (h < cnt) ? x[(uint32_t)(hp[h].off + (uint32_t)d)] : (T)0;
-        T acc = __builtin_nontemporal_load(y + u * D_dn + d);
+        T acc = a.add_y ? __builtin_nontemporal_load(y + u * D_dn + d) : (T)0;
 #pragma unroll
         for (int h = 0; h < MAXH; ++h)
             if (h < cnt) acc += hp[h].c * v[h];
         __builtin_nontemporal_store(acc, y + u * D_dn + d);
+        if (a.dotp) dsum += (double)x[u * D_dn + d] * (double)acc;
     }
+    if (a.dotp) block_dot_store<kUpBlock>(dsum, a.dotp + blockIdx.x);
 }
 
 // ------------------------------------------------------------ fallback path
@@ -512,6 +563,11 @@ __global__ __launch_bounds__(kFlyBlock) void k_hv_fly(const FlyArgs f, T U, cons
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_fill(T* v, uint64_t n) {
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) v[i] = (T)0;
+}
+
 // ---------------------------------------------------------------- launches
 
 template <typename T, typename E>
@@ -548,7 +604,7 @@ void launch_wide(int variant, int max_hops, uint64_t grid, size_t lds, hipStream
 template <typename T, typename E, int R, int MAXH>
 pdz_status set_wide_lds() {
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_wide<T, E, R, MAXH>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     return ok();
 }
 
@@ -621,9 +677,66 @@ HvPlan hv_resolve(const pdz_problem_s* p, pdz_dtype dt) {
     return pl;
 }
 
+// Down-pass launch geometry (also the number of x . y partial sums it writes).
+struct DownGeom {
+    bool wide = false;    // k_hv_down_wide (rows at least one work group wide, staged in LDS)
+    bool stage = false;   // narrow kernel with rows staged in LDS
+    int rows = 1;         // rows per group
+    size_t lds = 0;       // dynamic LDS bytes
+    uint64_t grid = 0;    // work groups
+};
+
+DownGeom down_geom(const pdz_problem_s* p, size_t es, const HvPlan& plan, unsigned cu) {
+    DownGeom g;
+    const uint64_t D_up = p->up.D, D_dn = p->dn.D;
+    const size_t lds_cap = kLdsBytes - kMaxCoef * es - 1024;
+    const size_t row_bytes = (size_t)D_dn * es;
+    if (D_dn >= (uint64_t)kWideBlock && row_bytes <= lds_cap) {
+        g.wide = g.stage = true;
+        g.rows = plan.down == 3 ? 2 : 1;
+        g.lds = kMaxCoef * es + (size_t)g.rows * row_bytes;
+        const uint64_t ngroups = (D_up + g.rows - 1) / g.rows;
+        const unsigned per_cu = (unsigned)(kLdsBytes / (g.lds + 256));
+        g.grid = (uint64_t)cu * (per_cu < 1 ? 1 : per_cu);
+        if (g.grid > ngroups) g.grid = ngroups;
+        return g;
+    }
+    g.stage = row_bytes <= lds_cap;
+    int R = 1;
+    if (D_dn < 2 * (uint64_t)kNarrowBlock) R = (int)((2 * kNarrowBlock + D_dn - 1) / D_dn);
+    if (g.stage) {
+        const int rmax = (int)(lds_cap / row_bytes);
+        if (R > rmax) R = rmax;
+    }
+    if ((uint64_t)R > D_up) R = (int)D_up;
+    if (R < 1) R = 1;
+    g.rows = R;
+    g.lds = kMaxCoef * es + (g.stage ? (size_t)R * row_bytes : 0);
+    const uint64_t ngroups = (D_up + R - 1) / R;
+    const unsigned per_cu = g.stage ? (unsigned)(kLdsBytes / (g.lds + 256)) : 8u;
+    g.grid = (uint64_t)cu * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
+    if (g.grid > ngroups) g.grid = ngroups;
+    return g;
+}
+
+uint64_t down_grid(const pdz_problem_s* p, size_t es, const HvPlan& plan, unsigned cu) {
+    return down_geom(p, es, plan, cu).grid;
+}
+
+// Up-pass work groups (tile order padded to whole XCD rounds).
+uint64_t up_blocks(const pdz_problem_s* p, size_t es, const HvPlan& plan) {
+    constexpr uint64_t kXcd = 8;
+    const uint64_t rows = es == 8 ? (uint64_t)up_rows<double>() : (uint64_t)up_rows<float>();
+    const uint64_t rt = (p->up.D + rows - 1) / rows;
+    const uint64_t nch = (p->dn.D + plan.up_cw - 1) / plan.up_cw;
+    if (plan.map == 1) return kXcd * (((nch + 1) / 2 + kXcd - 1) / kXcd) * 2 * rt;
+    if (plan.map == 3) return kXcd * ((nch + kXcd - 1) / kXcd) * rt;
+    return nch * rt;
+}
+
 template <typename T, typename E>
 pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coef, const T* x, T* y, hipStream_t s,
-                      const int* skip, bool compact, unsigned passes) {
+                      const int* skip, bool compact, unsigned passes, const HvSplit* split) {
     const uint64_t D_up = p->up.D, D_dn = p->dn.D;
     const int ncoef = (int)p->coef_host.size();
     // ---- down pass
@@ -638,46 +751,31 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     da.coef = coef;
     da.ncoef = ncoef;
     da.skip = skip;
-    const size_t lds_cap = kLdsBytes - kMaxCoef * sizeof(T) - 1024;
-    const size_t row_bytes = (size_t)D_dn * sizeof(T);
-    const unsigned cu = (unsigned)ctx->cu_count;
+    da.dotp = split ? split->dotp_dn : nullptr;
     const HvPlan plan = hv_resolve(p, sizeof(T) == 8 ? PDZ_F64 : PDZ_F32);
+    const DownGeom gm = down_geom(p, sizeof(T), plan, (unsigned)ctx->cu_count);
+    da.rows = gm.rows;
     if (!(passes & kPassDown)) {
         // up pass only
-    } else if (D_dn >= (uint64_t)kWideBlock && row_bytes <= lds_cap) {
-        const bool two = plan.down == 3;
-        da.rows = two ? 2 : 1;
-        const size_t lds = kMaxCoef * sizeof(T) + (size_t)da.rows * row_bytes;
-        const uint64_t ngroups = (D_up + da.rows - 1) / da.rows;
-        const unsigned per_cu = (unsigned)(kLdsBytes / (lds + 256));
-        uint64_t grid = (uint64_t)cu * (per_cu < 1 ? 1 : per_cu);
-        if (grid > ngroups) grid = ngroups;
-        launch_wide<T, E>(plan.down, p->dn.max_hops, grid, lds, s, da, x, y);
+    } else if (gm.wide) {
+        launch_wide<T, E>(plan.down, p->dn.max_hops, gm.grid, gm.lds, s, da, x, y);
+    } else if (gm.stage) {
+        hipLaunchKernelGGL((k_hv_down_narrow<T, E, true>), dim3((unsigned)gm.grid), dim3(kNarrowBlock), gm.lds, s, da,
+                           x, y);
     } else {
-        const bool stage = row_bytes <= lds_cap;
-        int R = 1;
-        if (D_dn < 2 * (uint64_t)kNarrowBlock) R = (int)((2 * kNarrowBlock + D_dn - 1) / D_dn);
-        if (stage) {
-            const int rmax = (int)(lds_cap / row_bytes);
-            if (R > rmax) R = rmax;
-        }
-        if ((uint64_t)R > D_up) R = (int)D_up;
-        if (R < 1) R = 1;
-        da.rows = R;
-        const size_t lds = kMaxCoef * sizeof(T) + (stage ? (size_t)R * row_bytes : 0);
-        const uint64_t ngroups = (D_up + R - 1) / R;
-        const unsigned per_cu = stage ? (unsigned)(kLdsBytes / (lds + 256)) : 8u;
-        uint64_t grid = (uint64_t)cu * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
-        if (grid > ngroups) grid = ngroups;
-        if (stage)
-            hipLaunchKernelGGL((k_hv_down_narrow<T, E, true>), dim3((unsigned)grid), dim3(kNarrowBlock), lds, s, da,
-                               x, y);
-        else
-            hipLaunchKernelGGL((k_hv_down_narrow<T, E, false>), dim3((unsigned)grid), dim3(kNarrowBlock), lds, s, da,
-                               x, y);
+        hipLaunchKernelGGL((k_hv_down_narrow<T, E, false>), dim3((unsigned)gm.grid), dim3(kNarrowBlock), gm.lds, s,
+                           da, x, y);
     }
     PDZ_HIP(hipGetLastError());
-    if (p->up.max_hops == 0 || !(passes & kPassUp)) return ok();
+    if (p->up.max_hops == 0 || !(passes & kPassUp)) {
+        if (split && split->z) {   // no up hops: the up term is zero
+            hipLaunchKernelGGL(k_zero_fill<T>, dim3(1024), dim3(256), 0, s, static_cast<T*>(split->z), p->D);
+            if (split->dotp_up) hipLaunchKernelGGL(k_zero_fill<double>, dim3(1), dim3(64), 0, s, split->dotp_up,
+                                                   (uint64_t)1);
+            PDZ_HIP(hipGetLastError());
+        }
+        return ok();
+    }
     // ---- up pass
     UpArgs<T, E> ua;
     ua.D_up = D_up;
@@ -687,49 +785,45 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     ua.coef = coef;
     ua.ncoef = ncoef;
     ua.skip = skip;
+    // split: the up term goes to its own buffer (no re-read of y); else it is added into y
+    ua.add_y = (split && split->z) ? 0 : 1;
+    ua.dotp = split ? split->dotp_up : nullptr;
+    T* yout = (split && split->z) ? static_cast<T*>(split->z) : y;
     constexpr int ROWS = up_rows<T>();
     const int CW = plan.up_cw;
-    constexpr int kXcd = 8;
     const bool idx64 = p->D > 0xFFFFFFFFull;
     ua.row_tiles = (uint32_t)((D_up + ROWS - 1) / ROWS);
     ua.max_hops = p->up.max_hops;
     ua.n_chunks = (uint32_t)((D_dn + CW - 1) / CW);
     const size_t lds = (size_t)ROWS * ua.max_hops * (sizeof(UpHop<T>) + (idx64 ? 8 : 0)) + ROWS * sizeof(int);
     ua.map = plan.map;
-    uint64_t blocks = (uint64_t)ua.n_chunks * ua.row_tiles;
-    if (plan.map == 1) {
-        const uint64_t pairs = (ua.n_chunks + 1) / 2;
-        const uint64_t pairs_per_xcd = (pairs + kXcd - 1) / kXcd;
-        blocks = kXcd * pairs_per_xcd * 2 * ua.row_tiles;
-    } else if (plan.map == 3) {
-        blocks = kXcd * ((ua.n_chunks + kXcd - 1) / kXcd) * ua.row_tiles;
-    }
+    const uint64_t blocks = up_blocks(p, sizeof(T), plan);
     if (plan.up == 2 && !idx64) {
         // preloaded rows: one column per lane (CW <= 64)
         if (sizeof(T) == 8 && CW == 16)
-            launch_up_pre<T, E, 16>(ua.max_hops, blocks, lds, s, ua, x, y);
+            launch_up_pre<T, E, 16>(ua.max_hops, blocks, lds, s, ua, x, yout);
         else if (CW == 32)
-            launch_up_pre<T, E, 32>(ua.max_hops, blocks, lds, s, ua, x, y);
+            launch_up_pre<T, E, 32>(ua.max_hops, blocks, lds, s, ua, x, yout);
         else
-            launch_up_pre<T, E, 64>(ua.max_hops, blocks, lds, s, ua, x, y);
+            launch_up_pre<T, E, 64>(ua.max_hops, blocks, lds, s, ua, x, yout);
     } else if (sizeof(T) == 8) {
         if (CW == 16)
-            launch_up<T, E, 16>(idx64, blocks, lds, s, ua, x, y);
+            launch_up<T, E, 16>(idx64, blocks, lds, s, ua, x, yout);
         else if (CW == 32)
-            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, y);
+            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, yout);
         else if (CW == 64)
-            launch_up<T, E, 64>(idx64, blocks, lds, s, ua, x, y);
+            launch_up<T, E, 64>(idx64, blocks, lds, s, ua, x, yout);
         else
-            launch_up<T, E, 128>(idx64, blocks, lds, s, ua, x, y);
+            launch_up<T, E, 128>(idx64, blocks, lds, s, ua, x, yout);
     } else {
         if (CW == 32)
-            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, y);
+            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, yout);
         else if (CW == 64)
-            launch_up<T, E, 64>(idx64, blocks, lds, s, ua, x, y);
+            launch_up<T, E, 64>(idx64, blocks, lds, s, ua, x, yout);
         else if (CW == 128)
-            launch_up<T, E, 128>(idx64, blocks, lds, s, ua, x, y);
+            launch_up<T, E, 128>(idx64, blocks, lds, s, ua, x, yout);
         else
-            launch_up<T, E, 256>(idx64, blocks, lds, s, ua, x, y);
+            launch_up<T, E, 256>(idx64, blocks, lds, s, ua, x, yout);
     }
     PDZ_HIP(hipGetLastError());
     return ok();
@@ -737,14 +831,14 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
 
 template <typename T>
 pdz_status run_hv(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipStream_t s, const int* skip,
-                  unsigned passes) {
+                  unsigned passes, const HvSplit* split) {
     DeviceCtx* ctx = nullptr;
     pdz_status st = device_ctx(&ctx);
     if (st != PDZ_OK) return st;
     if (p->hv_path == 0) {
         const bool compact = p->up.tbits16 > 0 && p->dn.tbits16 > 0;
-        if (compact) return run_tables<T, uint16_t>(p, ctx, coef, x, y, s, skip, true, passes);
-        return run_tables<T, uint32_t>(p, ctx, coef, x, y, s, skip, false, passes);
+        if (compact) return run_tables<T, uint16_t>(p, ctx, coef, x, y, s, skip, true, passes, split);
+        return run_tables<T, uint32_t>(p, ctx, coef, x, y, s, skip, false, passes, split);
     }
     FlyArgs f;
     f.N = p->N;
@@ -767,26 +861,26 @@ pdz_status run_hv(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipSt
 template <typename T, typename E, int CW>
 pdz_status set_up_lds() {
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     return ok();
 }
 
 template <typename T, typename E, int CW>
 pdz_status set_up_pre_lds() {
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up_pre<T, E, CW, up_rows<T>(), 16>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up_pre<T, E, CW, up_rows<T>(), 32>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up_pre<T, E, CW, up_rows<T>(), 48>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     return ok();
 }
 
 template <typename T, typename E>
 pdz_status prepare_one() {
-    const int lds = (int)kLdsBytes;
+    const int lds = (int)kDynLds;
     pdz_status st = set_wide_lds<T, E, 1, 0>();
     if (st == PDZ_OK) st = set_wide_lds<T, E, 2, 0>();
     if (sizeof(E) == 2) {
@@ -859,11 +953,38 @@ bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan) {
 }
 
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
-                     const int* skip, unsigned passes) {
+                     const int* skip, unsigned passes, const HvSplit* split) {
+    if (split && p->hv_path != 0) return fail(PDZ_EINVAL, "split H.v needs the table path");
     if (dt == PDZ_F64)
         return run_hv<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip,
-                              passes);
-    return run_hv<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip, passes);
+                              passes, split);
+    return run_hv<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip, passes,
+                         split);
+}
+
+size_t hv_dot_count_max(const pdz_problem_s* p, pdz_dtype dt) {
+    if (p->hv_path != 0) return 0;
+    DeviceCtx* ctx = nullptr;
+    if (device_ctx(&ctx) != PDZ_OK) return 0;
+    const size_t es = dt == PDZ_F64 ? 8 : 4;
+    size_t best = 0;
+    for (const HvPlan& c : hv_candidates(p, dt)) {
+        const size_t n = (size_t)down_grid(p, es, c, (unsigned)ctx->cu_count) +
+                         (p->up.max_hops == 0 ? 1 : (size_t)up_blocks(p, es, c));
+        if (n > best) best = n;
+    }
+    return best;
+}
+
+bool hv_dot_counts(const pdz_problem_s* p, pdz_dtype dt, int* n_dn, int* n_up) {
+    if (p->hv_path != 0) return false;
+    DeviceCtx* ctx = nullptr;
+    if (device_ctx(&ctx) != PDZ_OK) return false;
+    const size_t es = dt == PDZ_F64 ? 8 : 4;
+    const HvPlan plan = hv_resolve(p, dt);
+    *n_dn = (int)down_grid(p, es, plan, (unsigned)ctx->cu_count);
+    *n_up = p->up.max_hops == 0 ? 1 : (int)up_blocks(p, es, plan);
+    return true;
 }
 
 }  // namespace pdz

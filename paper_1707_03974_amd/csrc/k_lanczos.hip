@@ -12,6 +12,7 @@
 // Vectors may be stored in FP32 or FP64; every dot product multiplies in FP64
 // and accumulates in FP64.  Reductions use a fixed grid and a fixed tree, so
 // results are bitwise reproducible run to run.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -27,6 +28,7 @@ namespace {
 constexpr int kRedBlock = 256;
 constexpr int kRedGrid = 1024;   // partial sums per reduction (fixed for determinism)
 constexpr int kMaxIter = 2000;
+constexpr int kMaxPartials = 4096;   // partial sums a fused H.v dot may write
 
 struct Ctl {
     int k;          // completed Lanczos steps
@@ -153,6 +155,135 @@ __global__ __launch_bounds__(kRedBlock) void k_update(T* __restrict__ w, const T
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
+// Three-term recurrence on unnormalised vectors q_j with v_j = sc[j] q_j:
+// on entry w + z = H q_k (z: the up-hop part kept apart by the split H.v, or
+// NULL); on exit w = H v_k - alpha_k v_k - beta_k v_{k-1}
+// = sc[k] w - alpha_k sc[k] q_k - beta_k sc[k-1] q_{k-1}, the next q, with
+// partial[] = |w|^2.  No separate normalisation pass: sc[k+1] = 1 / beta_{k+1}.
+template <typename T, bool HZ>
+__device__ __forceinline__ T update_one(T wi, T zi, T qi, T qpi, double a, double b, double c, double& acc) {
+    const double hq = HZ ? (double)wi + (double)zi : (double)wi;   // H q_k, from its two parts
+    const T r = (T)(a * hq - b * (double)qi - c * (double)qpi);
+    acc += (double)r * (double)r;
+    return r;
+}
+
+// `vec`: every pointer is 16-byte aligned, so the body moves 16-byte vectors,
+// two per thread and array in flight; the last D mod (16 / sizeof(T))
+// elements go one per thread.  Each block's partial sums a fixed set of
+// elements in a fixed order.
+template <typename T, bool HZ>
+__global__ __launch_bounds__(kRedBlock) void k_update_scaled(T* __restrict__ w, const T* __restrict__ z,
+                                                             const T* __restrict__ q, const T* __restrict__ qp,
+                                                             uint64_t D, const double* alpha, const double* beta,
+                                                             const double* sc, const int* kidx, double* partial,
+                                                             const int* skip, int vec) {
+    if (skip && *skip) return;
+    __shared__ double red[kRedBlock];
+    const int k = *kidx;
+    const double a = sc[k];
+    const double b = alpha[k] * sc[k];
+    const double c = k > 0 ? beta[k] * sc[k - 1] : 0.0;
+    const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    double acc = 0.0;
+    uint64_t i = tid;
+    if (vec) {
+        constexpr int N = 16 / sizeof(T);
+        typedef T V __attribute__((ext_vector_type(N)));
+        V* wv = reinterpret_cast<V*>(w);
+        const V* zv = reinterpret_cast<const V*>(z);
+        const V* qv = reinterpret_cast<const V*>(q);
+        const V* pv = reinterpret_cast<const V*>(qp);
+        const uint64_t nv = D / N;
+        uint64_t j = tid;
+        for (; j + stride < nv; j += 2 * stride) {
+            const V w0 = wv[j], w1 = wv[j + stride];
+            const V q0 = qv[j], q1 = qv[j + stride];
+            const V p0 = pv[j], p1 = pv[j + stride];
+            V z0 = w0, z1 = w1;
+            if (HZ) {
+                z0 = zv[j];
+                z1 = zv[j + stride];
+            }
+            V r0, r1;
+#pragma unroll
+            for (int e = 0; e < N; ++e) r0[e] = update_one<T, HZ>(w0[e], z0[e], q0[e], p0[e], a, b, c, acc);
+#pragma unroll
+            for (int e = 0; e < N; ++e) r1[e] = update_one<T, HZ>(w1[e], z1[e], q1[e], p1[e], a, b, c, acc);
+            wv[j] = r0;
+            wv[j + stride] = r1;
+        }
+        if (j < nv) {
+            const V w0 = wv[j], q0 = qv[j], p0 = pv[j];
+            const V z0 = HZ ? zv[j] : w0;
+            V r0;
+#pragma unroll
+            for (int e = 0; e < N; ++e) r0[e] = update_one<T, HZ>(w0[e], z0[e], q0[e], p0[e], a, b, c, acc);
+            wv[j] = r0;
+        }
+        i = nv * N + tid;   // the ragged tail
+    }
+    for (; i < D; i += stride) w[i] = update_one<T, HZ>(w[i], HZ ? z[i] : T(0), q[i], qp[i], a, b, c, acc);
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+template <typename T>
+void launch_update_scaled(T* w, const T* z, const T* q, const T* qp, uint64_t D, const double* alpha,
+                          const double* beta, const double* sc, const int* kidx, double* partial, const int* skip,
+                          hipStream_t s) {
+    auto al = [](const void* x) { return ((uintptr_t)x & 15) == 0; };
+    const int vec = al(w) && al(q) && al(qp) && (!z || al(z));
+    if (z)
+        hipLaunchKernelGGL((k_update_scaled<T, true>), dim3(kRedGrid), dim3(kRedBlock), 0, s, w, z, q, qp, D, alpha,
+                           beta, sc, kidx, partial, skip, vec);
+    else
+        hipLaunchKernelGGL((k_update_scaled<T, false>), dim3(kRedGrid), dim3(kRedBlock), 0, s, w, z, q, qp, D, alpha,
+                           beta, sc, kidx, partial, skip, vec);
+}
+
+// alpha[k] = sc[k]^2 * (sum(p1[0..n1)) + sum(p2[0..n2))): <v_k, H v_k> from
+// partial sums of q_k . H q_k.
+__global__ __launch_bounds__(kRedBlock) void k_finalize_alpha(const double* p1, int n1, const double* p2, int n2,
+                                                              double* alpha, const double* sc, const int* kidx,
+                                                              const int* skip, uint32_t* err) {
+    if (skip && *skip) return;
+    __shared__ double red[kRedBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) acc += p1[i];
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) acc += p2[i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        const int k = *kidx;
+        const double v = sc[k] * sc[k] * acc;
+        alpha[k] = v;
+        if (!isfinite(v)) atomicOr(err, kErrNonFinite);
+    }
+}
+
+// out[b] = sum of in[b], in[b + grid], in[b + 2 grid], ... (fixed order)
+__global__ __launch_bounds__(kRedBlock) void k_sum_strided(const double* in, uint64_t n, double* out,
+                                                           const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[kRedBlock];
+    double acc = 0.0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        acc += in[i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+// sc[k] = 1 / beta[k] for the step counter k just advanced by k_tridiag.
+__global__ void k_next_scale(const double* beta, double* sc, const Ctl* ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && !ctl->done) sc[ctl->k] = 1.0 / beta[ctl->k];
+}
+
+// sc[0] = 1 / norm0
+__global__ void k_first_scale(double* sc, const Ctl* ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) sc[0] = 1.0 / ctl->norm0;
+}
+
 // Full re-orthogonalisation: c_j = <V_j, w> for j < nvec (grid.y = j).
 template <typename T>
 __global__ __launch_bounds__(kRedBlock) void k_dots_basis(const T* __restrict__ V, uint64_t ld, uint64_t D, int nvec,
@@ -192,11 +323,11 @@ __global__ __launch_bounds__(kRedBlock) void k_sub_basis(const T* __restrict__ V
     }
 }
 
-// y += s_j v (FP64 y)
+// y += s_j sc_j v (FP64 y; sc NULL = 1)
 template <typename T>
 __global__ __launch_bounds__(kRedBlock) void k_axpy_coef(double* __restrict__ y, const T* __restrict__ v, uint64_t D,
-                                                         const double* s, int j) {
-    const double c = s[j];
+                                                         const double* s, const double* sc, int j) {
+    const double c = sc ? s[j] * sc[j] : s[j];
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x)
         y[i] += c * (double)v[i];
 }
@@ -284,12 +415,13 @@ struct Layout {
     size_t buf[3] = {0, 0, 0};
     size_t basis = 0;
     size_t y = 0, hy = 0;
-    size_t alpha = 0, beta = 0, theta = 0, s = 0, partial = 0, coefs = 0, ctl = 0;
+    size_t alpha = 0, beta = 0, theta = 0, s = 0, sc = 0, partial = 0, partial2 = 0, coefs = 0, ctl = 0, z = 0;
     size_t total = 0;
     int nvec_basis = 0;
 };
 
-Layout make_layout(uint64_t D, const pdz_lanczos_opts* o) {
+Layout make_layout(const pdz_problem_s* p, const pdz_lanczos_opts* o) {
+    const uint64_t D = p->D;
     Layout L;
     const size_t es = o->storage == PDZ_F64 ? 8 : 4;
     L.vec = align256((size_t)D * es);
@@ -305,6 +437,8 @@ Layout make_layout(uint64_t D, const pdz_lanczos_opts* o) {
             L.buf[i] = off;
             off += L.vec;
         }
+        L.z = off;   // up-hop part of H q_k
+        off += L.vec;
     }
     if (o->refine) {
         L.y = off;
@@ -321,8 +455,14 @@ Layout make_layout(uint64_t D, const pdz_lanczos_opts* o) {
     off += align256(2 * m * 8);
     L.s = off;
     off += align256(m * 8);
+    L.sc = off;
+    off += align256(m * 8);
     L.partial = off;
-    off += align256((size_t)kRedGrid * (o->reorth ? m : 1) * 8);
+    off += align256(std::max<size_t>(std::max<size_t>((size_t)kRedGrid * (o->reorth ? m : 1), kMaxPartials),
+                                     hv_dot_count_max(p, (pdz_dtype)o->storage)) *
+                    8);
+    L.partial2 = off;
+    off += align256((size_t)kRedGrid * 8);
     L.coefs = off;
     off += align256(m * 8);
     L.ctl = off;
@@ -355,6 +495,9 @@ struct Run {
     double* beta() const { return reinterpret_cast<double*>(ws + L.beta); }
     double* theta() const { return reinterpret_cast<double*>(ws + L.theta); }
     double* svec() const { return reinterpret_cast<double*>(ws + L.s); }
+    double* sc() const { return reinterpret_cast<double*>(ws + L.sc); }
+    double* partial2() const { return reinterpret_cast<double*>(ws + L.partial2); }
+    T* zbuf() const { return reinterpret_cast<T*>(ws + L.z); }
     double* partial() const { return reinterpret_cast<double*>(ws + L.partial); }
     double* coefs() const { return reinterpret_cast<double*>(ws + L.coefs); }
     Ctl* ctl() const { return reinterpret_cast<Ctl*>(ws + L.ctl); }
@@ -366,8 +509,9 @@ struct Run {
         return ok();
     }
 
-    // v_1 = v0 / |v0| into dst; zero vector into zero_dst.
-    pdz_status start(const void* v0, T* dst, T* zero_dst) {
+    // v_1 = v0 / |v0| into dst; zero vector into zero_dst.  scaled: keep
+    // dst = v0 unnormalised and set sc[0] = 1 / |v0| instead.
+    pdz_status start(const void* v0, T* dst, T* zero_dst, bool scaled) {
         const unsigned g = grid_elems(D);
         hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, s, err, kErrNonFinite);
         hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, ctl(), beta());
@@ -387,8 +531,57 @@ struct Run {
         PDZ_HIP(hipStreamSynchronize(s));
         if (!(h.norm0 > 0.0) || !std::isfinite(h.norm0))
             return fail(PDZ_EINVAL, "start vector has zero or non-finite norm");
-        hipLaunchKernelGGL(k_scale<T>, dim3(g), dim3(kRedBlock), 0, s, dst, D, &ctl()->norm0, (const int*)nullptr, 0,
-                           (const int*)nullptr);
+        if (scaled)
+            hipLaunchKernelGGL(k_first_scale, dim3(1), dim3(1), 0, s, sc(), ctl());
+        else
+            hipLaunchKernelGGL(k_scale<T>, dim3(g), dim3(kRedBlock), 0, s, dst, D, &ctl()->norm0, (const int*)nullptr,
+                               0, (const int*)nullptr);
+        return launch_check();
+    }
+
+    // Split H.v layout of this run: partial-sum counts of its two passes
+    // (ndn = 0: the on-the-fly path, which takes a separate dot kernel).
+    struct SplitCounts {
+        int ndn = 0, nup = 0;
+    };
+    SplitCounts split_counts() const {
+        SplitCounts c;
+        if (!hv_dot_counts(p, (pdz_dtype)o->storage, &c.ndn, &c.nup)) c.ndn = c.nup = 0;
+        return c;
+    }
+
+    // One step of the three-term recurrence on unnormalised vectors (v_k =
+    // sc[k] q_k): q = q_k, qp = q_{k-1}, w receives q_{k+1}.  H q_k comes in
+    // two parts (w: diagonal + down hops, z: up hops) that the update adds;
+    // alpha comes from partial sums of q . (each part) written by the two
+    // passes of H.v, so no pass re-reads a D-sized vector for them.
+    pdz_status step_scaled(T* q, T* qp, T* w, const SplitCounts& c) {
+        if (c.ndn > 0) {
+            HvSplit sp;
+            sp.z = zbuf();
+            sp.dotp_dn = partial();
+            sp.dotp_up = partial() + c.ndn;
+            pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sp);
+            if (st != PDZ_OK) return st;
+            hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn,
+                               (uint64_t)c.nup, partial2(), done());
+            hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), c.ndn, partial2(),
+                               (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
+        } else {
+            pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done());
+            if (st != PDZ_OK) return st;
+            hipLaunchKernelGGL((k_dot_partial<T, T>), dim3(kRedGrid), dim3(kRedBlock), 0, s, q, w, D, partial(),
+                               done());
+            hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), (int)kRedGrid,
+                               (const double*)nullptr, 0, alpha(), sc(), kptr(), done(), err);
+        }
+        launch_update_scaled<T>(w, c.ndn > 0 ? (const T*)zbuf() : (const T*)nullptr, q, qp, D, alpha(), beta(), sc(),
+                                kptr(), partial(), done(), s);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, beta(), kptr(), 1,
+                           (int)kStoreSqrt, done(), err);
+        hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kRedBlock), 0, s, alpha(), beta(), svec(), theta(), ctl(), o->tol,
+                           o->max_iter, err);
+        hipLaunchKernelGGL(k_next_scale, dim3(1), dim3(1), 0, s, beta(), sc(), ctl());
         return launch_check();
     }
 
@@ -447,10 +640,11 @@ struct Run {
         // three rotating buffers; a block of `period` steps (multiple of 3) keeps the rotation aligned
         int period = o->check_every;
         if (period % 3) period += 3 - period % 3;
+        const SplitCounts counts = split_counts();
         auto enqueue_block = [&]() -> pdz_status {
             for (int t = 0; t < period; ++t) {
                 const int a = t % 3;
-                pdz_status s2 = step(buf(a), buf((a + 2) % 3), buf((a + 1) % 3), 0);
+                pdz_status s2 = step_scaled(buf(a), buf((a + 2) % 3), buf((a + 1) % 3), counts);
                 if (s2 != PDZ_OK) return s2;
             }
             return ok();
@@ -505,55 +699,59 @@ struct Run {
             Ctl saved;
             pdz_status st = read_ctl(&saved);
             if (st != PDZ_OK) return st;
-            std::vector<double> alpha_h(m + 1), beta_h(m + 2), s_h(m);
+            std::vector<double> alpha_h(m + 1), beta_h(m + 2), sc_h(m + 1);
             PDZ_HIP(hipMemcpyAsync(alpha_h.data(), alpha(), (size_t)m * 8, hipMemcpyDeviceToHost, s));
             PDZ_HIP(hipMemcpyAsync(beta_h.data(), beta(), (size_t)(m + 1) * 8, hipMemcpyDeviceToHost, s));
+            PDZ_HIP(hipMemcpyAsync(sc_h.data(), sc(), (size_t)m * 8, hipMemcpyDeviceToHost, s));
             PDZ_HIP(hipStreamSynchronize(s));
-            st = start(v0, buf(0), buf(2));
+            st = start(v0, buf(0), buf(2), true);
             if (st != PDZ_OK) return st;
             // restore the recurrence coefficients overwritten by start()
             PDZ_HIP(hipMemcpyAsync(alpha(), alpha_h.data(), (size_t)m * 8, hipMemcpyHostToDevice, s));
             PDZ_HIP(hipMemcpyAsync(beta(), beta_h.data(), (size_t)(m + 1) * 8, hipMemcpyHostToDevice, s));
+            PDZ_HIP(hipMemcpyAsync(sc(), sc_h.data(), (size_t)m * 8, hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_fill_zero<double>, dim3(g), dim3(kRedBlock), 0, s, y(), D);
+            const SplitCounts counts = split_counts();
             for (int j = 0; j < m; ++j) {
                 const int a = j % 3;
-                T* v = buf(a);
-                T* vp = buf((a + 2) % 3);
+                T* q = buf(a);
+                T* qp = buf((a + 2) % 3);
                 T* w = buf((a + 1) % 3);
-                hipLaunchKernelGGL(k_axpy_coef<T>, dim3(g), dim3(kRedBlock), 0, s, y(), v, D, svec(), j);
+                hipLaunchKernelGGL(k_axpy_coef<T>, dim3(g), dim3(kRedBlock), 0, s, y(), q, D, svec(), sc(), j);
                 if (j + 1 < m) {
-                    // the step kernels read alpha/beta at index *kptr: set k = j on the device
+                    // the step kernels read alpha/beta/sc at index *kptr: set k = j on the device
                     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, ctl(), j, 0);
-                    st = launch_hv(p, (pdz_dtype)o->storage, v, w, s, nullptr);
+                    HvSplit sp;
+                    sp.z = zbuf();
+                    st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, nullptr, kPassDown | kPassUp,
+                                   counts.ndn > 0 ? &sp : nullptr);
                     if (st != PDZ_OK) return st;
-                    hipLaunchKernelGGL(k_update<T>, dim3(kRedGrid), dim3(kRedBlock), 0, s, w, v, vp, D, alpha(), beta(),
-                                       kptr(), partial(), (const int*)nullptr);
-                    hipLaunchKernelGGL(k_scale<T>, dim3(g), dim3(kRedBlock), 0, s, w, D, beta(), kptr(), 1,
-                                       (const int*)nullptr);
+                    launch_update_scaled<T>(w, counts.ndn > 0 ? (const T*)zbuf() : (const T*)nullptr, q, qp, D,
+                                            alpha(), beta(), sc(), kptr(), partial(), (const int*)nullptr, s);
                 }
             }
             hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, ctl(), saved.k, saved.done);
         }
-        double* sc = &ctl()->scratch[0];
+        double* scr = &ctl()->scratch[0];
         hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(kRedGrid), dim3(kRedBlock), 0, s, y(), y(), D,
                            partial(), (const int*)nullptr);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, sc, (const int*)nullptr, 0,
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, scr, (const int*)nullptr, 0,
                            (int)kStoreSqrt, (const int*)nullptr, err);
-        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kRedBlock), 0, s, y(), D, sc, (const int*)nullptr, 0,
+        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kRedBlock), 0, s, y(), D, scr, (const int*)nullptr, 0,
                            (const int*)nullptr);
         pdz_status st = launch_hv(p, PDZ_F64, y(), hy(), s, nullptr);
         if (st != PDZ_OK) return st;
         hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(kRedGrid), dim3(kRedBlock), 0, s, y(), hy(), D,
                            partial(), (const int*)nullptr);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, sc + 1,
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, scr + 1,
                            (const int*)nullptr, 0, (int)kStoreSum, (const int*)nullptr, err);
-        hipLaunchKernelGGL(k_resid_partial, dim3(kRedGrid), dim3(kRedBlock), 0, s, hy(), y(), D, sc + 1, partial());
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, sc + 2,
+        hipLaunchKernelGGL(k_resid_partial, dim3(kRedGrid), dim3(kRedBlock), 0, s, hy(), y(), D, scr + 1, partial());
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, scr + 2,
                            (const int*)nullptr, 0, (int)kStoreSqrt, (const int*)nullptr, err);
         st = launch_check();
         if (st != PDZ_OK) return st;
         double h[3];
-        PDZ_HIP(hipMemcpyAsync(h, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        PDZ_HIP(hipMemcpyAsync(h, scr, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         PDZ_HIP(hipStreamSynchronize(s));
         *E_ref = h[1];
         *r_ref = h[2];
@@ -563,7 +761,7 @@ struct Run {
     pdz_status run(const void* v0, double* ritz_out, pdz_lanczos_result* res) {
         T* v1 = o->reorth ? basis(0) : buf(0);
         T* zero = o->reorth ? buf(0) : buf(2);
-        pdz_status st = start(v0, v1, zero);
+        pdz_status st = start(v0, v1, zero, !o->reorth);
         if (st != PDZ_OK) return st;
         Ctl h;
         st = iterate(&h);
@@ -629,7 +827,7 @@ pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, 
     pdz_status st = check_opts(o);
     if (st != PDZ_OK) return st;
     pdz_lanczos_opts oo = *o;
-    *bytes = make_layout(p->D, &oo).total;
+    *bytes = make_layout(p, &oo).total;
     return ok();
 }
 
@@ -640,7 +838,7 @@ pdz_status pdz_lanczos_history(pdz_problem p, const pdz_lanczos_opts* o, const v
     if (st != PDZ_OK) return st;
     pdz_lanczos_opts oo = *o;
     if (oo.reorth) oo.use_graph = 0;
-    const Layout L = make_layout(p->D, &oo);
+    const Layout L = make_layout(p, &oo);
     if (ws_bytes < L.total) return fail(PDZ_EINVAL, "workspace smaller than pdz_lanczos_workspace_size");
     Ctl h;
     PDZ_HIP(hipMemcpy(&h, static_cast<const char*>(ws) + L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
@@ -663,7 +861,7 @@ pdz_status pdz_lanczos(pdz_problem p, const pdz_lanczos_opts* o, const void* v0,
     pdz_lanczos_opts oo = *o;
     if (ritz_out) oo.refine = 1;
     if (oo.reorth) oo.use_graph = 0;
-    const Layout L = make_layout(p->D, &oo);
+    const Layout L = make_layout(p, &oo);
     if (!ws) return fail(PDZ_EINVAL, "workspace is NULL");
     if (ws_bytes < L.total) return fail(PDZ_EINVAL, "workspace smaller than pdz_lanczos_workspace_size");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PDZ_EINVAL, "workspace must be 256-byte aligned");

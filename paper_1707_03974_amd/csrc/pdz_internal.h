@@ -125,9 +125,21 @@ pdz_status batch_prepare();   // the same for the batched H.v kernels
 std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt);
 bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan);
 // passes: kPassDown | kPassUp for y = H x; one bit alone launches only that
-// pass of the table path (the up pass then adds onto y).
+// pass of the table path (the down pass writes y, the up pass adds onto it).
+// split (table path only): the up term goes to split->z instead of being
+// added to y, and each pass writes per-work-group partial sums of x . (its
+// output) to dotp_dn / dotp_up (counts from hv_dot_counts); the sums in index
+// order give x . (H x) = sum(dotp_dn) + sum(dotp_up).
 constexpr unsigned kPassDown = 1u, kPassUp = 2u;
+struct HvSplit {
+    void* z = nullptr;          // D elements of the same precision as y
+    double* dotp_dn = nullptr;
+    double* dotp_up = nullptr;
+};
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
-                     const int* skip = nullptr, unsigned passes = kPassDown | kPassUp);
+                     const int* skip = nullptr, unsigned passes = kPassDown | kPassUp,
+                     const HvSplit* split = nullptr);
+bool hv_dot_counts(const pdz_problem_s* p, pdz_dtype dt, int* n_dn, int* n_up);   // false: no split path
+size_t hv_dot_count_max(const pdz_problem_s* p, pdz_dtype dt);   // n_dn + n_up over every valid plan
 
 }  // namespace pdz

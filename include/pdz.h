@@ -132,11 +132,14 @@ pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* str
 
 /* Launch geometry of pdz_hv for one precision.  0 in a field = automatic.
  * down: 1 one row per work group with the column's hop table loaded up front,
- *       2 one row with the table read in a loop, 3 two rows per work group;
+ *       2 one row with the table read in a loop, 3 two rows per work group,
+ *       4 three rows per work group (1: 16-bit tables and at most 48 hops
+ *       per state; 3, 4: the rows must fit in LDS);
  * up_cw: column-chunk width of the up-hop pass (F32: 32, 64, 128, 256;
  *       F64: 16, 32, 64, 128);
  * up: 1 the hops of a row are loaded in batches of 8, 2 all hops of a row are
- *       loaded before the first multiply-add (up_cw <= 64);
+ *       loaded before the first multiply-add (up_cw <= 64), 3 batches of 16
+ *       (D < 2^32);
  * map: order of the up-pass tiles: 1 each XCD walks a pair of neighbouring
  *       column chunks at a time (blocks are dealt to XCDs round robin),
  *       2 chunk-major over all blocks, 3 each XCD walks one chunk at a time.
@@ -165,7 +168,8 @@ pdz_status pdz_hv_set_plan(pdz_problem p, pdz_dtype dt, const pdz_hv_plan* plan)
  * buffers x, y (D elements each, not overlapping; x is read, y overwritten),
  * `reps` launches each after one warm-up launch, HIP events on `stream`;
  * select the fastest with pdz_hv_set_plan and return it in *best.  trials
- * (may be NULL) receives up to max_trials timings, *n_trials their count.
+ * (may be NULL) receives up to max_trials timings; *n_trials is the number of
+ * plans timed, which may exceed max_trials.
  * Synchronous. */
 pdz_status pdz_hv_tune(pdz_problem p, pdz_dtype dt, const void* x, void* y, int32_t reps, pdz_hv_trial* trials,
                        int32_t max_trials, int32_t* n_trials, pdz_hv_plan* best, void* stream);

@@ -110,14 +110,15 @@ class Problem:
             x = torch.empty(self.D, dtype=tdt, device="cuda").uniform_(-1.0, 1.0)
         if y is None:
             y = torch.empty_like(x)
-        trials = (_lib.HvTrial * 128)()
+        cap = 256
+        trials = (_lib.HvTrial * cap)()
         n = ctypes.c_int32()
         best = _lib.HvPlan()
         _lib.check(lib().pdz_hv_tune(self._h, _dtype_code(dtype), ctypes.c_void_p(x.data_ptr()),
-                                     ctypes.c_void_p(y.data_ptr()), int(reps), trials, 128, ctypes.byref(n),
+                                     ctypes.c_void_p(y.data_ptr()), int(reps), trials, cap, ctypes.byref(n),
                                      ctypes.byref(best), _stream_handle(stream)))
         out = [{"down": trials[k].plan.down, "up_cw": trials[k].plan.up_cw, "up": trials[k].plan.up,
-                "map": trials[k].plan.map, "ms": trials[k].ms} for k in range(n.value)]
+                "map": trials[k].plan.map, "ms": trials[k].ms} for k in range(min(n.value, cap))]
         return {"down": best.down, "up_cw": best.up_cw, "up": best.up, "map": best.map}, out
 
     def kernel_times(self, dtype, reps=10, stream=None):

@@ -42,6 +42,7 @@ struct DownArgs {
     const E* dn_ell;
     uint32_t tmask;   // target mask of an entry
     int cshift;       // amplitude index = entry >> cshift
+    uint32_t ell_bytes;   // size of dn_ell (16-bit tables; 0 otherwise)
     const T* coef;
     int ncoef;
     int rows;         // rows staged per group
@@ -125,10 +126,57 @@ __device__ __forceinline__ void block_dot_store(double v, double* out) {
 
 // ---------------------------------------------------------------- down pass
 
-// Long rows: R (1 or 2) consecutive rows staged interleaved as
+// Long rows: R (1 to 3) consecutive rows staged interleaved as
 // lds[d * R + r]; each thread owns columns d and accumulates R outputs, so one
 // table entry and one LDS gather serve R rows.  The rows of the next group are
 // loaded into registers (up to PER per thread) while the current group computes.
+// Four hops from two slot-pair words: acc[r] += c_h * row_r[target_h], in
+// slot order.
+template <typename T, int R>
+__device__ __forceinline__ void hops4(T (&acc)[R], const T* coef, const T* rows, uint32_t w0, uint32_t w1,
+                                      uint32_t tmask, int cshift) {
+    const uint32_t e0 = w0 & 0xFFFFu, e1 = w0 >> 16, e2 = w1 & 0xFFFFu, e3 = w1 >> 16;
+    const T c0 = coef[e0 >> cshift], c1 = coef[e1 >> cshift], c2 = coef[e2 >> cshift], c3 = coef[e3 >> cshift];
+    const T* s0 = rows + (size_t)(e0 & tmask) * R;
+    const T* s1 = rows + (size_t)(e1 & tmask) * R;
+    const T* s2 = rows + (size_t)(e2 & tmask) * R;
+    const T* s3 = rows + (size_t)(e3 & tmask) * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        acc[r] += c0 * s0[r];
+        acc[r] += c1 * s1[r];
+        acc[r] += c2 * s2[r];
+        acc[r] += c3 * s3[r];
+    }
+}
+
+// The last n (1 to 3) hops of a column; slots past n read entry 0.
+template <typename T, int R>
+__device__ __forceinline__ void hops_tail(T (&acc)[R], const T* coef, const T* rows, uint32_t w0, uint32_t w1, int n,
+                                          uint32_t tmask, int cshift) {
+    const uint32_t e0 = w0 & 0xFFFFu;
+    const uint32_t e1 = n > 1 ? w0 >> 16 : 0u;
+    const uint32_t e2 = n > 2 ? w1 & 0xFFFFu : 0u;
+    const T c0 = coef[e0 >> cshift], c1 = coef[e1 >> cshift], c2 = coef[e2 >> cshift];
+    const T* s0 = rows + (size_t)(e0 & tmask) * R;
+    const T* s1 = rows + (size_t)(e1 & tmask) * R;
+    const T* s2 = rows + (size_t)(e2 & tmask) * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        acc[r] += c0 * s0[r];
+        if (n > 1) acc[r] += c1 * s1[r];
+        if (n > 2) acc[r] += c2 * s2[r];
+    }
+}
+
+// Row of flat index k in a group of R rows of Dn elements each.
+template <int R>
+__device__ __forceinline__ uint32_t row_of(uint32_t k, uint32_t Dn) {
+    if (R == 1) return 0u;
+    if (R == 2) return k >= Dn ? 1u : 0u;
+    return k >= 2 * Dn ? 2u : (k >= Dn ? 1u : 0u);
+}
+
 template <typename T, typename E, int R, int MAXH>
 __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E> a, const T* __restrict__ x,
                                                              T* __restrict__ y) {
@@ -140,7 +188,11 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
     const uint32_t Dn = (uint32_t)D_dn;
     const uint64_t ngroups = (D_up + R - 1) / R;
-    constexpr int PER = R == 2 ? (sizeof(T) == 8 ? 8 : 12) : (sizeof(T) == 8 ? 16 : 24);
+    // raw buffer over the 16-bit table (dword 3: the gfx9 untyped 32-bit format)
+    const __amdgpu_buffer_rsrc_t ell_rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<E*>(a.dn_ell), (short)0, (int)a.ell_bytes, 0x00020000);
+    static_assert(R >= 1 && R <= 3, "rows per group");
+    constexpr int PER = R >= 2 ? (sizeof(T) == 8 ? 8 : 12) : (sizeof(T) == 8 ? 16 : 24);
     T pre[PER];
     double dsum = 0.0;   // x . y over this work group's elements (when a.dotp is set)
     auto fetch = [&](uint64_t g) {
@@ -162,7 +214,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
         for (int i = 0; i < PER; ++i) {
             const uint32_t k = threadIdx.x + (uint32_t)i * kWideBlock;
             if (k < (uint32_t)R * Dn) {
-                const uint32_t r = (R == 2 && k >= Dn) ? 1u : 0u;
+                const uint32_t r = row_of<R>(k, Dn);
                 rows[(size_t)(k - r * Dn) * R + r] = pre[i];
             }
         }
@@ -170,7 +222,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
             const uint64_t nelem = (uint64_t)nr * D_dn;
             const T* base = x + u0 * D_dn;
             for (uint32_t k = threadIdx.x + (uint32_t)PER * kWideBlock; k < (uint32_t)R * Dn; k += kWideBlock) {
-                const uint32_t r = (R == 2 && k >= Dn) ? 1u : 0u;
+                const uint32_t r = row_of<R>(k, Dn);
                 rows[(size_t)(k - r * Dn) * R + r] = (k < nelem) ? base[k] : (T)0;
             }
         }
@@ -202,6 +254,48 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
 #pragma unroll
                         for (int r = 0; r < R; ++r) acc[r] += c * sv[r];
                     }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (r < nr) {
+                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                        dsum += (double)rows[(size_t)d * R + r] * (double)acc[r];
+                    }
+                continue;
+            }
+            if constexpr (sizeof(E) == 2) {
+                // Slot-pair words of four hops at a time, in two register
+                // sets: the words of the group after next are loaded while a
+                // group computes.  Slots past the count load pair 0 instead
+                // (no branch around a load, so the wait before a group covers
+                // only its own words).  Buffer loads (range-checked against
+                // the table size) keep the compiler from merging the two
+                // loads that feed a loop-carried word into one load at its
+                // use, which would undo the prefetch.  The last one to three
+                // hops form one group whose missing slots use entry 0 (an
+                // address inside the staged rows) and add nothing.
+                auto ld = [&](int slot) -> uint32_t {
+                    const uint32_t pair = (uint32_t)(slot < cnt ? slot : 0) >> 1;
+                    return __builtin_amdgcn_raw_buffer_load_b32(ell_rs, (pair * Dn + d) * 4u, 0, 0);
+                };
+                uint32_t a0 = ld(0), a1 = ld(2), b0 = ld(4), b1 = ld(6);
+                int h = 0;
+                for (; h + 8 <= cnt; h += 8) {
+                    hops4<T, R>(acc, coef, rows, a0, a1, a.tmask, a.cshift);
+                    a0 = ld(h + 8);
+                    a1 = ld(h + 10);
+                    __builtin_amdgcn_sched_barrier(0);   // issue them before the next group's work
+                    hops4<T, R>(acc, coef, rows, b0, b1, a.tmask, a.cshift);
+                    b0 = ld(h + 12);
+                    b1 = ld(h + 14);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const int left = cnt - h;   // 0 to 7: slots h.. in a0, a1, then b0, b1
+                if (left >= 4) {
+                    hops4<T, R>(acc, coef, rows, a0, a1, a.tmask, a.cshift);
+                    if (left > 4) hops_tail<T, R>(acc, coef, rows, b0, b1, left - 4, a.tmask, a.cshift);
+                } else if (left > 0) {
+                    hops_tail<T, R>(acc, coef, rows, a0, a1, left, a.tmask, a.cshift);
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -340,7 +434,7 @@ struct __align__(16) UpHop<double> {
 // that XCD's L2, and both halves of every 128-byte line are used there.
 // The tile's hop lists are decoded once into LDS.  IDX64 selects 64-bit
 // element offsets (D >= 2^32).
-template <typename T, typename E, int CW, int ROWS_PER_TILE, bool IDX64>
+template <typename T, typename E, int CW, int ROWS_PER_TILE, bool IDX64, int NB>
 __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const T* __restrict__ x, T* __restrict__ y) {
     if (a.skip && *a.skip) return;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -398,20 +492,41 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
         }
         int h = 0;
         if (nv == VEC) {
-            for (; h + 8 <= cnt; h += 8) {
-                T v[8][VEC];
-                T c[8];
+            for (; h + NB <= cnt; h += NB) {
+                T v[NB][VEC];
+                T c[NB];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < NB; ++q) {
                     const UpHop<T> hq = hp[h + q];
                     c[q] = hq.c;
                     const T* src = IDX64 ? x + o64[h + q] + d : x + (uint32_t)(hq.off + (uint32_t)d);
                     vec_load<T, VEC>(src, v[q]);
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
+                for (int q = 0; q < NB; ++q)
 #pragma unroll
                     for (int i = 0; i < VEC; ++i) acc[i] += c[q] * v[q][i];
+            }
+            if (h < cnt) {
+                // the last cnt - h (< NB) hops as one batch: every load issued
+                // before the first multiply-add; slots past the count reload
+                // hop h and their products are not added
+                T v[NB][VEC];
+                T c[NB];
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    const int k = h + q < cnt ? h + q : h;
+                    const UpHop<T> hq = hp[k];
+                    c[q] = hq.c;
+                    const T* src = IDX64 ? x + o64[k] + d : x + (uint32_t)(hq.off + (uint32_t)d);
+                    vec_load<T, VEC>(src, v[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (h + q < cnt)
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) acc[i] += c[q] * v[q][i];
+                h = cnt;
             }
         }
         for (; h < cnt; ++h) {
@@ -584,7 +699,8 @@ void fill_table_view(const SectorTables& t, bool compact, const E** ell, uint32_
 }
 
 // Down-pass variant: 1 = one row, table loaded up front (compile-time bound
-// on the hop slots); 2 = one row, table in a loop; 3 = two rows, loop.
+// on the hop slots); 2 = one row, table in a loop; 3 = two rows, loop;
+// 4 = three rows, loop.
 template <typename T, typename E>
 void launch_wide(int variant, int max_hops, uint64_t grid, size_t lds, hipStream_t s, const DownArgs<T, E>& da,
                  const T* x, T* y) {
@@ -597,6 +713,8 @@ void launch_wide(int variant, int max_hops, uint64_t grid, size_t lds, hipStream
         hipLaunchKernelGGL((k_hv_down_wide<T, E, 1, 48>), g, b, lds, s, da, x, y);
     else if (variant == 3)
         hipLaunchKernelGGL((k_hv_down_wide<T, E, 2, 0>), g, b, lds, s, da, x, y);
+    else if (variant == 4)
+        hipLaunchKernelGGL((k_hv_down_wide<T, E, 3, 0>), g, b, lds, s, da, x, y);
     else
         hipLaunchKernelGGL((k_hv_down_wide<T, E, 1, 0>), g, b, lds, s, da, x, y);
 }
@@ -617,14 +735,17 @@ pdz_status set_wide_lds() {
 template <typename T>
 constexpr int up_rows() { return 8; }
 
+// nb: hop loads in flight per batch (8, or 16 with 32-bit offsets)
 template <typename T, typename E, int CW>
-void launch_up(bool idx64, uint64_t blocks, size_t lds, hipStream_t s, const UpArgs<T, E>& ua, const T* x, T* y) {
+void launch_up(bool idx64, int nb, uint64_t blocks, size_t lds, hipStream_t s, const UpArgs<T, E>& ua, const T* x,
+               T* y) {
+    const dim3 g((unsigned)blocks), b(kUpBlock);
     if (idx64)
-        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), true>), dim3((unsigned)blocks), dim3(kUpBlock), lds, s, ua,
-                           x, y);
+        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), true, 8>), g, b, lds, s, ua, x, y);
+    else if (nb == 16)
+        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), false, 16>), g, b, lds, s, ua, x, y);
     else
-        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), false>), dim3((unsigned)blocks), dim3(kUpBlock), lds, s,
-                           ua, x, y);
+        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), false, 8>), g, b, lds, s, ua, x, y);
 }
 
 template <typename T, typename E, int CW>
@@ -677,6 +798,8 @@ HvPlan hv_resolve(const pdz_problem_s* p, pdz_dtype dt) {
     return pl;
 }
 
+int down_rows(int variant) { return variant == 4 ? 3 : variant == 3 ? 2 : 1; }
+
 // Down-pass launch geometry (also the number of x . y partial sums it writes).
 struct DownGeom {
     bool wide = false;    // k_hv_down_wide (rows at least one work group wide, staged in LDS)
@@ -693,7 +816,7 @@ DownGeom down_geom(const pdz_problem_s* p, size_t es, const HvPlan& plan, unsign
     const size_t row_bytes = (size_t)D_dn * es;
     if (D_dn >= (uint64_t)kWideBlock && row_bytes <= lds_cap) {
         g.wide = g.stage = true;
-        g.rows = plan.down == 3 ? 2 : 1;
+        g.rows = down_rows(plan.down);
         g.lds = kMaxCoef * es + (size_t)g.rows * row_bytes;
         const uint64_t ngroups = (D_up + g.rows - 1) / g.rows;
         const unsigned per_cu = (unsigned)(kLdsBytes / (g.lds + 256));
@@ -748,6 +871,7 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     da.dn_states = p->dn.states;
     da.dn_count = p->dn.count;
     fill_table_view<T, E>(p->dn, compact, &da.dn_ell, &da.tmask, &da.cshift);
+    da.ell_bytes = compact ? (uint32_t)(((uint64_t)(p->dn.max_hops + 1) & ~1ull) * D_dn * sizeof(uint16_t)) : 0u;
     da.coef = coef;
     da.ncoef = ncoef;
     da.skip = skip;
@@ -798,6 +922,7 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     const size_t lds = (size_t)ROWS * ua.max_hops * (sizeof(UpHop<T>) + (idx64 ? 8 : 0)) + ROWS * sizeof(int);
     ua.map = plan.map;
     const uint64_t blocks = up_blocks(p, sizeof(T), plan);
+    const int nb = plan.up == 3 ? 16 : 8;
     if (plan.up == 2 && !idx64) {
         // preloaded rows: one column per lane (CW <= 64)
         if (sizeof(T) == 8 && CW == 16)
@@ -808,22 +933,22 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
             launch_up_pre<T, E, 64>(ua.max_hops, blocks, lds, s, ua, x, yout);
     } else if (sizeof(T) == 8) {
         if (CW == 16)
-            launch_up<T, E, 16>(idx64, blocks, lds, s, ua, x, yout);
+            launch_up<T, E, 16>(idx64, nb, blocks, lds, s, ua, x, yout);
         else if (CW == 32)
-            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, yout);
+            launch_up<T, E, 32>(idx64, nb, blocks, lds, s, ua, x, yout);
         else if (CW == 64)
-            launch_up<T, E, 64>(idx64, blocks, lds, s, ua, x, yout);
+            launch_up<T, E, 64>(idx64, nb, blocks, lds, s, ua, x, yout);
         else
-            launch_up<T, E, 128>(idx64, blocks, lds, s, ua, x, yout);
+            launch_up<T, E, 128>(idx64, nb, blocks, lds, s, ua, x, yout);
     } else {
         if (CW == 32)
-            launch_up<T, E, 32>(idx64, blocks, lds, s, ua, x, yout);
+            launch_up<T, E, 32>(idx64, nb, blocks, lds, s, ua, x, yout);
         else if (CW == 64)
-            launch_up<T, E, 64>(idx64, blocks, lds, s, ua, x, yout);
+            launch_up<T, E, 64>(idx64, nb, blocks, lds, s, ua, x, yout);
         else if (CW == 128)
-            launch_up<T, E, 128>(idx64, blocks, lds, s, ua, x, yout);
+            launch_up<T, E, 128>(idx64, nb, blocks, lds, s, ua, x, yout);
         else
-            launch_up<T, E, 256>(idx64, blocks, lds, s, ua, x, yout);
+            launch_up<T, E, 256>(idx64, nb, blocks, lds, s, ua, x, yout);
     }
     PDZ_HIP(hipGetLastError());
     return ok();
@@ -860,9 +985,11 @@ pdz_status run_hv(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipSt
 
 template <typename T, typename E, int CW>
 pdz_status set_up_lds() {
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), false>),
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), false, 8>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), true>),
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), false, 16>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), true, 8>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     return ok();
 }
@@ -888,6 +1015,7 @@ pdz_status prepare_one() {
         if (st == PDZ_OK) st = set_wide_lds<T, E, 1, 32>();
         if (st == PDZ_OK) st = set_wide_lds<T, E, 1, 48>();
     }
+    if (st == PDZ_OK) st = set_wide_lds<T, E, 3, 0>();
     if (st != PDZ_OK) return st;
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_narrow<T, E, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
@@ -923,6 +1051,7 @@ std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
         if (compact && p->dn.max_hops <= 48) downs.push_back(1);
         downs.push_back(2);
         if (row_fits(p, es, 2) && p->up.D >= 2) downs.push_back(3);
+        if (row_fits(p, es, 3) && p->up.D >= 3) downs.push_back(4);
     } else {
         downs.push_back(d.down);
     }
@@ -930,7 +1059,7 @@ std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
     const bool pre_ok = p->up.max_hops <= 48 && p->D <= 0xFFFFFFFFull;
     for (int dv : downs)
         for (int k = 0; k < kNumCw; ++k)
-            for (int um = 1; um <= 2; ++um)
+            for (int um = 1; um <= 3; ++um)
                 for (int mp = 1; mp <= 3; ++mp) {
                     HvPlan c;
                     c.down = dv;
@@ -938,6 +1067,7 @@ std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
                     c.up = um;
                     c.map = mp;
                     if (um == 2 && (!pre_ok || cws[k] > 64)) continue;
+                    if (um == 3 && p->D > 0xFFFFFFFFull) continue;
                     if (c.down != d.down || c.up_cw != d.up_cw || c.up != d.up || c.map != d.map) out.push_back(c);
                 }
     return out;

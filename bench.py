@@ -28,12 +28,13 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_NAMES = {"down": "k_hv_down_wide", "up": "k_hv_up / k_hv_up_pre"}
 
 
-def recorded_traffic(workload, kernel):
+def recorded_traffic(workload, kernel, plan):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None.
 
     The summary (profiles/hv_traffic_<workload>.txt) holds FETCH_SIZE and
-    WRITE_SIZE per dispatch scaled by a plain copy's reading, and the SHA-1 of
-    the H.v kernel source it was taken with; a changed source gives None.
+    WRITE_SIZE per dispatch scaled by a plain copy's reading, the SHA-1 of the
+    H.v kernel source and the tuned launch plan it was taken with; a changed
+    source or a different plan gives None.
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", f"hv_traffic_{workload}.txt")
@@ -49,7 +50,7 @@ def recorded_traffic(workload, kernel):
     with open(src, "rb") as f:
         sha = hashlib.sha1(f.read()).hexdigest()
     k = rec.get("kernels", {}).get(kernel)
-    if rec.get("source_sha1") != sha or not k:
+    if rec.get("source_sha1") != sha or not k or rec.get("plans", {}).get("f32") != plan:
         return None
     return k["fetch_bytes"] + k["write_bytes"]
 
@@ -352,7 +353,7 @@ def main():
     dom = "up" if kt32["up"] >= kt32["down"] else "down"
     kbytes = {"down": 2.0 * D * 4, "up": 3.0 * D * 4}
     ach_dom = kbytes[dom] / (kt32[dom] * 1e-3) / 1e9
-    traffic = recorded_traffic(w.name, dom + "_f32")
+    traffic = recorded_traffic(w.name, dom + "_f32", tuned["f32"]["best"])
 
     copy = None
     if args.calibrate_copy:

@@ -6,9 +6,10 @@ Workload (default): 4x4 periodic cluster with nearest (t=1) and next-nearest
 nnz = 11,473,115,940 per H.v.  Synthetic seeded input; nothing is read from
 disk.
 
-One timed step = one Lanczos step of the library (H.v, alpha dot, three-term
-update with |w|, tridiagonal eigensolve, normalisation), replayed from a
-captured HIP graph.  `value` = H.v nonzeros processed per second over the
+One timed step = one Lanczos step of the library (H.v in two passes that also
+form the partial sums of alpha, the three-term update on unnormalised vectors
+with |w|, the tridiagonal eigensolve and the next scale factor), replayed from
+a captured HIP graph.  `value` = H.v nonzeros processed per second over the
 timed steps, with the Krylov vectors stored in FP32 (FP64 scalars); the FP64
 path is reported beside it.  Prints one JSON line.
 """

@@ -172,14 +172,29 @@ __device__ __forceinline__ T update_one(T wi, T zi, T qi, T qpi, double a, doubl
 // two per thread and array in flight; the last D mod (16 / sizeof(T))
 // elements go one per thread.  Each block's partial sums a fixed set of
 // elements in a fixed order.
+constexpr int kUpdBlock = 512;   // 32 waves per CU at kRedGrid work groups: more loads in flight
+
+// Sum over a work group of BLOCK threads (fixed order), valid in thread 0.
+template <int BLOCK>
+__device__ __forceinline__ double block_sum_waves(double v) {
+    __shared__ double ws[BLOCK / 64];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < BLOCK / 64; ++i) t += ws[i];
+    return t;
+}
+
 template <typename T, bool HZ>
-__global__ __launch_bounds__(kRedBlock) void k_update_scaled(T* __restrict__ w, const T* __restrict__ z,
+__global__ __launch_bounds__(kUpdBlock) void k_update_scaled(T* __restrict__ w, const T* __restrict__ z,
                                                              const T* __restrict__ q, const T* __restrict__ qp,
                                                              uint64_t D, const double* alpha, const double* beta,
                                                              const double* sc, const int* kidx, double* partial,
                                                              const int* skip, int vec) {
     if (skip && *skip) return;
-    __shared__ double red[kRedBlock];
     const int k = *kidx;
     const double a = sc[k];
     const double b = alpha[k] * sc[k];
@@ -225,7 +240,7 @@ __global__ __launch_bounds__(kRedBlock) void k_update_scaled(T* __restrict__ w, 
         i = nv * N + tid;   // the ragged tail
     }
     for (; i < D; i += stride) w[i] = update_one<T, HZ>(w[i], HZ ? z[i] : T(0), q[i], qp[i], a, b, c, acc);
-    acc = block_sum(acc, red);
+    acc = block_sum_waves<kUpdBlock>(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
@@ -236,10 +251,10 @@ void launch_update_scaled(T* w, const T* z, const T* q, const T* qp, uint64_t D,
     auto al = [](const void* x) { return ((uintptr_t)x & 15) == 0; };
     const int vec = al(w) && al(q) && al(qp) && (!z || al(z));
     if (z)
-        hipLaunchKernelGGL((k_update_scaled<T, true>), dim3(kRedGrid), dim3(kRedBlock), 0, s, w, z, q, qp, D, alpha,
+        hipLaunchKernelGGL((k_update_scaled<T, true>), dim3(kRedGrid), dim3(kUpdBlock), 0, s, w, z, q, qp, D, alpha,
                            beta, sc, kidx, partial, skip, vec);
     else
-        hipLaunchKernelGGL((k_update_scaled<T, false>), dim3(kRedGrid), dim3(kRedBlock), 0, s, w, z, q, qp, D, alpha,
+        hipLaunchKernelGGL((k_update_scaled<T, false>), dim3(kRedGrid), dim3(kUpdBlock), 0, s, w, z, q, qp, D, alpha,
                            beta, sc, kidx, partial, skip, vec);
 }
 

@@ -164,23 +164,27 @@ def batched_bench(torch, pdz, synth, reps, rel=1e-8):
     E_ref = [r["E0"] for r in ref]
     out["E0_ref_iters_max"] = max(r["iters"] for r in ref)
 
-    def run_batch(storage):
+    def run_batch(storage, refine=0):
+        key = "E0_refined" if refine else "E0"
+
         def run(tol):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            res, _ = b.lanczos(storage=storage, tol=tol, max_iter=800)
+            res, _ = b.lanczos(storage=storage, tol=tol, max_iter=800, refine=refine)
             torch.cuda.synchronize()
-            return time.perf_counter() - t0, [r["E0"] for r in res], max(r["iters"] for r in res)
+            return time.perf_counter() - t0, [r[key] for r in res], max(r["iters"] for r in res)
         return run
 
-    def run_single(storage):
+    def run_single(storage, refine=0):
+        key = "E0_refined" if refine else "E0"
+
         def run(tol):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             E, it = [], 0
             for i, q in enumerate(probs):
-                r = q.lanczos(storage=storage, tol=tol, max_iter=800, seed=1 + i)
-                E.append(r["E0"])
+                r = q.lanczos(storage=storage, tol=tol, max_iter=800, seed=1 + i, refine=refine)
+                E.append(r[key])
                 it = max(it, r["iters"])
             torch.cuda.synchronize()
             return time.perf_counter() - t0, E, it
@@ -188,7 +192,9 @@ def batched_bench(torch, pdz, synth, reps, rel=1e-8):
 
     b.lanczos(storage="f64", tol=1e-6, max_iter=800)   # warm-up (graph instantiation paths)
     for key, fn in (("batched_f64", run_batch("f64")), ("batched_f32", run_batch("f32")),
-                    ("single_f64", run_single("f64")), ("single_f32", run_single("f32"))):
+                    ("batched_f32_refined", run_batch("f32", 1)),
+                    ("single_f64", run_single("f64")), ("single_f32", run_single("f32")),
+                    ("single_f32_refined", run_single("f32", 1))):
         tol, secs, err, iters = _tol_to_rel(fn, E_ref, rel)
         out["time_to_E0_1e-8_" + key] = {"seconds": secs, "tol": tol, "max_rel_err": err, "max_iters": iters,
                                          "met": err <= rel}

@@ -307,8 +307,13 @@ pdz_status pdz_batch_lanczos_workspace_size(pdz_batch b, const pdz_lanczos_opts*
  * of check_every steps (rounded up to a multiple of 3) are replayed as one
  * captured HIP graph.  Problem i starts from the seeded vector of seed + i
  * (the pdz_lanczos start vector of that seed), so its result equals a
- * pdz_lanczos run with that seed up to summation order.  reorth and refine
- * must be 0.  ws: caller-owned device workspace, 256-byte aligned.
+ * pdz_lanczos run with that seed up to summation order.  reorth must be 0.
+ * refine = 1: after the run, every problem's Lanczos vectors are regenerated
+ * bit for bit from its start vector and stored alpha, beta, its Ritz vector
+ * is accumulated in FP64 and normalised, and E0_refined / resid_refined are
+ * its FP64 Rayleigh quotient and residual (one batched FP64 H.v); the
+ * workspace then includes two FP64 packed vectors.  ws: caller-owned device
+ * workspace, 256-byte aligned.
  * results: host array of n entries.  Synchronous.
  * Errors: PDZ_EINVAL (bad options, workspace too small, non-finite scalar);
  * PDZ_ENOCONV when some problem reached max_iter (results still hold every

@@ -315,6 +315,100 @@ __global__ __launch_bounds__(kRed) void k_btridiag(BCtl* ctl, const double* alph
     }
 }
 
+// ---- FP64 refinement of the Ritz vectors (storage FP32 or FP64)
+
+// kfin[p] = steps the run took; counters restart for the regeneration pass.
+__global__ void k_bregen_init(BCtl* ctl, int* kfin, uint32_t n) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int k = ctl[p].k;
+    kfin[p] = k;
+    ctl[p].k = 0;
+    ctl[p].done = k > 0 ? 0 : 1;
+}
+
+// y += s_k v_k (FP64) for every live cluster, s = row p of svec (eigenvector of T_kfin).
+template <typename T>
+__global__ __launch_bounds__(kRed) void k_baxpy_ritz(const BChunk* ch, const BProb* probs, const BCtl* ctl,
+                                                     const double* svec, int ld, const T* v, double* y) {
+    const BChunk c = ch[blockIdx.x];
+    const BCtl st = ctl[c.prob];
+    if (st.done) return;
+    const double sk = svec[(size_t)c.prob * ld + st.k];
+    const uint64_t off = probs[c.prob].off;
+    for (uint64_t i = c.begin + threadIdx.x; i < c.end; i += blockDim.x) y[off + i] += sk * (double)v[off + i];
+}
+
+// A cluster whose last Lanczos vector has been added needs no further one.
+__global__ void k_bregen_mark(BCtl* ctl, const int* kfin, uint32_t n) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n || ctl[p].done) return;
+    if (ctl[p].k + 1 >= kfin[p]) ctl[p].done = 1;
+}
+
+// v_{k+1} from w = H v_k with the stored alpha_k, beta_k, beta_{k+1}: the same
+// two roundings as the run (recurrence, then scaling), so the vectors are the
+// run's bit for bit.
+template <typename T>
+__global__ __launch_bounds__(kRed) void k_bregen_update(const BChunk* ch, const BProb* probs, const BCtl* ctl,
+                                                        const double* alpha, const double* beta, int ld, T* w,
+                                                        const T* v, const T* vp) {
+    const BChunk c = ch[blockIdx.x];
+    const BCtl st = ctl[c.prob];
+    if (st.done) return;
+    const size_t row = (size_t)c.prob * ld;
+    const double a = alpha[row + st.k], bt = beta[row + st.k];
+    const double inv = 1.0 / beta[row + st.k + 1];
+    const uint64_t off = probs[c.prob].off;
+    for (uint64_t i = c.begin + threadIdx.x; i < c.end; i += blockDim.x) {
+        const T r = (T)((double)w[off + i] - a * (double)v[off + i] - bt * (double)vp[off + i]);
+        w[off + i] = (T)((double)r * inv);
+    }
+}
+
+__global__ void k_bregen_next(BCtl* ctl, uint32_t n) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n || ctl[p].done) return;
+    ctl[p].k += 1;
+}
+
+// Every cluster that ran at least one step is live again.
+__global__ void k_bregen_reopen(BCtl* ctl, const int* kfin, uint32_t n) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    ctl[p].k = 0;
+    ctl[p].done = kfin[p] > 0 ? 0 : 1;
+}
+
+// out[p] = sum of the chunk partials of cluster p (sqrt when root).
+__global__ __launch_bounds__(kRed) void k_bsum_out(const uint32_t* ch_begin, const double* partial, const BCtl* ctl,
+                                                   double* out, int root) {
+    __shared__ double red[kRed];
+    const uint32_t p = blockIdx.x;
+    if (ctl[p].done) return;
+    double acc = 0.0;
+    for (uint32_t c = ch_begin[p] + threadIdx.x; c < ch_begin[p + 1]; c += blockDim.x) acc += partial[c];
+    acc = bsum(acc, red);
+    if (threadIdx.x == 0) out[p] = root ? sqrt(acc) : acc;
+}
+
+// partial[c] = |hy - E_p y|^2 over chunk c.
+__global__ __launch_bounds__(kRed) void k_bresid(const BChunk* ch, const BProb* probs, const BCtl* ctl,
+                                                 const double* hy, const double* y, const double* E, double* partial) {
+    __shared__ double red[kRed];
+    const BChunk c = ch[blockIdx.x];
+    if (ctl[c.prob].done) return;
+    const double e = E[c.prob];
+    const uint64_t off = probs[c.prob].off;
+    double acc = 0.0;
+    for (uint64_t i = c.begin + threadIdx.x; i < c.end; i += blockDim.x) {
+        const double r = hy[off + i] - e * y[off + i];
+        acc += r * r;
+    }
+    acc = bsum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr size_t kBatchLds = 159 * 1024;   // dynamic LDS limit: 160 KiB less the static queue slot
@@ -460,6 +554,7 @@ pdz_status batch_hv_any(pdz_batch_s* b, pdz_dtype dt, const void* x, void* y, hi
 
 struct BLayout {
     size_t vec = 0, buf[3] = {0, 0, 0}, alpha = 0, beta = 0, svec = 0, partial = 0, ctl = 0, total = 0;
+    size_t y = 0, hy = 0, kfin = 0, eref = 0;   // refinement (refine == 1)
     int ld = 0;
 };
 
@@ -484,6 +579,16 @@ BLayout blayout(const pdz_batch_s* b, const pdz_lanczos_opts* o) {
     off += al256((size_t)b->nchunks * 8);
     L.ctl = off;
     off += al256((size_t)b->n * sizeof(BCtl));
+    if (o->refine) {
+        L.y = off;
+        off += al256(b->total * 8);
+        L.hy = off;
+        off += al256(b->total * 8);
+        L.kfin = off;
+        off += al256((size_t)b->n * sizeof(int));
+        L.eref = off;
+        off += al256((size_t)b->n * 2 * 8);
+    }
     L.total = off;
     return L;
 }
@@ -593,6 +698,7 @@ pdz_status batch_lanczos_run(pdz_batch_s* b, const pdz_lanczos_opts* o, char* ws
         return fail(PDZ_EINVAL, "non-finite Lanczos scalar (start vector or H)");
     }
     bool all_conv = true;
+    int kmax = 0;
     for (int i = 0; i < b->n; ++i) {
         if (!(h[i].norm0 > 0.0) || !std::isfinite(h[i].norm0))
             return fail(PDZ_EINVAL, "a start vector has zero or non-finite norm");
@@ -603,6 +709,61 @@ pdz_status batch_lanczos_run(pdz_batch_s* b, const pdz_lanczos_opts* o, char* ws
         res[i].iters = h[i].k;
         res[i].converged = h[i].converged;
         all_conv = all_conv && h[i].converged;
+        kmax = std::max(kmax, h[i].k);
+    }
+    if (o->refine && kmax > 0) {
+        // Ritz vector y_p = sum_j s_{p,j} v_{p,j} in FP64 from the regenerated
+        // Lanczos vectors, normalised; its FP64 Rayleigh quotient and residual.
+        double* y = reinterpret_cast<double*>(ws + L.y);
+        double* hy = reinterpret_cast<double*>(ws + L.hy);
+        int* kfin = reinterpret_cast<int*>(ws + L.kfin);
+        double* eref = reinterpret_cast<double*>(ws + L.eref);
+        const dim3 npg((b->n + 255) / 256), b256(256);
+        hipLaunchKernelGGL(k_bregen_init, npg, b256, 0, s, ctl, kfin, (uint32_t)b->n);
+        hipLaunchKernelGGL(k_bzero<T>, dim3(1024), blk, 0, s, b->total, buf[0], buf[2]);
+        hipLaunchKernelGGL(k_bzero<double>, dim3(1024), blk, 0, s, b->total, y, hy);
+        hipLaunchKernelGGL(k_bfill<T>, nch, blk, 0, s, b->d_chunks, b->d_probs, o->seed, buf[0]);
+        hipLaunchKernelGGL(k_bdot<T>, nch, blk, 0, s, b->d_chunks, b->d_probs, ctl, buf[0], buf[0], partial);
+        hipLaunchKernelGGL(k_bfinal, np, blk, 0, s, b->d_chunk_begin, partial, ctl, alpha, beta, ld, 2, err);
+        hipLaunchKernelGGL(k_bscale<T>, nch, blk, 0, s, b->d_chunks, b->d_probs, ctl, beta, ld, 0, 1, buf[0]);
+        for (int j = 0; j < kmax; ++j) {
+            const int a = j % 3;
+            T* v = buf[a];
+            T* vp = buf[(a + 2) % 3];
+            T* w = buf[(a + 1) % 3];
+            hipLaunchKernelGGL(k_baxpy_ritz<T>, nch, blk, 0, s, b->d_chunks, b->d_probs, ctl, svec, ld, v, y);
+            if (j + 1 >= kmax) break;
+            hipLaunchKernelGGL(k_bregen_mark, npg, b256, 0, s, ctl, kfin, (uint32_t)b->n);
+            st = batch_hv_any(b, dt, v, w, s, done, dstride);
+            if (st != PDZ_OK) return st;
+            hipLaunchKernelGGL(k_bregen_update<T>, nch, blk, 0, s, b->d_chunks, b->d_probs, ctl, alpha, beta, ld, w,
+                               v, vp);
+            hipLaunchKernelGGL(k_bregen_next, npg, b256, 0, s, ctl, (uint32_t)b->n);
+        }
+        hipLaunchKernelGGL(k_bregen_reopen, npg, b256, 0, s, ctl, kfin, (uint32_t)b->n);
+        hipLaunchKernelGGL(k_bdot<double>, nch, blk, 0, s, b->d_chunks, b->d_probs, ctl, y, y, partial);
+        hipLaunchKernelGGL(k_bfinal, np, blk, 0, s, b->d_chunk_begin, partial, ctl, alpha, beta, ld, 2, err);
+        hipLaunchKernelGGL(k_bscale<double>, nch, blk, 0, s, b->d_chunks, b->d_probs, ctl, beta, ld, 0, 1, y);
+        st = batch_hv_any(b, PDZ_F64, y, hy, s, done, dstride);
+        if (st != PDZ_OK) return st;
+        hipLaunchKernelGGL(k_bdot<double>, nch, blk, 0, s, b->d_chunks, b->d_probs, ctl, y, hy, partial);
+        hipLaunchKernelGGL(k_bsum_out, np, blk, 0, s, b->d_chunk_begin, partial, ctl, eref, 0);
+        hipLaunchKernelGGL(k_bresid, nch, blk, 0, s, b->d_chunks, b->d_probs, ctl, hy, y, eref, partial);
+        hipLaunchKernelGGL(k_bsum_out, np, blk, 0, s, b->d_chunk_begin, partial, ctl, eref + b->n, 1);
+        PDZ_HIP(hipGetLastError());
+        std::vector<double> er(2 * (size_t)b->n);
+        std::vector<int> kf(b->n);
+        PDZ_HIP(hipMemcpyAsync(er.data(), eref, er.size() * 8, hipMemcpyDeviceToHost, s));
+        PDZ_HIP(hipMemcpyAsync(kf.data(), kfin, kf.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+        PDZ_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < b->n; ++i)
+            if (kf[i] > 0) {
+                res[i].E0_refined = er[i];
+                res[i].resid_refined = er[b->n + i];
+            }
+        // leave the control blocks as the run ended
+        PDZ_HIP(hipMemcpyAsync(ctl, h.data(), b->n * sizeof(BCtl), hipMemcpyHostToDevice, s));
+        PDZ_HIP(hipStreamSynchronize(s));
     }
     return all_conv ? ok() : fail(PDZ_ENOCONV, "max_iter reached before every cluster met the tolerance");
 }
@@ -823,8 +984,8 @@ pdz_status pdz_batch_lanczos(pdz_batch b, const pdz_lanczos_opts* o, void* ws, s
     if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(PDZ_EINVAL, "tol must be finite and >= 0");
     if (o->storage != PDZ_F64 && o->storage != PDZ_F32) return fail(PDZ_EINVAL, "storage must be F64 or F32");
     if (o->check_every < 1) return fail(PDZ_EINVAL, "check_every must be >= 1");
-    if (o->reorth != 0 || o->refine != 0)
-        return fail(PDZ_EINVAL, "batched Lanczos runs the three-term recurrence without refinement");
+    if (o->reorth != 0) return fail(PDZ_EINVAL, "batched Lanczos runs the three-term recurrence (reorth must be 0)");
+    if (o->refine != 0 && o->refine != 1) return fail(PDZ_EINVAL, "refine must be 0 or 1");
     const BLayout L = blayout(b, o);
     if (!ws || ws_bytes < L.total) return fail(PDZ_EINVAL, "workspace smaller than pdz_batch_lanczos_workspace_size");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PDZ_EINVAL, "workspace must be 256-byte aligned");

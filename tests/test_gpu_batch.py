@@ -202,6 +202,46 @@ def test_batched_lanczos_fp32_storage():
         assert abs(r["E0"] - E[w.name]["E0"]) <= 2e-6 * abs(E[w.name]["E0"]), (w.name, r)
 
 
+def test_batched_fp32_storage_with_fp64_refinement_meets_1e8():
+    """FP32 Krylov vectors, FP64 Ritz vectors rebuilt from the regenerated run: every cluster's
+    Rayleigh quotient within 1e-8 of the oracle's energy."""
+    E = _energies()["batched"]
+    ws = synth.batched_workloads()
+    probs, b = _make([_args(w) for w in ws])
+    res, st = b.lanczos(storage="f32", tol=1e-7, max_iter=600, refine=1)
+    assert st == 0
+    worst_unrefined = 0.0
+    for w, r in zip(ws, res):
+        e = E[w.name]["E0"]
+        assert abs(r["E0_refined"] - e) <= 1e-8 * abs(e), (w.name, r)
+        assert 0.0 <= r["resid_refined"] < 1e-2, (w.name, r)
+        worst_unrefined = max(worst_unrefined, abs(r["E0"] - e) / abs(e))
+    assert worst_unrefined > 1e-8   # the FP32 Ritz values alone do not meet the bound
+
+
+def test_batched_refinement_matches_single_refinement_and_fp64_runs():
+    ws = synth.batched_workloads()[:8]
+    probs, b = _make([_args(w) for w in ws])
+    res, _ = b.lanczos(storage="f32", tol=1e-7, max_iter=400, seed=5, refine=1)
+    for i, (q, r) in enumerate(zip(probs, res)):
+        s = q.lanczos(storage="f32", tol=1e-7, max_iter=400, seed=5 + i, refine=1)
+        assert abs(r["E0_refined"] - s["E0_refined"]) <= 1e-9 * abs(s["E0_refined"]), (i, r, s)
+    # FP64 storage: the rebuilt Ritz vector's Rayleigh quotient is the converged Ritz value
+    res64, _ = b.lanczos(storage="f64", tol=1e-12, max_iter=600, refine=1)
+    for r in res64:
+        assert abs(r["E0_refined"] - r["E0"]) <= 1e-10 * abs(r["E0"]), r
+        assert r["resid_refined"] < 1e-4, r
+
+
+def test_batched_refinement_leaves_energies_and_counts_unchanged():
+    probs, b = _make(_small_batch_args())
+    a, _ = b.lanczos(tol=1e-12, storage="f32")
+    c, _ = b.lanczos(tol=1e-12, storage="f32", refine=1)
+    assert [r["E0"] for r in a] == [r["E0"] for r in c]
+    assert [r["iters"] for r in a] == [r["iters"] for r in c]
+    assert all(r["resid_refined"] == -1.0 for r in a)
+
+
 def test_batched_errors_and_noconv():
     torch = torch_cuda()
     pdz = _pdz()
@@ -217,7 +257,7 @@ def test_batched_errors_and_noconv():
     with pytest.raises(pdz.PdzError):
         b.lanczos(reorth=1)
     with pytest.raises(pdz.PdzError):
-        b.lanczos(refine=1)
+        b.lanczos(refine=2)
     with pytest.raises(pdz.PdzError):
         b.lanczos(workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
     res, st = b.lanczos(max_iter=4, tol=1e-15)

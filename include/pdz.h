@@ -196,6 +196,9 @@ typedef struct {
     int32_t check_every;   /* host reads the device convergence flag every this many steps (>=1) */
     int32_t use_graph;     /* 1: replay blocks of check_every steps as a captured HIP graph     */
     int32_t refine;        /* 1: build the Ritz vector and return its FP64 Rayleigh quotient    */
+    int32_t keep_basis;    /* 1: keep every Lanczos vector in the workspace (max_iter + 1 of D   */
+                           /*    elements) so that refine combines them in one pass instead of */
+                           /*    regenerating them with a second run of H.v products           */
 } pdz_lanczos_opts;
 
 typedef struct {
@@ -209,7 +212,7 @@ typedef struct {
 } pdz_lanczos_result;
 
 /* Fill *o with defaults: max_iter 300, tol 1e-12, F64, no reorth, seed 1,
- * check_every 10, use_graph 1, refine 0. */
+ * check_every 10, use_graph 1, refine 0, keep_basis 0. */
 pdz_status pdz_lanczos_default_opts(pdz_lanczos_opts* o);
 
 /* Bytes of device workspace pdz_lanczos needs for these options. */
@@ -307,7 +310,8 @@ pdz_status pdz_batch_lanczos_workspace_size(pdz_batch b, const pdz_lanczos_opts*
  * of check_every steps (rounded up to a multiple of 3) are replayed as one
  * captured HIP graph.  Problem i starts from the seeded vector of seed + i
  * (the pdz_lanczos start vector of that seed), so its result equals a
- * pdz_lanczos run with that seed up to summation order.  reorth must be 0.
+ * pdz_lanczos run with that seed up to summation order.  reorth and
+ * keep_basis must be 0.
  * refine = 1: after the run, every problem's Lanczos vectors are regenerated
  * bit for bit from its start vector and stored alpha, beta, its Ritz vector
  * is accumulated in FP64 and normalised, and E0_refined / resid_refined are

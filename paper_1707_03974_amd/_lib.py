@@ -47,7 +47,7 @@ class Info(ctypes.Structure):
 class LanczosOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("storage", ctypes.c_int32),
                 ("reorth", ctypes.c_int32), ("seed", ctypes.c_uint64), ("check_every", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("refine", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("refine", ctypes.c_int32), ("keep_basis", ctypes.c_int32)]
 
 
 class LanczosResult(ctypes.Structure):

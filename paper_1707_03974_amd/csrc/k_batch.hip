@@ -986,6 +986,7 @@ pdz_status pdz_batch_lanczos(pdz_batch b, const pdz_lanczos_opts* o, void* ws, s
     if (o->check_every < 1) return fail(PDZ_EINVAL, "check_every must be >= 1");
     if (o->reorth != 0) return fail(PDZ_EINVAL, "batched Lanczos runs the three-term recurrence (reorth must be 0)");
     if (o->refine != 0 && o->refine != 1) return fail(PDZ_EINVAL, "refine must be 0 or 1");
+    if (o->keep_basis != 0) return fail(PDZ_EINVAL, "keep_basis is not offered for batches (refine regenerates)");
     const BLayout L = blayout(b, o);
     if (!ws || ws_bytes < L.total) return fail(PDZ_EINVAL, "workspace smaller than pdz_batch_lanczos_workspace_size");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PDZ_EINVAL, "workspace must be 256-byte aligned");

@@ -188,12 +188,15 @@ __device__ __forceinline__ double block_sum_waves(double v) {
     return t;
 }
 
-template <typename T, bool HZ>
+// KEEP: the new vector is also stored as slot k + 1 of the kept basis (slots
+// of keep_ld elements, keep_cap of them), the copy the refinement combines.
+template <typename T, bool HZ, bool KEEP>
 __global__ __launch_bounds__(kUpdBlock) void k_update_scaled(T* __restrict__ w, const T* __restrict__ z,
                                                              const T* __restrict__ q, const T* __restrict__ qp,
                                                              uint64_t D, const double* alpha, const double* beta,
                                                              const double* sc, const int* kidx, double* partial,
-                                                             const int* skip, int vec) {
+                                                             const int* skip, int vec, T* __restrict__ keep,
+                                                             uint64_t keep_ld, int keep_cap) {
     if (skip && *skip) return;
     const int k = *kidx;
     const double a = sc[k];
@@ -201,6 +204,7 @@ __global__ __launch_bounds__(kUpdBlock) void k_update_scaled(T* __restrict__ w, 
     const double c = k > 0 ? beta[k] * sc[k - 1] : 0.0;
     const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    T* kept = (KEEP && k + 1 < keep_cap) ? keep + (uint64_t)(k + 1) * keep_ld : nullptr;
     double acc = 0.0;
     uint64_t i = tid;
     if (vec) {
@@ -210,6 +214,7 @@ __global__ __launch_bounds__(kUpdBlock) void k_update_scaled(T* __restrict__ w, 
         const V* zv = reinterpret_cast<const V*>(z);
         const V* qv = reinterpret_cast<const V*>(q);
         const V* pv = reinterpret_cast<const V*>(qp);
+        V* kv = reinterpret_cast<V*>(kept);
         const uint64_t nv = D / N;
         uint64_t j = tid;
         for (; j + stride < nv; j += 2 * stride) {
@@ -228,6 +233,10 @@ __global__ __launch_bounds__(kUpdBlock) void k_update_scaled(T* __restrict__ w, 
             for (int e = 0; e < N; ++e) r1[e] = update_one<T, HZ>(w1[e], z1[e], q1[e], p1[e], a, b, c, acc);
             wv[j] = r0;
             wv[j + stride] = r1;
+            if (KEEP && kv) {
+                kv[j] = r0;
+                kv[j + stride] = r1;
+            }
         }
         if (j < nv) {
             const V w0 = wv[j], q0 = qv[j], p0 = pv[j];
@@ -236,26 +245,57 @@ __global__ __launch_bounds__(kUpdBlock) void k_update_scaled(T* __restrict__ w, 
 #pragma unroll
             for (int e = 0; e < N; ++e) r0[e] = update_one<T, HZ>(w0[e], z0[e], q0[e], p0[e], a, b, c, acc);
             wv[j] = r0;
+            if (KEEP && kv) kv[j] = r0;
         }
         i = nv * N + tid;   // the ragged tail
     }
-    for (; i < D; i += stride) w[i] = update_one<T, HZ>(w[i], HZ ? z[i] : T(0), q[i], qp[i], a, b, c, acc);
+    for (; i < D; i += stride) {
+        const T r = update_one<T, HZ>(w[i], HZ ? z[i] : T(0), q[i], qp[i], a, b, c, acc);
+        w[i] = r;
+        if (KEEP && kept) kept[i] = r;
+    }
     acc = block_sum_waves<kUpdBlock>(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
+template <typename T, bool KEEP>
+void launch_update_scaled_k(T* w, const T* z, const T* q, const T* qp, uint64_t D, const double* alpha,
+                            const double* beta, const double* sc, const int* kidx, double* partial, const int* skip,
+                            hipStream_t s, int vec, T* keep, uint64_t keep_ld, int keep_cap) {
+    if (z)
+        hipLaunchKernelGGL((k_update_scaled<T, true, KEEP>), dim3(kRedGrid), dim3(kUpdBlock), 0, s, w, z, q, qp, D,
+                           alpha, beta, sc, kidx, partial, skip, vec, keep, keep_ld, keep_cap);
+    else
+        hipLaunchKernelGGL((k_update_scaled<T, false, KEEP>), dim3(kRedGrid), dim3(kUpdBlock), 0, s, w, z, q, qp, D,
+                           alpha, beta, sc, kidx, partial, skip, vec, keep, keep_ld, keep_cap);
+}
+
+// keep: NULL, or the kept basis (keep_cap slots of keep_ld elements)
 template <typename T>
 void launch_update_scaled(T* w, const T* z, const T* q, const T* qp, uint64_t D, const double* alpha,
                           const double* beta, const double* sc, const int* kidx, double* partial, const int* skip,
-                          hipStream_t s) {
+                          hipStream_t s, T* keep = nullptr, uint64_t keep_ld = 0, int keep_cap = 0) {
     auto al = [](const void* x) { return ((uintptr_t)x & 15) == 0; };
-    const int vec = al(w) && al(q) && al(qp) && (!z || al(z));
-    if (z)
-        hipLaunchKernelGGL((k_update_scaled<T, true>), dim3(kRedGrid), dim3(kUpdBlock), 0, s, w, z, q, qp, D, alpha,
-                           beta, sc, kidx, partial, skip, vec);
+    const int vec = al(w) && al(q) && al(qp) && (!z || al(z)) && (!keep || (al(keep) && keep_ld % 4 == 0));
+    if (keep)
+        launch_update_scaled_k<T, true>(w, z, q, qp, D, alpha, beta, sc, kidx, partial, skip, s, vec, keep, keep_ld,
+                                        keep_cap);
     else
-        hipLaunchKernelGGL((k_update_scaled<T, false>), dim3(kRedGrid), dim3(kUpdBlock), 0, s, w, z, q, qp, D, alpha,
-                           beta, sc, kidx, partial, skip, vec);
+        launch_update_scaled_k<T, false>(w, z, q, qp, D, alpha, beta, sc, kidx, partial, skip, s, vec, nullptr, 0, 0);
+}
+
+// y = sum_{j < m} (s_j sc_j) Q_j over kept unnormalised vectors, in j order
+// (the sums the regenerating refinement forms one vector at a time).
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_combine_kept(double* __restrict__ y, const T* __restrict__ Q,
+                                                            uint64_t ld, uint64_t D, int m, const double* __restrict__ s,
+                                                            const double* __restrict__ sc) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < m; ++j) acc += (s[j] * sc[j]) * (double)Q[(uint64_t)j * ld + i];
+        y[i] = acc;
+    }
 }
 
 // alpha[k] = sc[k]^2 * (sum(p1[0..n1)) + sum(p2[0..n2))): <v_k, H v_k> from
@@ -433,6 +473,8 @@ struct Layout {
     size_t alpha = 0, beta = 0, theta = 0, s = 0, sc = 0, partial = 0, partial2 = 0, coefs = 0, ctl = 0, z = 0;
     size_t total = 0;
     int nvec_basis = 0;
+    size_t kept = 0;   // kept Lanczos vectors (keep_basis, three-term path): nkept slots
+    int nkept = 0;
 };
 
 Layout make_layout(const pdz_problem_s* p, const pdz_lanczos_opts* o) {
@@ -454,6 +496,11 @@ Layout make_layout(const pdz_problem_s* p, const pdz_lanczos_opts* o) {
         }
         L.z = off;   // up-hop part of H q_k
         off += L.vec;
+        if (o->keep_basis) {
+            L.nkept = o->max_iter + 1;
+            L.kept = off;
+            off += L.vec * (size_t)L.nkept;
+        }
     }
     if (o->refine) {
         L.y = off;
@@ -503,6 +550,7 @@ struct Run {
     uint64_t D;
     T* buf(int i) const { return reinterpret_cast<T*>(ws + L.buf[i]); }
     T* basis(int j) const { return reinterpret_cast<T*>(ws + L.basis + (size_t)j * L.vec); }
+    T* kept(int j) const { return L.nkept ? reinterpret_cast<T*>(ws + L.kept + (size_t)j * L.vec) : nullptr; }
     uint64_t ld() const { return L.vec / sizeof(T); }
     double* y() const { return reinterpret_cast<double*>(ws + L.y); }
     double* hy() const { return reinterpret_cast<double*>(ws + L.hy); }
@@ -546,6 +594,8 @@ struct Run {
         PDZ_HIP(hipStreamSynchronize(s));
         if (!(h.norm0 > 0.0) || !std::isfinite(h.norm0))
             return fail(PDZ_EINVAL, "start vector has zero or non-finite norm");
+        if (scaled && kept(0))
+            hipLaunchKernelGGL((k_copy<T, T>), dim3(g), dim3(kRedBlock), 0, s, dst, kept(0), D);
         if (scaled)
             hipLaunchKernelGGL(k_first_scale, dim3(1), dim3(1), 0, s, sc(), ctl());
         else
@@ -591,7 +641,7 @@ struct Run {
                                (const double*)nullptr, 0, alpha(), sc(), kptr(), done(), err);
         }
         launch_update_scaled<T>(w, c.ndn > 0 ? (const T*)zbuf() : (const T*)nullptr, q, qp, D, alpha(), beta(), sc(),
-                                kptr(), partial(), done(), s);
+                                kptr(), partial(), done(), s, kept(0), ld(), L.nkept);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, beta(), kptr(), 1,
                            (int)kStoreSqrt, done(), err);
         hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kRedBlock), 0, s, alpha(), beta(), svec(), theta(), ctl(), o->tol,
@@ -709,6 +759,9 @@ struct Run {
         const unsigned g = grid_elems(D);
         if (o->reorth) {
             hipLaunchKernelGGL(k_combine_basis<T>, dim3(g), dim3(kRedBlock), 0, s, y(), basis(0), ld(), D, m, svec());
+        } else if (kept(0) && m <= L.nkept) {
+            hipLaunchKernelGGL(k_combine_kept<T>, dim3(g), dim3(kRedBlock), 0, s, y(), kept(0), ld(), D, m, svec(),
+                               sc());
         } else {
             // regenerate v_1..v_m with the same kernels and the stored alpha, beta
             Ctl saved;
@@ -813,6 +866,7 @@ pdz_status check_opts(const pdz_lanczos_opts* o) {
     if (o->reorth != 0 && o->reorth != 1) return fail(PDZ_EINVAL, "reorth must be 0 or 1");
     if (o->check_every < 1) return fail(PDZ_EINVAL, "check_every must be >= 1");
     if (o->refine != 0 && o->refine != 1) return fail(PDZ_EINVAL, "refine must be 0 or 1");
+    if (o->keep_basis != 0 && o->keep_basis != 1) return fail(PDZ_EINVAL, "keep_basis must be 0 or 1");
     return ok();
 }
 
@@ -834,6 +888,7 @@ pdz_status pdz_lanczos_default_opts(pdz_lanczos_opts* o) {
     o->check_every = 10;
     o->use_graph = 1;
     o->refine = 0;
+    o->keep_basis = 0;
     return ok();
 }
 

@@ -66,6 +66,37 @@ def test_fp32_storage_and_fp64_refinement():
     assert r["resid_refined"] >= 0
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_kept_basis_refinement_equals_regenerating_refinement_bitwise(storage):
+    """The refinement from kept Lanczos vectors forms the same sums, in the same order, over the same
+    vectors as the one that regenerates them: identical Rayleigh quotient, residual and Ritz vector."""
+    torch = torch_cuda()
+    g = _gpu("torus4x3")
+    ya = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    yb = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    a = g.lanczos(storage=storage, tol=1e-7, max_iter=400, ritz=ya)
+    b = g.lanczos(storage=storage, tol=1e-7, max_iter=400, ritz=yb, keep_basis=1)
+    for k in ("E0", "E0_refined", "resid_refined", "iters"):
+        assert a[k] == b[k], (k, a, b)
+    assert torch.equal(ya, yb)
+    # a start vector given by the caller, and the plain stream path
+    v0 = to_dev(synth.random_vector(g.D, 9), torch.float64 if storage == "f64" else torch.float32)
+    c = g.lanczos(v0=v0, storage=storage, tol=1e-9, max_iter=400, refine=1, use_graph=0)
+    d = g.lanczos(v0=v0, storage=storage, tol=1e-9, max_iter=400, refine=1, keep_basis=1)
+    assert c["E0_refined"] == d["E0_refined"] and c["resid_refined"] == d["resid_refined"], (c, d)
+
+
+def test_kept_basis_option_is_validated_and_sized():
+    import paper_1707_03974_amd as pdz
+    g = _gpu("ring8")
+    o0 = g.lanczos_opts(storage="f32", max_iter=50)
+    o1 = g.lanczos_opts(storage="f32", max_iter=50, keep_basis=1)
+    vec = ((g.D * 4 + 255) // 256) * 256
+    assert g.workspace_size(o1) - g.workspace_size(o0) == 51 * vec
+    with pytest.raises(pdz.PdzError):
+        g.lanczos(keep_basis=2)
+
+
 def test_full_reorthogonalisation():
     E = _energies()["ring8"]["E0"]
     r = _gpu("ring8").lanczos(reorth=1, tol=1e-12)

@@ -121,6 +121,37 @@ class Problem:
                 "map": trials[k].plan.map, "ms": trials[k].ms} for k in range(min(n.value, cap))]
         return {"down": best.down, "up_cw": best.up_cw, "up": best.up, "map": best.map}, out
 
+    def tune_lanczos(self, dtype, top=6, steps=(20, 60), reps=3):
+        """Plan for Lanczos steps: the libpdz autotuner ranks every H.v plan, then each of the `top`
+        fastest is timed as Lanczos steps (libpdz wall time of a steps[1]-step run minus that of a
+        steps[0]-step run, so that set-up and graph capture cancel) and the fastest is selected.
+        Inside Lanczos the update rides on the down pass and the up pass writes its part apart, so
+        the ranking can differ from that of the bare H.v.  Returns (best, hv_trials, step_trials)."""
+        import torch
+        _, trials = self.tune(dtype, reps=reps)
+        keys = ("down", "up_cw", "up", "map")
+        cand = []
+        for t in sorted(trials, key=lambda t: t["ms"]):
+            k = tuple(t[n] for n in keys)
+            if k not in cand:
+                cand.append(k)
+            if len(cand) == top:
+                break
+        kw = dict(storage=dtype, tol=0.0, check_every=10, seed=1)
+        ws = torch.empty(self.workspace_size(self.lanczos_opts(max_iter=steps[1], **kw)), dtype=torch.uint8,
+                         device="cuda")
+        out = []
+        for k in cand:
+            self.set_plan(dtype, *k)
+            self.lanczos(workspace=ws, max_iter=steps[0], **kw)   # warm-up
+            t0 = self.lanczos(workspace=ws, max_iter=steps[0], **kw)["seconds"]
+            t1 = self.lanczos(workspace=ws, max_iter=steps[1], **kw)["seconds"]
+            out.append(dict(zip(keys, k), ms_per_step=(t1 - t0) / (steps[1] - steps[0]) * 1e3))
+        del ws
+        best = min(out, key=lambda r: r["ms_per_step"])
+        self.set_plan(dtype, *(best[n] for n in keys))
+        return {n: best[n] for n in keys}, trials, out
+
     def kernel_times(self, dtype, reps=10, stream=None):
         """Mean ms of each H.v kernel launched alone: {"down", "up", "hv"} (HIP events in libpdz)."""
         import torch

@@ -48,6 +48,24 @@ struct DownArgs {
     int rows;         // rows staged per group
     double* dotp;     // NULL, or one partial sum of x . y (this pass's output) per work group
     const int* skip;
+    // Fused Lanczos recurrence (FUSE kernels only): the staged rows are
+    // q_{k+1} = sc[k] (y + fz) - alpha[k] sc[k] fq1 - beta[k] sc[k-1] fq2,
+    // formed element by element from the previous step's down part (y, then
+    // overwritten by this pass's output), its up part fz, q_k (fq1) and
+    // q_{k-1} (fq2, overwritten by q_{k+1}; also copied to slot k + 1 of fkeep
+    // when that is set), with k = *fkidx.  fnorm: one partial |q_{k+1}|^2 per
+    // work group.
+    const T* fz;
+    const T* fq1;
+    T* fq2;
+    T* fkeep;
+    uint64_t fkeep_ld;
+    int fkeep_cap;
+    const double* falpha;
+    const double* fbeta;
+    const double* fsc;
+    const int* fkidx;
+    double* fnorm;
 };
 
 template <typename T, typename E>
@@ -124,6 +142,31 @@ __device__ __forceinline__ void block_dot_store(double v, double* out) {
     }
 }
 
+// Two sums at once (fixed order) into *out1, *out2 by thread 0.
+template <int BLOCK>
+__device__ __forceinline__ void block_dot_store2(double v1, double* out1, double v2, double* out2) {
+    __shared__ double wsum2[2][BLOCK / 64];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        v1 += __shfl_xor(v1, m);
+        v2 += __shfl_xor(v2, m);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wsum2[0][threadIdx.x >> 6] = v1;
+        wsum2[1][threadIdx.x >> 6] = v2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t1 = 0.0, t2 = 0.0;
+        for (int i = 0; i < BLOCK / 64; ++i) {
+            t1 += wsum2[0][i];
+            t2 += wsum2[1][i];
+        }
+        *out1 = t1;
+        *out2 = t2;
+    }
+}
+
 // ---------------------------------------------------------------- down pass
 
 // Long rows: R (1 to 3) consecutive rows staged interleaved as
@@ -177,10 +220,11 @@ __device__ __forceinline__ uint32_t row_of(uint32_t k, uint32_t Dn) {
     return k >= 2 * Dn ? 2u : (k >= Dn ? 1u : 0u);
 }
 
-template <typename T, typename E, int R, int MAXH>
+template <typename T, typename E, int R, int MAXH, bool FUSE = false>
 __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E> a, const T* __restrict__ x,
                                                              T* __restrict__ y) {
     if (a.skip && *a.skip) return;
+    static_assert(!FUSE || MAXH == 0, "the fused recurrence rides on the looped table reads");
     extern __shared__ __align__(16) unsigned char smem[];
     T* coef = reinterpret_cast<T*>(smem);
     T* rows = coef + kMaxCoef;
@@ -192,17 +236,60 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
     const __amdgpu_buffer_rsrc_t ell_rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<E*>(a.dn_ell), (short)0, (int)a.ell_bytes, 0x00020000);
     static_assert(R >= 1 && R <= 3, "rows per group");
-    constexpr int PER = R >= 2 ? (sizeof(T) == 8 ? 8 : 12) : (sizeof(T) == 8 ? 16 : 24);
+    // elements per thread loaded ahead for the next group: the fused form holds
+    // four raw operands per element until the group is staged
+    constexpr int PER = FUSE ? (sizeof(T) == 8 ? 6 : 12)
+                             : (R >= 2 ? (sizeof(T) == 8 ? 8 : 12) : (sizeof(T) == 8 ? 16 : 24));
     T pre[PER];
+    T pz[FUSE ? PER : 1], p1[FUSE ? PER : 1], p2[FUSE ? PER : 1];   // FUSE: fz, fq1, fq2 (pre holds y)
     double dsum = 0.0;   // x . y over this work group's elements (when a.dotp is set)
+    double nsum = 0.0;   // |q_{k+1}|^2 over this work group's elements (FUSE)
+    double fa = 0.0, fb = 0.0, fc = 0.0;
+    T* fkeep = nullptr;
+    if constexpr (FUSE) {
+        const int k = *a.fkidx;
+        fa = a.fsc[k];
+        fb = a.falpha[k] * a.fsc[k];
+        fc = k > 0 ? a.fbeta[k] * a.fsc[k - 1] : 0.0;
+        if (a.fkeep && k + 1 < a.fkeep_cap) fkeep = a.fkeep + (uint64_t)(k + 1) * a.fkeep_ld;
+    }
+    // element k of the rows that start at element `off`: x, or q_{k+1} formed
+    // (and stored) here
+    auto stage_elem = [&](uint64_t off, uint32_t k) -> T {
+        if constexpr (FUSE) {
+            const T v = lanczos_recurrence<T>(y[off + k], a.fz[off + k], a.fq1[off + k], a.fq2[off + k], fa, fb, fc);
+            a.fq2[off + k] = v;
+            if (fkeep) fkeep[off + k] = v;
+            nsum += (double)v * (double)v;
+            return v;
+        } else {
+            return __builtin_nontemporal_load(x + off + k);
+        }
+    };
     auto fetch = [&](uint64_t g) {
         const uint64_t u0 = g * R;
         const uint64_t nelem = ((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * D_dn;
-        const T* base = x + u0 * D_dn;
+        if constexpr (FUSE) {
+            // raw operands only: the recurrence is formed when the group is staged,
+            // so these loads stay in flight while the current group computes
+            const uint64_t off = u0 * D_dn;
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const uint64_t k = threadIdx.x + (uint64_t)i * kWideBlock;
-            pre[i] = (k < nelem) ? __builtin_nontemporal_load(base + k) : (T)0;
+            for (int i = 0; i < PER; ++i) {
+                const uint64_t k = threadIdx.x + (uint64_t)i * kWideBlock;
+                if (k < nelem) {
+                    pre[i] = y[off + k];
+                    pz[i] = a.fz[off + k];
+                    p1[i] = a.fq1[off + k];
+                    p2[i] = a.fq2[off + k];
+                }
+            }
+        } else {
+            const T* base = x + u0 * D_dn;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const uint64_t k = threadIdx.x + (uint64_t)i * kWideBlock;
+                pre[i] = (k < nelem) ? __builtin_nontemporal_load(base + k) : (T)0;
+            }
         }
     };
     if (blockIdx.x < ngroups) fetch(blockIdx.x);
@@ -210,12 +297,24 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
         const uint64_t u0 = g * R;
         const int nr = (int)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
         __syncthreads();
+        const uint64_t nelem_g = (uint64_t)nr * D_dn;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const uint32_t k = threadIdx.x + (uint32_t)i * kWideBlock;
             if (k < (uint32_t)R * Dn) {
                 const uint32_t r = row_of<R>(k, Dn);
-                rows[(size_t)(k - r * Dn) * R + r] = pre[i];
+                T v = pre[i];
+                if constexpr (FUSE) {
+                    v = (T)0;
+                    if (k < nelem_g) {
+                        const uint64_t e = u0 * D_dn + k;
+                        v = lanczos_recurrence<T>(pre[i], pz[i], p1[i], p2[i], fa, fb, fc);
+                        a.fq2[e] = v;
+                        if (fkeep) fkeep[e] = v;
+                        nsum += (double)v * (double)v;
+                    }
+                }
+                rows[(size_t)(k - r * Dn) * R + r] = v;
             }
         }
         {   // elements beyond the register prefetch, loaded now
@@ -223,7 +322,9 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
             const T* base = x + u0 * D_dn;
             for (uint32_t k = threadIdx.x + (uint32_t)PER * kWideBlock; k < (uint32_t)R * Dn; k += kWideBlock) {
                 const uint32_t r = row_of<R>(k, Dn);
-                rows[(size_t)(k - r * Dn) * R + r] = (k < nelem) ? base[k] : (T)0;
+                T v = (T)0;
+                if (k < nelem) v = FUSE ? stage_elem(u0 * D_dn, k) : base[k];
+                rows[(size_t)(k - r * Dn) * R + r] = v;
             }
         }
         __syncthreads();
@@ -338,7 +439,10 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
                 }
         }
     }
-    if (a.dotp) block_dot_store<kWideBlock>(dsum, a.dotp + blockIdx.x);
+    if constexpr (FUSE)
+        block_dot_store2<kWideBlock>(dsum, a.dotp + blockIdx.x, nsum, a.fnorm + blockIdx.x);
+    else if (a.dotp)
+        block_dot_store<kWideBlock>(dsum, a.dotp + blockIdx.x);
 }
 
 // Short rows: `rows` consecutive rows staged row-major; threads walk the
@@ -719,11 +823,24 @@ void launch_wide(int variant, int max_hops, uint64_t grid, size_t lds, hipStream
         hipLaunchKernelGGL((k_hv_down_wide<T, E, 1, 0>), g, b, lds, s, da, x, y);
 }
 
-template <typename T, typename E, int R, int MAXH>
+template <typename T, typename E, int R, int MAXH, bool FUSE = false>
 pdz_status set_wide_lds() {
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_wide<T, E, R, MAXH>),
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_wide<T, E, R, MAXH, FUSE>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     return ok();
+}
+
+// The looped down-pass variants (2, 3, 4) with the fused recurrence.
+template <typename T, typename E>
+void launch_wide_fused(int variant, uint64_t grid, size_t lds, hipStream_t s, const DownArgs<T, E>& da, T* y) {
+    const dim3 g((unsigned)grid), b(kWideBlock);
+    const T* x = da.fq2;
+    if (variant == 3)
+        hipLaunchKernelGGL((k_hv_down_wide<T, E, 2, 0, true>), g, b, lds, s, da, x, y);
+    else if (variant == 4)
+        hipLaunchKernelGGL((k_hv_down_wide<T, E, 3, 0, true>), g, b, lds, s, da, x, y);
+    else
+        hipLaunchKernelGGL((k_hv_down_wide<T, E, 1, 0, true>), g, b, lds, s, da, x, y);
 }
 
 // Up-pass geometry: the x[:, chunk] slab one XCD streams over is
@@ -876,9 +993,29 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     da.ncoef = ncoef;
     da.skip = skip;
     da.dotp = split ? split->dotp_dn : nullptr;
+    const bool fused = split && split->fq2;
+    da.fz = fused ? static_cast<const T*>(split->fz) : nullptr;
+    da.fq1 = fused ? static_cast<const T*>(split->fq1) : nullptr;
+    da.fq2 = fused ? static_cast<T*>(split->fq2) : nullptr;
+    da.fkeep = fused ? static_cast<T*>(split->fkeep) : nullptr;
+    da.fkeep_ld = fused ? split->fkeep_ld : 0;
+    da.fkeep_cap = fused ? split->fkeep_cap : 0;
+    da.falpha = fused ? split->falpha : nullptr;
+    da.fbeta = fused ? split->fbeta : nullptr;
+    da.fsc = fused ? split->fsc : nullptr;
+    da.fkidx = fused ? split->fkidx : nullptr;
+    da.fnorm = fused ? split->fnorm : nullptr;
     const HvPlan plan = hv_resolve(p, sizeof(T) == 8 ? PDZ_F64 : PDZ_F32);
     const DownGeom gm = down_geom(p, sizeof(T), plan, (unsigned)ctx->cu_count);
     da.rows = gm.rows;
+    if (fused) {
+        if (!(passes & kPassDown) || (passes & kPassUp) || !gm.wide ||
+            !(plan.down == 2 || plan.down == 3 || plan.down == 4) || !split->dotp_dn || !split->fnorm)
+            return fail(PDZ_EINVAL, "fused recurrence needs the looped wide down pass, alone");
+        launch_wide_fused<T, E>(plan.down, gm.grid, gm.lds, s, da, y);
+        PDZ_HIP(hipGetLastError());
+        return ok();
+    }
     if (!(passes & kPassDown)) {
         // up pass only
     } else if (gm.wide) {
@@ -1016,6 +1153,9 @@ pdz_status prepare_one() {
         if (st == PDZ_OK) st = set_wide_lds<T, E, 1, 48>();
     }
     if (st == PDZ_OK) st = set_wide_lds<T, E, 3, 0>();
+    if (st == PDZ_OK) st = set_wide_lds<T, E, 1, 0, true>();
+    if (st == PDZ_OK) st = set_wide_lds<T, E, 2, 0, true>();
+    if (st == PDZ_OK) st = set_wide_lds<T, E, 3, 0, true>();
     if (st != PDZ_OK) return st;
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_narrow<T, E, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
@@ -1090,6 +1230,16 @@ pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* 
                               passes, split);
     return run_hv<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip, passes,
                          split);
+}
+
+bool hv_fused_available(const pdz_problem_s* p, pdz_dtype dt) {
+    if (p->hv_path != 0) return false;
+    DeviceCtx* ctx = nullptr;
+    if (device_ctx(&ctx) != PDZ_OK) return false;
+    const size_t es = dt == PDZ_F64 ? 8 : 4;
+    const HvPlan plan = hv_resolve(p, dt);
+    const DownGeom gm = down_geom(p, es, plan, (unsigned)ctx->cu_count);
+    return gm.wide && (plan.down == 2 || plan.down == 3 || plan.down == 4);
 }
 
 size_t hv_dot_count_max(const pdz_problem_s* p, pdz_dtype dt) {

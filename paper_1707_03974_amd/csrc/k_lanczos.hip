@@ -162,8 +162,7 @@ __global__ __launch_bounds__(kRedBlock) void k_update(T* __restrict__ w, const T
 // partial[] = |w|^2.  No separate normalisation pass: sc[k+1] = 1 / beta_{k+1}.
 template <typename T, bool HZ>
 __device__ __forceinline__ T update_one(T wi, T zi, T qi, T qpi, double a, double b, double c, double& acc) {
-    const double hq = HZ ? (double)wi + (double)zi : (double)wi;   // H q_k, from its two parts
-    const T r = (T)(a * hq - b * (double)qi - c * (double)qpi);
+    const T r = lanczos_recurrence<T>(wi, HZ ? zi : T(0), qi, qpi, a, b, c);   // H q_k from its two parts
     acc += (double)r * (double)r;
     return r;
 }
@@ -470,7 +469,8 @@ struct Layout {
     size_t buf[3] = {0, 0, 0};
     size_t basis = 0;
     size_t y = 0, hy = 0;
-    size_t alpha = 0, beta = 0, theta = 0, s = 0, sc = 0, partial = 0, partial2 = 0, coefs = 0, ctl = 0, z = 0;
+    size_t alpha = 0, beta = 0, theta = 0, s = 0, sc = 0, partial = 0, partial2 = 0, partial3 = 0, coefs = 0, ctl = 0,
+           z = 0;
     size_t total = 0;
     int nvec_basis = 0;
     size_t kept = 0;   // kept Lanczos vectors (keep_basis, three-term path): nkept slots
@@ -525,6 +525,8 @@ Layout make_layout(const pdz_problem_s* p, const pdz_lanczos_opts* o) {
                     8);
     L.partial2 = off;
     off += align256((size_t)kRedGrid * 8);
+    L.partial3 = off;   // |q_{k+1}|^2 per work group of the fused pass
+    off += align256((size_t)kMaxPartials * 8);
     L.coefs = off;
     off += align256(m * 8);
     L.ctl = off;
@@ -560,6 +562,7 @@ struct Run {
     double* svec() const { return reinterpret_cast<double*>(ws + L.s); }
     double* sc() const { return reinterpret_cast<double*>(ws + L.sc); }
     double* partial2() const { return reinterpret_cast<double*>(ws + L.partial2); }
+    double* partial3() const { return reinterpret_cast<double*>(ws + L.partial3); }
     T* zbuf() const { return reinterpret_cast<T*>(ws + L.z); }
     double* partial() const { return reinterpret_cast<double*>(ws + L.partial); }
     double* coefs() const { return reinterpret_cast<double*>(ws + L.coefs); }
@@ -650,6 +653,60 @@ struct Run {
         return launch_check();
     }
 
+    // The two passes of H q_k and alpha_k (the first half of step_scaled).
+    pdz_status head_step(T* q, T* w, const SplitCounts& c) {
+        HvSplit sp;
+        sp.z = zbuf();
+        sp.dotp_dn = partial();
+        sp.dotp_up = partial() + c.ndn;
+        pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sp);
+        if (st != PDZ_OK) return st;
+        hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn, (uint64_t)c.nup,
+                           partial2(), done());
+        hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), c.ndn, partial2(),
+                           (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
+        return launch_check();
+    }
+
+    // The same step as the update of step_scaled followed by the next step's
+    // H.v and alpha, with the update carried out by the down pass while it
+    // stages its rows: q1 = q_k, q2 = q_{k-1} (receives q_{k+1}), w = down
+    // part of H q_k (receives that of H q_{k+1}), zbuf = up part of H q_k
+    // (receives that of H q_{k+1}).  Between the two passes: beta_{k+1}, the
+    // tridiagonal solve of T_{k+1} and sc[k+1], as in step_scaled.
+    pdz_status fused_step(T* q1, T* q2, T* w, const SplitCounts& c) {
+        HvSplit f;
+        f.dotp_dn = partial();
+        f.fq1 = q1;
+        f.fq2 = q2;
+        f.fz = zbuf();
+        f.fkeep = kept(0);
+        f.fkeep_ld = ld();
+        f.fkeep_cap = L.nkept;
+        f.falpha = alpha();
+        f.fbeta = beta();
+        f.fsc = sc();
+        f.fkidx = kptr();
+        f.fnorm = partial3();
+        pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassDown, &f);
+        if (st != PDZ_OK) return st;
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial3(), c.ndn, beta(), kptr(), 1,
+                           (int)kStoreSqrt, done(), err);
+        hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kRedBlock), 0, s, alpha(), beta(), svec(), theta(), ctl(), o->tol,
+                           o->max_iter, err);
+        hipLaunchKernelGGL(k_next_scale, dim3(1), dim3(1), 0, s, beta(), sc(), ctl());
+        HvSplit u;
+        u.z = zbuf();
+        u.dotp_up = partial() + c.ndn;
+        st = launch_hv(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassUp, &u);
+        if (st != PDZ_OK) return st;
+        hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn, (uint64_t)c.nup,
+                           partial2(), done());
+        hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), c.ndn, partial2(),
+                           (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
+        return launch_check();
+    }
+
     // One Lanczos step with v = v_k, vp = v_{k-1}, w the output slot.
     // `reorth_nvec` > 0: re-orthogonalise against basis(0..reorth_nvec-1).
     pdz_status step(T* v, T* vp, T* w, int reorth_nvec) {
@@ -680,6 +737,14 @@ struct Run {
         return launch_check();
     }
 
+    // The update rides on the down pass when the plan's down pass is the
+    // looped wide kernel (the split H.v is available there too).
+    bool fused_path() const {
+        if (o->reorth) return false;
+        const SplitCounts c = split_counts();
+        return c.ndn > 0 && c.ndn <= kMaxPartials && hv_fused_available(p, (pdz_dtype)o->storage);
+    }
+
     pdz_status read_ctl(Ctl* h) {
         PDZ_HIP(hipMemcpyAsync(h, ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, s));
         PDZ_HIP(hipStreamSynchronize(s));
@@ -702,14 +767,29 @@ struct Run {
             }
             return read_ctl(h);
         }
-        // three rotating buffers; a block of `period` steps (multiple of 3) keeps the rotation aligned
-        int period = o->check_every;
-        if (period % 3) period += 3 - period % 3;
         const SplitCounts counts = split_counts();
+        // fused: q_k alternates between buf(0) and buf(1) (the update runs in
+        // place over q_{k-1}), buf(2) holds the down part of H q_k; after the
+        // first H.v, every step is one fused_step.  Otherwise three rotating
+        // buffers.  A block of `period` steps keeps the rotation aligned.
+        const bool fuse = fused_path();
+        int period = o->check_every;
+        const int rot = fuse ? 2 : 3;
+        if (period % rot) period += rot - period % rot;
+        if (fuse) {
+            st = head_step(buf(0), buf(2), counts);
+            if (st != PDZ_OK) return st;
+        }
         auto enqueue_block = [&]() -> pdz_status {
             for (int t = 0; t < period; ++t) {
-                const int a = t % 3;
-                pdz_status s2 = step_scaled(buf(a), buf((a + 2) % 3), buf((a + 1) % 3), counts);
+                pdz_status s2;
+                if (fuse) {
+                    const int a = t % 2;
+                    s2 = fused_step(buf(a), buf(1 - a), buf(2), counts);
+                } else {
+                    const int a = t % 3;
+                    s2 = step_scaled(buf(a), buf((a + 2) % 3), buf((a + 1) % 3), counts);
+                }
                 if (s2 != PDZ_OK) return s2;
             }
             return ok();
@@ -828,7 +908,7 @@ struct Run {
 
     pdz_status run(const void* v0, double* ritz_out, pdz_lanczos_result* res) {
         T* v1 = o->reorth ? basis(0) : buf(0);
-        T* zero = o->reorth ? buf(0) : buf(2);
+        T* zero = o->reorth ? buf(0) : (fused_path() ? buf(1) : buf(2));
         pdz_status st = start(v0, v1, zero, !o->reorth);
         if (st != PDZ_OK) return st;
         Ctl h;

@@ -86,6 +86,75 @@ def test_kept_basis_refinement_equals_regenerating_refinement_bitwise(storage):
     assert c["E0_refined"] == d["E0_refined"] and c["resid_refined"] == d["resid_refined"], (c, d)
 
 
+# a problem whose rows are long enough for the wide down pass, where the update of each Lanczos step
+# is carried out by the next step's down pass: 14-site ring, 2 + 7 electrons (D = 91 * 3432)
+RING14 = dict(n_sites=14, U=3.0, n_up=2, n_dn=7)
+
+
+def _ring14_bonds():
+    return [synth.Bond(i, (i + 1) % 14, 1.0) for i in range(14)] + [synth.Bond(i, (i + 2) % 14, -0.3) for i in range(14)]
+
+
+def _ring14():
+    import paper_1707_03974_amd as pdz
+    return pdz.Problem(RING14["n_sites"], _ring14_bonds(), RING14["U"], RING14["n_up"], RING14["n_dn"])
+
+
+def _ring14_e0():
+    from scipy.sparse.linalg import eigsh
+    b = _ring14_bonds()
+    po = oracle.Problem(14, [x.i for x in b], [x.j for x in b], [x.t for x in b], RING14["U"], RING14["n_up"],
+                        RING14["n_dn"])
+    H = oracle.build_csr(po)
+    return float(eigsh(H, k=1, which="SA", tol=1e-13, v0=np.ones(H.shape[0]))[0][0])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_fused_recurrence_path_matches_oracle_and_unfused_path(storage):
+    g = _ring14()
+    assert g.info["D_dn"] >= 1024
+    E = _ring14_e0()
+    tol = 1e-12 if storage == "f64" else 1e-7
+    # looped wide down pass (the update rides on it) against the up-front variant (separate update)
+    g.set_plan(storage, 3, 0, 0, 0)
+    a = g.lanczos(storage=storage, tol=tol, max_iter=600, refine=1)
+    g.set_plan(storage, 1, 0, 0, 0)
+    b = g.lanczos(storage=storage, tol=tol, max_iter=600, refine=1)
+    g.set_plan(storage, 0, 0, 0, 0)
+    bound = 1e-10 if storage == "f64" else 1e-8
+    for r in (a, b):
+        assert r["converged"] == 1
+        assert abs(r["E0_refined"] - E) <= bound * abs(E), (r, E)
+    assert abs(a["iters"] - b["iters"]) <= 2, (a, b)
+    if storage == "f64":
+        assert abs(a["E0"] - b["E0"]) <= 1e-12 * abs(E)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_fused_pass_forms_the_vectors_the_separate_update_regenerates(storage):
+    """Kept vectors come from the fused down pass; the regenerating refinement re-forms them with the
+    separate update kernel: equal Ritz vectors bit for bit only if every vector is equal bit for bit."""
+    torch = torch_cuda()
+    g = _ring14()
+    g.set_plan(storage, 4 if storage == "f32" else 2, 0, 0, 0)
+    ya = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    yb = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    a = g.lanczos(storage=storage, tol=1e-9, max_iter=400, ritz=ya)
+    b = g.lanczos(storage=storage, tol=1e-9, max_iter=400, ritz=yb, keep_basis=1)
+    g.set_plan(storage, 0, 0, 0, 0)
+    for k in ("E0", "E0_refined", "resid_refined", "iters"):
+        assert a[k] == b[k], (k, a, b)
+    assert torch.equal(ya, yb)
+
+
+def test_fused_path_graph_and_stream_agree_bitwise():
+    g = _ring14()
+    a = g.lanczos(storage="f32", tol=1e-7, use_graph=1, check_every=4)
+    b = g.lanczos(storage="f32", tol=1e-7, use_graph=0, check_every=4)
+    c = g.lanczos(storage="f32", tol=1e-7, use_graph=1, check_every=7)
+    assert a["E0"] == b["E0"] == c["E0"] and a["iters"] == b["iters"] == c["iters"]
+
+
 def test_kept_basis_option_is_validated_and_sized():
     import paper_1707_03974_amd as pdz
     g = _gpu("ring8")

@@ -26,9 +26,6 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 
 
-KERNEL_NAMES = {"down": "k_hv_down_wide", "up": "k_hv_up / k_hv_up_pre"}
-
-
 def recorded_traffic(workload, kernel, plan):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None.
 
@@ -356,15 +353,28 @@ def main():
     bytes64 = 2.0 * D * 8
     ach32 = bytes32 / (ms32 * 1e-3) / 1e9
     ach64 = bytes64 / (ms64 * 1e-3) / 1e9
-    # per kernel (each launched alone, HIP events on its stream inside libpdz):
-    # down pass reads x and writes y (2 D s bytes); up pass reads x, reads y, writes y (3 D s)
+    # per kernel of the public H.v (each launched alone, HIP events on its stream inside libpdz)
     kt32 = g.kernel_times("f32", reps=args.hv_reps)
     kt64 = g.kernel_times("f64", reps=args.hv_reps)
     _log(f"kernel times f32 {kt32}, f64 {kt64}")
-    dom = "up" if kt32["up"] >= kt32["down"] else "down"
-    kbytes = {"down": 2.0 * D * 4, "up": 3.0 * D * 4}
-    ach_dom = kbytes[dom] / (kt32[dom] * 1e-3) / 1e9
-    traffic = recorded_traffic(w.name, dom + "_f32", tuned["f32"]["best"])
+    # per launch group of the timed Lanczos step (HIP events between the launches inside libpdz):
+    # the dominant kernel and its algorithmic bytes per launch.  Down pass fused with the update:
+    # reads the two parts of H q_k, q_k and q_(k-1), writes q_(k+1) and its down part (6 D s);
+    # separate down pass: x read, part written (2 D s); up pass inside Lanczos: x read through the
+    # gathers, its part written (2 D s); separate update: 4 vectors read, 1 written (5 D s).
+    lk32 = g.lanczos_kernel_times("f32", steps=max(10, 2 * args.hv_reps))
+    lk64 = g.lanczos_kernel_times("f64", steps=max(10, 2 * args.hv_reps))
+    _log(f"lanczos kernel times f32 {lk32}, f64 {lk64}")
+    groups = {"down": lk32["down"], "up": lk32["up"], "update": lk32["update"]}
+    dom = max(groups, key=groups.get)
+    streams = {"down": 6.0 if lk32["fused"] else 2.0, "up": 2.0, "update": 5.0}
+    kbytes = streams[dom] * D * 4
+    ach_dom = kbytes / (groups[dom] * 1e-3) / 1e9
+    role = {"down": "fused_f32" if lk32["fused"] else "down_f32", "up": "up_f32_split", "update": None}[dom]
+    traffic = recorded_traffic(w.name, role, tuned["f32"]["best"]) if role else None
+    names = {"down": ("down pass with the recurrence update fused (k_hv_down_wide)" if lk32["fused"]
+                      else "down pass (k_hv_down_wide)"),
+             "up": "up pass, its part written apart (k_hv_up)", "update": "recurrence update (k_update_scaled)"}
 
     copy = None
     if args.calibrate_copy:
@@ -423,15 +433,15 @@ def main():
                    "storage": "f32", "step": "one Lanczos step (H.v + recurrence + tridiagonal solve)"},
         "roofline": {"bound": "hbm", "achieved": ach_dom, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": ach_dom / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": f"{dom} pass of H.v, FP32 ({KERNEL_NAMES[dom]}, plan {tuned['f32']['best']})",
-                     "avg_ms": kt32[dom], "algorithmic_bytes": kbytes[dom],
-                     "other_kernel": {"name": "up" if dom == "down" else "down",
-                                      "avg_ms": kt32["up" if dom == "down" else "down"]},
+                     "kernel": f"{names[dom]} in the FP32 Lanczos step, plan {tuned['f32']['best']}",
+                     "avg_ms": groups[dom], "algorithmic_bytes": kbytes,
+                     "step_kernels_ms": lk32,
+                     "public_hv_kernel_ms": kt32,
                      "whole_hv": {"ms": ms32, "algorithmic_bytes": bytes32, "achieved": ach32,
                                   "frac": ach32 / PEAK_HBM_GBS}},
         "fp64": {"value": nnz * args.steps / t64, "ms_per_step": t64 / args.steps * 1e3,
                  "hv_ms": ms64, "hv_achieved_GBs": ach64, "hv_frac": ach64 / PEAK_HBM_GBS,
-                 "kernel_ms": kt64,
+                 "kernel_ms": kt64, "step_kernels_ms": lk64,
                  "hv_nnz_per_s": nnz / (ms64 * 1e-3)},
         "hv_nnz_per_s_f32": nnz / (ms32 * 1e-3),
         "time_to_E0_1e-8": tte,

@@ -215,6 +215,18 @@ typedef struct {
  * check_every 10, use_graph 1, refine 0, keep_basis 0. */
 pdz_status pdz_lanczos_default_opts(pdz_lanczos_opts* o);
 
+/* Timing of the Lanczos step of pdz_lanczos (measurement aid): the seeded
+ * start vector, then `steps` steps (1 <= steps < max_iter, tol taken as 0)
+ * launched on `stream` without a graph, with HIP events between the launch
+ * groups of each step.  ms (5 doubles) receives mean milliseconds per step:
+ * [0] the down pass (it also carries out the recurrence update when
+ * *fused == 1), [1] the up pass, [2] the separate update kernel (0 when
+ * fused), [3] the scalar kernels (alpha, beta, tridiagonal solve), [4] the
+ * whole step.  ws as for pdz_lanczos with these options (reorth must be 0);
+ * its contents are overwritten.  Synchronous.  Errors: PDZ_EINVAL. */
+pdz_status pdz_lanczos_kernel_times(pdz_problem p, const pdz_lanczos_opts* o, void* ws, size_t ws_bytes,
+                                    int32_t steps, double* ms, int32_t* fused, void* stream);
+
 /* Bytes of device workspace pdz_lanczos needs for these options. */
 pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, size_t* bytes);
 

@@ -163,6 +163,21 @@ class Problem:
                                              ctypes.c_void_p(y.data_ptr()), int(reps), ms, _stream_handle(stream)))
         return {"down": ms[0], "up": ms[1], "hv": ms[2]}
 
+    def lanczos_kernel_times(self, dtype, steps=20, stream=None, **kw):
+        """Mean ms per Lanczos step of each launch group (HIP events in libpdz): {"down", "up",
+        "update", "scalars", "step", "fused"}; "down" carries the recurrence update when fused."""
+        import torch
+        o = self.lanczos_opts(storage=dtype, max_iter=steps + 1, tol=0.0, **kw)
+        ws = torch.empty(self.workspace_size(o), dtype=torch.uint8, device="cuda")
+        ms = (ctypes.c_double * 5)()
+        fused = ctypes.c_int32()
+        _lib.check(lib().pdz_lanczos_kernel_times(self._h, ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()),
+                                                  ws.numel(), int(steps), ms, ctypes.byref(fused),
+                                                  _stream_handle(stream)))
+        del ws
+        return {"down": ms[0], "up": ms[1], "update": ms[2], "scalars": ms[3], "step": ms[4],
+                "fused": bool(fused.value)}
+
     def lanczos_opts(self, **kw):
         o = LanczosOpts()
         _lib.check(lib().pdz_lanczos_default_opts(ctypes.byref(o)))

@@ -93,6 +93,8 @@ _SIGNATURES = {
     "pdz_lanczos_workspace_size": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), ctypes.POINTER(ctypes.c_size_t)]),
     "pdz_lanczos": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, _P, ctypes.c_size_t, _P,
                                      ctypes.POINTER(LanczosResult), _P]),
+    "pdz_lanczos_kernel_times": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), _P]),
     "pdz_lanczos_history": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "pdz_batch_create": (ctypes.c_int32, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),

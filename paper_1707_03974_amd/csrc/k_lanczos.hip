@@ -570,6 +570,12 @@ struct Run {
     int* done() const { return &ctl()->done; }
     int* kptr() const { return &ctl()->k; }
 
+    // Optional HIP events recorded between the launches of one step (timing).
+    hipEvent_t* ev = nullptr;
+    void mark(int i) {
+        if (ev) (void)hipEventRecord(ev[i], s);
+    }
+
     pdz_status launch_check() {
         PDZ_HIP(hipGetLastError());
         return ok();
@@ -624,13 +630,19 @@ struct Run {
     // alpha comes from partial sums of q . (each part) written by the two
     // passes of H.v, so no pass re-reads a D-sized vector for them.
     pdz_status step_scaled(T* q, T* qp, T* w, const SplitCounts& c) {
+        mark(0);
         if (c.ndn > 0) {
-            HvSplit sp;
-            sp.z = zbuf();
-            sp.dotp_dn = partial();
-            sp.dotp_up = partial() + c.ndn;
-            pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sp);
+            HvSplit sd;   // down pass (no z: it would be cleared after a down-only launch)
+            sd.dotp_dn = partial();
+            pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown, &sd);
             if (st != PDZ_OK) return st;
+            mark(1);
+            HvSplit su;
+            su.z = zbuf();
+            su.dotp_up = partial() + c.ndn;
+            st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done(), kPassUp, &su);
+            if (st != PDZ_OK) return st;
+            mark(2);
             hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn,
                                (uint64_t)c.nup, partial2(), done());
             hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), c.ndn, partial2(),
@@ -638,18 +650,23 @@ struct Run {
         } else {
             pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done());
             if (st != PDZ_OK) return st;
+            mark(1);
+            mark(2);
             hipLaunchKernelGGL((k_dot_partial<T, T>), dim3(kRedGrid), dim3(kRedBlock), 0, s, q, w, D, partial(),
                                done());
             hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), (int)kRedGrid,
                                (const double*)nullptr, 0, alpha(), sc(), kptr(), done(), err);
         }
+        mark(3);
         launch_update_scaled<T>(w, c.ndn > 0 ? (const T*)zbuf() : (const T*)nullptr, q, qp, D, alpha(), beta(), sc(),
                                 kptr(), partial(), done(), s, kept(0), ld(), L.nkept);
+        mark(4);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, beta(), kptr(), 1,
                            (int)kStoreSqrt, done(), err);
         hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kRedBlock), 0, s, alpha(), beta(), svec(), theta(), ctl(), o->tol,
                            o->max_iter, err);
         hipLaunchKernelGGL(k_next_scale, dim3(1), dim3(1), 0, s, beta(), sc(), ctl());
+        mark(5);
         return launch_check();
     }
 
@@ -675,6 +692,7 @@ struct Run {
     // (receives that of H q_{k+1}).  Between the two passes: beta_{k+1}, the
     // tridiagonal solve of T_{k+1} and sc[k+1], as in step_scaled.
     pdz_status fused_step(T* q1, T* q2, T* w, const SplitCounts& c) {
+        mark(0);
         HvSplit f;
         f.dotp_dn = partial();
         f.fq1 = q1;
@@ -690,21 +708,82 @@ struct Run {
         f.fnorm = partial3();
         pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassDown, &f);
         if (st != PDZ_OK) return st;
+        mark(1);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial3(), c.ndn, beta(), kptr(), 1,
                            (int)kStoreSqrt, done(), err);
         hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kRedBlock), 0, s, alpha(), beta(), svec(), theta(), ctl(), o->tol,
                            o->max_iter, err);
         hipLaunchKernelGGL(k_next_scale, dim3(1), dim3(1), 0, s, beta(), sc(), ctl());
+        mark(2);
         HvSplit u;
         u.z = zbuf();
         u.dotp_up = partial() + c.ndn;
         st = launch_hv(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassUp, &u);
         if (st != PDZ_OK) return st;
+        mark(3);
         hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn, (uint64_t)c.nup,
                            partial2(), done());
         hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), c.ndn, partial2(),
                            (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
+        mark(4);
+        mark(5);
         return launch_check();
+    }
+
+    // Mean duration of each launch group over `steps` Lanczos steps from the
+    // seeded start, stream launches with events between the groups.
+    // ms[0] down pass (fused with the update on the fused path), ms[1] up
+    // pass, ms[2] separate update (0 on the fused path), ms[3] scalar
+    // kernels, ms[4] whole step.
+    pdz_status timed_steps(int steps, double* ms, int* fused_out) {
+        const bool fuse = fused_path();
+        const SplitCounts counts = split_counts();
+        pdz_status st = start(nullptr, buf(0), fuse ? buf(1) : buf(2), true);
+        if (st != PDZ_OK) return st;
+        if (fuse) {
+            st = head_step(buf(0), buf(2), counts);
+            if (st != PDZ_OK) return st;
+        }
+        hipEvent_t e[6];
+        for (int i = 0; i < 6; ++i) PDZ_HIP(hipEventCreate(&e[i]));
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        ev = e;
+        for (int t = 0; t < steps && st == PDZ_OK; ++t) {
+            if (fuse) {
+                const int a = t % 2;
+                st = fused_step(buf(a), buf(1 - a), buf(2), counts);
+            } else {
+                const int a = t % 3;
+                st = step_scaled(buf(a), buf((a + 2) % 3), buf((a + 1) % 3), counts);
+            }
+            if (st != PDZ_OK) break;
+            hipError_t he = hipEventSynchronize(e[5]);
+            float f[5];
+            for (int i = 0; i < 5 && he == hipSuccess; ++i) he = hipEventElapsedTime(&f[i], e[i], e[i + 1]);
+            if (he != hipSuccess) {
+                st = hip_fail(he, "Lanczos step timing");
+                break;
+            }
+            for (int i = 0; i < 5; ++i) acc[i] += f[i];
+        }
+        ev = nullptr;
+        for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]);
+        if (st != PDZ_OK) return st;
+        const double n = steps > 0 ? steps : 1;
+        if (fuse) {   // marks: 0 P 1 scalars 2 U 3 scalars 4 (5 = 4)
+            ms[0] = acc[0] / n;
+            ms[1] = acc[2] / n;
+            ms[2] = 0.0;
+            ms[3] = (acc[1] + acc[3]) / n;
+        } else {      // marks: 0 D 1 U 2 scalars 3 update 4 scalars 5
+            ms[0] = acc[0] / n;
+            ms[1] = acc[1] / n;
+            ms[2] = acc[3] / n;
+            ms[3] = (acc[2] + acc[4]) / n;
+        }
+        ms[4] = (acc[0] + acc[1] + acc[2] + acc[3] + acc[4]) / n;
+        *fused_out = fuse ? 1 : 0;
+        return ok();
     }
 
     // One Lanczos step with v = v_k, vp = v_{k-1}, w the output slot.
@@ -999,6 +1078,37 @@ pdz_status pdz_lanczos_history(pdz_problem p, const pdz_lanczos_opts* o, const v
                           hipMemcpyDeviceToHost));
     *n_out = n;
     return ok();
+}
+
+pdz_status pdz_lanczos_kernel_times(pdz_problem p, const pdz_lanczos_opts* o, void* ws, size_t ws_bytes,
+                                    int32_t steps, double* ms, int32_t* fused, void* stream) {
+    if (!p || !ms || !fused) return fail(PDZ_EINVAL, "NULL argument");
+    pdz_status st = check_opts(o);
+    if (st != PDZ_OK) return st;
+    if (o->reorth) return fail(PDZ_EINVAL, "step timing covers the three-term recurrence (reorth must be 0)");
+    if (steps < 1 || steps >= o->max_iter) return fail(PDZ_EINVAL, "steps must be in [1, max_iter)");
+    const Layout L = make_layout(p, o);
+    if (!ws || ws_bytes < L.total) return fail(PDZ_EINVAL, "workspace smaller than pdz_lanczos_workspace_size");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PDZ_EINVAL, "workspace must be 256-byte aligned");
+    int dev = 0;
+    PDZ_HIP(hipGetDevice(&dev));
+    if (dev != p->device) return fail(PDZ_EINVAL, "problem lives on another device");
+    DeviceCtx* ctx = nullptr;
+    st = device_ctx(&ctx);
+    if (st != PDZ_OK) return st;
+    pdz_lanczos_opts oo = *o;
+    oo.tol = 0.0;
+    hipStream_t s = (hipStream_t)stream;
+    int f = 0;
+    if (oo.storage == PDZ_F64) {
+        Run<double> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, p->D};
+        st = r.timed_steps(steps, ms, &f);
+    } else {
+        Run<float> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, p->D};
+        st = r.timed_steps(steps, ms, &f);
+    }
+    *fused = f;
+    return st;
 }
 
 pdz_status pdz_lanczos(pdz_problem p, const pdz_lanczos_opts* o, const void* v0, void* ws, size_t ws_bytes,

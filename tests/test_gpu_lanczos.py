@@ -155,6 +155,22 @@ def test_fused_path_graph_and_stream_agree_bitwise():
     assert a["E0"] == b["E0"] == c["E0"] and a["iters"] == b["iters"] == c["iters"]
 
 
+def test_lanczos_step_timing_reports_each_launch_group():
+    import paper_1707_03974_amd as pdz
+    g = _ring14()
+    for dt, plan, fused in (("f32", (4, 0, 0, 0), True), ("f32", (1, 0, 0, 0), False), ("f64", (2, 0, 0, 0), True)):
+        g.set_plan(dt, *plan)
+        t = g.lanczos_kernel_times(dt, steps=6)
+        assert t["fused"] == fused, (dt, plan, t)
+        assert t["down"] > 0 and t["up"] > 0 and t["scalars"] > 0
+        assert (t["update"] > 0) == (not fused)
+        assert t["step"] >= t["down"] + t["up"] + t["update"] - 1e-9
+    g.set_plan("f32", 0, 0, 0, 0)
+    g.set_plan("f64", 0, 0, 0, 0)
+    with pytest.raises(pdz.PdzError):
+        g.lanczos_kernel_times("f32", steps=0)
+
+
 def test_kept_basis_option_is_validated_and_sized():
     import paper_1707_03974_amd as pdz
     g = _gpu("ring8")

@@ -195,7 +195,13 @@ typedef struct {
     uint64_t seed;         /* start vector when v0 == NULL: SplitMix64 output r -> 2u-1         */
     int32_t check_every;   /* host reads the device convergence flag every this many steps (>=1) */
     int32_t use_graph;     /* 1: replay blocks of check_every steps as a captured HIP graph     */
-    int32_t refine;        /* 1: build the Ritz vector and return its FP64 Rayleigh quotient    */
+    int32_t refine;        /* 1: build the Ritz vector and return its FP64 Rayleigh quotient;   */
+                           /* 2: also, when its FP64 residual r is too large for that quotient */
+                           /*    to be within 1e-8 (|r|^2 / gap > 1e-8 |E0|, gap = distance to */
+                           /*    the second Ritz value of T_k), run FP64 Lanczos from the Ritz  */
+                           /*    vector (tol max(tol, 1e-12), max_iter at least 300) and its    */
+                           /*    refined energy is returned (and the status is that run's);   */
+                           /*    the workspace then holds that FP64 run's workspace too        */
     int32_t keep_basis;    /* 1: keep every Lanczos vector in the workspace (max_iter + 1 of D   */
                            /*    elements) so that refine combines them in one pass instead of */
                            /*    regenerating them with a second run of H.v products           */
@@ -209,6 +215,7 @@ typedef struct {
     double seconds;        /* wall time of the call                                             */
     int32_t iters;         /* Lanczos steps taken                                               */
     int32_t converged;     /* 1 if the tolerance was met or the Krylov space became invariant   */
+    int32_t restart_iters; /* steps of the FP64 restart (refine == 2 when it ran), else 0       */
 } pdz_lanczos_result;
 
 /* Fill *o with defaults: max_iter 300, tol 1e-12, F64, no reorth, seed 1,
@@ -238,8 +245,9 @@ pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, 
  *     seeded start vector; it is normalised internally (not modified).
  * ws: caller-owned device workspace of at least pdz_lanczos_workspace_size
  *     bytes, 256-byte aligned.  ritz_out: NULL, or a device array of D doubles
- *     that receives the normalised Ritz vector; it forces refine, so size the
- *     workspace with refine = 1.  Synchronous.
+ *     that receives the normalised Ritz vector (of the FP64 restart when one
+ *     ran); it forces refine >= 1, so size the workspace with refine >= 1.
+ *     Synchronous.
  * Errors: PDZ_EINVAL (bad options, null handle/result, ws too small, zero or
  * non-finite start vector); PDZ_ENOCONV when max_iter is reached (res holds
  * the best estimate). */

@@ -200,7 +200,7 @@ class Problem:
         """
         import torch
         if ritz is not None:
-            kw["refine"] = 1
+            kw["refine"] = max(1, int(kw.get("refine", 1)))
         o = self.lanczos_opts(**kw)
         nbytes = self.workspace_size(o)
         if workspace is None:

@@ -53,7 +53,7 @@ class LanczosOpts(ctypes.Structure):
 class LanczosResult(ctypes.Structure):
     _fields_ = [("E0", ctypes.c_double), ("resid_est", ctypes.c_double), ("E0_refined", ctypes.c_double),
                 ("resid_refined", ctypes.c_double), ("seconds", ctypes.c_double), ("iters", ctypes.c_int32),
-                ("converged", ctypes.c_int32)]
+                ("converged", ctypes.c_int32), ("restart_iters", ctypes.c_int32)]
 
 
 class HvPlan(ctypes.Structure):

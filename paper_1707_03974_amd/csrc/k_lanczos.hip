@@ -475,7 +475,47 @@ struct Layout {
     int nvec_basis = 0;
     size_t kept = 0;   // kept Lanczos vectors (keep_basis, three-term path): nkept slots
     int nkept = 0;
+    size_t restart = 0;   // workspace of the FP64 restart (refine == 2)
 };
+
+// Second-lowest eigenvalue of the k x k tridiagonal matrix (diagonal a[0..k),
+// off-diagonal b[1..k)) by bisection on the Sturm count (host, FP64).
+double tridiag_second_min_host(const std::vector<double>& a, const std::vector<double>& b, int k) {
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i]) : 0.0) + (i + 1 < k ? std::fabs(b[i + 1]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    auto count_below = [&](double x) {   // eigenvalues < x
+        int c = 0;
+        double q = a[0] - x;
+        if (q < 0) ++c;
+        for (int i = 1; i < k; ++i) {
+            const double d = q != 0.0 ? q : 1e-300;
+            q = a[i] - x - b[i] * b[i] / d;
+            if (q < 0) ++c;
+        }
+        return c;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(lo) + std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_below(mid) >= 2) hi = mid; else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Options of the FP64 Lanczos restart from the Ritz vector (refine == 2).
+pdz_lanczos_opts restart_opts(const pdz_lanczos_opts* o) {
+    pdz_lanczos_opts r = *o;
+    r.storage = PDZ_F64;
+    r.reorth = 0;
+    r.refine = 1;
+    r.keep_basis = 0;
+    r.tol = o->tol > 1e-12 ? o->tol : 1e-12;
+    r.max_iter = o->max_iter > 300 ? o->max_iter : 300;
+    return r;
+}
 
 Layout make_layout(const pdz_problem_s* p, const pdz_lanczos_opts* o) {
     const uint64_t D = p->D;
@@ -531,6 +571,11 @@ Layout make_layout(const pdz_problem_s* p, const pdz_lanczos_opts* o) {
     off += align256(m * 8);
     L.ctl = off;
     off += align256(sizeof(Ctl));
+    if (o->refine == 2) {
+        const pdz_lanczos_opts r = restart_opts(o);
+        L.restart = off;
+        off += align256(make_layout(p, &r).total);
+    }
     L.total = off;
     return L;
 }
@@ -1010,10 +1055,45 @@ struct Run {
         if (o->refine && h.k > 0) {
             st = refine(v0, h.k, &res->E0_refined, &res->resid_refined);
             if (st != PDZ_OK) return st;
+            if (o->refine == 2) {
+                bool restarted = false;
+                st = maybe_restart(h.k, ritz_out, res, &restarted);
+                if (st != PDZ_OK && st != PDZ_ENOCONV) return st;
+                if (restarted) return st;
+            }
             if (ritz_out) PDZ_HIP(hipMemcpyAsync(ritz_out, y(), (size_t)D * 8, hipMemcpyDeviceToDevice, s));
         }
         PDZ_HIP(hipStreamSynchronize(s));
         return h.converged ? ok() : fail(PDZ_ENOCONV, "max_iter reached before the tolerance");
+    }
+
+    // refine == 2: when the FP64 residual r of the Ritz vector y is too large
+    // for its Rayleigh quotient theta to be within 1e-8 of the eigenvalue,
+    // |r|^2 / gap > 1e-8 |theta| with gap = theta_2(T_k) - theta_1(T_k), run
+    // FP64 Lanczos from y (three-term recurrence, tol at least 1e-12, at
+    // least 300 steps) and report its refined energy.
+    pdz_status maybe_restart(int k, double* ritz_out, pdz_lanczos_result* res, bool* restarted) {
+        *restarted = false;
+        if (k < 2) return ok();
+        std::vector<double> a(k), b(k + 1);
+        PDZ_HIP(hipMemcpyAsync(a.data(), alpha(), (size_t)k * 8, hipMemcpyDeviceToHost, s));
+        PDZ_HIP(hipMemcpyAsync(b.data(), beta(), (size_t)(k + 1) * 8, hipMemcpyDeviceToHost, s));
+        PDZ_HIP(hipStreamSynchronize(s));
+        const double gap = tridiag_second_min_host(a, b, k) - res->E0;
+        const double r = res->resid_refined;
+        if (!(gap > 0.0) || !(r * r > 1e-8 * std::fabs(res->E0_refined) * gap)) return ok();
+        const pdz_lanczos_opts ro = restart_opts(o);
+        const Layout L2 = make_layout(p, &ro);
+        Run<double> r2{p, &ro, L2, ws + L.restart, s, err, D};
+        pdz_lanczos_result rr;
+        std::memset(&rr, 0, sizeof(rr));
+        pdz_status st = r2.run(y(), ritz_out, &rr);
+        if (st != PDZ_OK && st != PDZ_ENOCONV) return st;
+        *restarted = true;
+        res->E0_refined = rr.E0_refined;
+        res->resid_refined = rr.resid_refined;
+        res->restart_iters = rr.iters;
+        return st;
     }
 };
 
@@ -1024,7 +1104,8 @@ pdz_status check_opts(const pdz_lanczos_opts* o) {
     if (o->storage != PDZ_F64 && o->storage != PDZ_F32) return fail(PDZ_EINVAL, "storage must be F64 or F32");
     if (o->reorth != 0 && o->reorth != 1) return fail(PDZ_EINVAL, "reorth must be 0 or 1");
     if (o->check_every < 1) return fail(PDZ_EINVAL, "check_every must be >= 1");
-    if (o->refine != 0 && o->refine != 1) return fail(PDZ_EINVAL, "refine must be 0 or 1");
+    if (o->refine < 0 || o->refine > 2) return fail(PDZ_EINVAL, "refine must be 0, 1 or 2");
+    if (o->refine == 2 && o->reorth) return fail(PDZ_EINVAL, "refine = 2 restarts the three-term recurrence (reorth 0)");
     if (o->keep_basis != 0 && o->keep_basis != 1) return fail(PDZ_EINVAL, "keep_basis must be 0 or 1");
     return ok();
 }
@@ -1119,7 +1200,7 @@ pdz_status pdz_lanczos(pdz_problem p, const pdz_lanczos_opts* o, const void* v0,
     if (st != PDZ_OK) return st;
     std::memset(res, 0, sizeof(*res));
     pdz_lanczos_opts oo = *o;
-    if (ritz_out) oo.refine = 1;
+    if (ritz_out && oo.refine == 0) oo.refine = 1;
     if (oo.reorth) oo.use_graph = 0;
     const Layout L = make_layout(p, &oo);
     if (!ws) return fail(PDZ_EINVAL, "workspace is NULL");

@@ -171,6 +171,28 @@ def test_lanczos_step_timing_reports_each_launch_group():
         g.lanczos_kernel_times("f32", steps=0)
 
 
+def test_fp32_run_with_fp64_restart_recovers_the_fp64_energy():
+    """refine = 2: a loosely converged FP32 run whose Ritz vector does not bound the energy to 1e-8 is
+    followed by FP64 Lanczos from that vector; the result is the FP64 ground-state energy."""
+    torch = torch_cuda()
+    E = _energies()["torus4x3"]["E0"]
+    g = _gpu("torus4x3")
+    y = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    r = g.lanczos(storage="f32", tol=1e-12, max_iter=25, refine=2, ritz=y)   # stopped early on purpose
+    assert r["converged"] == 0 and r["restart_iters"] > 0, r
+    assert abs(r["E0_refined"] - E) <= 1e-10 * abs(E), r
+    assert abs(float(torch.linalg.norm(y)) - 1.0) < 1e-12
+    # a converged FP64 run needs no restart; refine = 1 reports no restart either
+    a = g.lanczos(storage="f64", tol=1e-12, max_iter=400, refine=2)
+    assert a["restart_iters"] == 0 and abs(a["E0_refined"] - E) <= 1e-10 * abs(E), a
+    b = g.lanczos(storage="f32", tol=1e-12, max_iter=25, refine=1)
+    assert b["restart_iters"] == 0 and abs(b["E0_refined"] - E) > 1e-10 * abs(E), b
+    # the restart's workspace is part of the refine = 2 size
+    o1 = g.lanczos_opts(storage="f32", max_iter=100, refine=1)
+    o2 = g.lanczos_opts(storage="f32", max_iter=100, refine=2)
+    assert g.workspace_size(o2) > g.workspace_size(o1) + 3 * g.D * 8
+
+
 def test_kept_basis_option_is_validated_and_sized():
     import paper_1707_03974_amd as pdz
     g = _gpu("ring8")

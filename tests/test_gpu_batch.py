@@ -266,3 +266,16 @@ def test_batched_errors_and_noconv():
     arr = (ctypes.c_void_p * 1)(None)
     h = ctypes.c_void_p()
     assert lib.pdz_batch_create(arr, 1, ctypes.byref(h)) == _lib.PDZ_EINVAL
+
+
+def test_batch_plan_cache_round_trip(tmp_path):
+    from paper_1707_03974_amd import tuning
+    probs, b = _make(_small_batch_args())
+    path = str(tmp_path / "plans.json")
+    e1, t1 = tuning.tuned_batch_plan(b, "f32", reps=1, path=path)
+    assert t1 and e1["ms"] > 0
+    b.set_plan()   # back to automatic
+    e2, t2 = tuning.tuned_batch_plan(b, "f32", reps=1, path=path)
+    assert t2 is None and e2 == e1
+    got = b.get_plan()
+    assert all(got[k] == e1[k] for k in ("tile_elems", "block", "wgs_per_cu", "order"))

@@ -190,3 +190,15 @@ def test_invalid_plan_is_rejected():
     g = _gpu_problem(synth.workload("torus4x3"))
     with pytest.raises(pdz.PdzError):
         g.set_plan("f32", 1, 7)
+
+
+def test_problem_plan_cache_round_trip(tmp_path):
+    from paper_1707_03974_amd import tuning
+    g = _gpu_problem(synth.workload("torus4x3"))
+    path = str(tmp_path / "plans.json")
+    e1, t1 = tuning.tuned_plan(g, "f64", reps=1, path=path)
+    assert t1 and e1["ms"] > 0
+    g.set_plan("f64", 0, 0, 0, 0)
+    e2, t2 = tuning.tuned_plan(g, "f64", reps=1, path=path)
+    assert t2 is None and e2 == e1
+    assert g.get_plan("f64") == {k: e1[k] for k in ("down", "up_cw", "up", "map")}

@@ -139,7 +139,8 @@ pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* str
  *       F64: 16, 32, 64, 128);
  * up: 1 the hops of a row are loaded in batches of 8, 2 all hops of a row are
  *       loaded before the first multiply-add (up_cw <= 64), 3 batches of 16
- *       (D < 2^32);
+ *       (D < 2^32), 4 batches of 8 with 16-byte lanes, several rows of the
+ *       chunk per wave (up_cw * element size <= 512 bytes; D < 2^32);
  * map: order of the up-pass tiles: 1 each XCD walks a pair of neighbouring
  *       column chunks at a time (blocks are dealt to XCDs round robin),
  *       2 chunk-major over all blocks, 3 each XCD walks one chunk at a time.

@@ -538,7 +538,7 @@ struct __align__(16) UpHop<double> {
 // that XCD's L2, and both halves of every 128-byte line are used there.
 // The tile's hop lists are decoded once into LDS.  IDX64 selects 64-bit
 // element offsets (D >= 2^32).
-template <typename T, typename E, int CW, int ROWS_PER_TILE, bool IDX64, int NB>
+template <typename T, typename E, int CW, int ROWS_PER_TILE, bool IDX64, int NB, int VECP = 0>
 __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const T* __restrict__ x, T* __restrict__ y) {
     if (a.skip && *a.skip) return;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -568,7 +568,9 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
     }
     __syncthreads();
     // each lane owns VEC consecutive columns: CW / VEC lanes per row segment
-    constexpr int VEC = (CW >= 256 && sizeof(T) == 4) ? 4 : (CW >= 128 ? 2 : 1);
+    // (VECP > 0: 16-byte lanes at any chunk width, several rows per wave)
+    constexpr int VEC = VECP > 0 ? VECP : ((CW >= 256 && sizeof(T) == 4) ? 4 : (CW >= 128 ? 2 : 1));
+    static_assert(CW % VEC == 0 && kUpBlock % (CW / VEC) == 0, "lanes per row segment");
     constexpr int LANES = CW / VEC;
     const uint32_t lane = threadIdx.x % LANES;
     const uint64_t d = (uint64_t)chunk * CW + (uint64_t)lane * VEC;
@@ -852,6 +854,17 @@ void launch_wide_fused(int variant, uint64_t grid, size_t lds, hipStream_t s, co
 template <typename T>
 constexpr int up_rows() { return 8; }
 
+// Wide lanes (plan up 4): 16 bytes per lane, so a wave covers 64 * 16 / (CW * sizeof(T)) rows of
+// the chunk at once and a tile holds one row per lane group of the work group.
+template <typename T, int CW>
+constexpr int wide_rows() { return kUpBlock / (CW * (int)sizeof(T) / 16); }
+
+template <typename T, typename E, int CW>
+void launch_up_wide(uint64_t blocks, size_t lds, hipStream_t s, const UpArgs<T, E>& ua, const T* x, T* y) {
+    hipLaunchKernelGGL((k_hv_up<T, E, CW, wide_rows<T, CW>(), false, 8, 16 / (int)sizeof(T)>), dim3((unsigned)blocks),
+                       dim3(kUpBlock), lds, s, ua, x, y);
+}
+
 // nb: hop loads in flight per batch (8, or 16 with 32-bit offsets)
 template <typename T, typename E, int CW>
 void launch_up(bool idx64, int nb, uint64_t blocks, size_t lds, hipStream_t s, const UpArgs<T, E>& ua, const T* x,
@@ -963,10 +976,16 @@ uint64_t down_grid(const pdz_problem_s* p, size_t es, const HvPlan& plan, unsign
     return down_geom(p, es, plan, cu).grid;
 }
 
+// Rows per up-pass tile: 8, or one per lane group with wide lanes (plan up 4).
+int up_tile_rows(size_t es, const HvPlan& plan) {
+    if (plan.up == 4) return kUpBlock / (int)((size_t)plan.up_cw * es / 16);
+    return 8;
+}
+
 // Up-pass work groups (tile order padded to whole XCD rounds).
 uint64_t up_blocks(const pdz_problem_s* p, size_t es, const HvPlan& plan) {
     constexpr uint64_t kXcd = 8;
-    const uint64_t rows = es == 8 ? (uint64_t)up_rows<double>() : (uint64_t)up_rows<float>();
+    const uint64_t rows = (uint64_t)up_tile_rows(es, plan);
     const uint64_t rt = (p->up.D + rows - 1) / rows;
     const uint64_t nch = (p->dn.D + plan.up_cw - 1) / plan.up_cw;
     if (plan.map == 1) return kXcd * (((nch + 1) / 2 + kXcd - 1) / kXcd) * 2 * rt;
@@ -1050,8 +1069,8 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     ua.add_y = (split && split->z) ? 0 : 1;
     ua.dotp = split ? split->dotp_up : nullptr;
     T* yout = (split && split->z) ? static_cast<T*>(split->z) : y;
-    constexpr int ROWS = up_rows<T>();
     const int CW = plan.up_cw;
+    const int ROWS = up_tile_rows(sizeof(T), plan);
     const bool idx64 = p->D > 0xFFFFFFFFull;
     ua.row_tiles = (uint32_t)((D_up + ROWS - 1) / ROWS);
     ua.max_hops = p->up.max_hops;
@@ -1060,7 +1079,23 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     ua.map = plan.map;
     const uint64_t blocks = up_blocks(p, sizeof(T), plan);
     const int nb = plan.up == 3 ? 16 : 8;
-    if (plan.up == 2 && !idx64) {
+    if (plan.up == 4 && !idx64) {
+        if (sizeof(T) == 8) {
+            if (CW == 16)
+                launch_up_wide<T, E, 16>(blocks, lds, s, ua, x, yout);
+            else if (CW == 32)
+                launch_up_wide<T, E, 32>(blocks, lds, s, ua, x, yout);
+            else
+                launch_up_wide<T, E, 64>(blocks, lds, s, ua, x, yout);
+        } else {
+            if (CW == 32)
+                launch_up_wide<T, E, 32>(blocks, lds, s, ua, x, yout);
+            else if (CW == 64)
+                launch_up_wide<T, E, 64>(blocks, lds, s, ua, x, yout);
+            else
+                launch_up_wide<T, E, 128>(blocks, lds, s, ua, x, yout);
+        }
+    } else if (plan.up == 2 && !idx64) {
         // preloaded rows: one column per lane (CW <= 64)
         if (sizeof(T) == 8 && CW == 16)
             launch_up_pre<T, E, 16>(ua.max_hops, blocks, lds, s, ua, x, yout);
@@ -1132,6 +1167,14 @@ pdz_status set_up_lds() {
 }
 
 template <typename T, typename E, int CW>
+pdz_status set_up_wide_lds() {
+    PDZ_HIP(hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_hv_up<T, E, CW, wide_rows<T, CW>(), false, 8, 16 / (int)sizeof(T)>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
+    return ok();
+}
+
+template <typename T, typename E, int CW>
 pdz_status set_up_pre_lds() {
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up_pre<T, E, CW, up_rows<T>(), 16>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
@@ -1163,6 +1206,9 @@ pdz_status prepare_one() {
     if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 32 : 64>();
     if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 64 : 128>();
     if (st == PDZ_OK) st = set_up_lds<T, E, sizeof(T) == 8 ? 128 : 256>();
+    if (st == PDZ_OK) st = set_up_wide_lds<T, E, sizeof(T) == 8 ? 16 : 32>();
+    if (st == PDZ_OK) st = set_up_wide_lds<T, E, sizeof(T) == 8 ? 32 : 64>();
+    if (st == PDZ_OK) st = set_up_wide_lds<T, E, sizeof(T) == 8 ? 64 : 128>();
     if (sizeof(T) == 8 && st == PDZ_OK) st = set_up_pre_lds<T, E, 16>();
     if (st == PDZ_OK) st = set_up_pre_lds<T, E, 32>();
     if (st == PDZ_OK) st = set_up_pre_lds<T, E, 64>();
@@ -1199,7 +1245,7 @@ std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
     const bool pre_ok = p->up.max_hops <= 48 && p->D <= 0xFFFFFFFFull;
     for (int dv : downs)
         for (int k = 0; k < kNumCw; ++k)
-            for (int um = 1; um <= 3; ++um)
+            for (int um = 1; um <= 4; ++um)
                 for (int mp = 1; mp <= 3; ++mp) {
                     HvPlan c;
                     c.down = dv;
@@ -1208,6 +1254,8 @@ std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
                     c.map = mp;
                     if (um == 2 && (!pre_ok || cws[k] > 64)) continue;
                     if (um == 3 && p->D > 0xFFFFFFFFull) continue;
+                    // wide lanes: 16-byte lanes, at most 32 lanes per row segment
+                    if (um == 4 && (p->D > 0xFFFFFFFFull || (size_t)cws[k] * es / 16 > 32)) continue;
                     if (c.down != d.down || c.up_cw != d.up_cw || c.up != d.up || c.map != d.map) out.push_back(c);
                 }
     return out;

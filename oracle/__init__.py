@@ -16,7 +16,9 @@ Everything here is the plain definition, written from the paper:
   site index increasing right to left), so every sign is counted, not derived;
 * Lanczos is the textbook three-term recurrence (cited in Sec. I) with full
   re-orthogonalisation and LAPACK's tridiagonal eigensolver;
-* the random start vector is SplitMix64 (Steele, Lea, Flood, OOPSLA 2014).
+* the random start vector is SplitMix64 (Steele, Lea, Flood, OOPSLA 2014);
+* fermion operators between sectors and the resolvent of the dynamical
+  correlations are the operator algebra above and a spectral sum (dynamics.py).
 
 The oracle shares no code with the HIP path.  Its inputs come from synth/.
 """
@@ -27,5 +29,6 @@ from .hamiltonian import (Problem, build_csr, hv_rows, diag_values, nnz_structur
 from .lanczos import lanczos, LanczosResult
 from .splitmix import splitmix64_mix, splitmix64_outputs, start_vector
 from . import mlp
+from . import dynamics
 
 __all__ = [n for n in dir() if not n.startswith("_")]

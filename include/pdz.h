@@ -235,6 +235,41 @@ pdz_status pdz_lanczos_default_opts(pdz_lanczos_opts* o);
 pdz_status pdz_lanczos_kernel_times(pdz_problem p, const pdz_lanczos_opts* o, void* ws, size_t ws_bytes,
                                     int32_t steps, double* ms, int32_t* fused, void* stream);
 
+/* ------------------------------------------- dynamical correlations */
+
+/* Fermion operator between sectors, for the Lanczos continued fraction of a
+ * dynamical correlation function (the method Sec. I cites): y = c_{site,spin} x
+ * (op 0: one electron of that spin removed) or y = c+_{site,spin} x (op 1: one
+ * added).  x: D(src) elements in the layout of `src`; y: D(dst) elements of
+ * `dst`, a problem on the same sites whose fillings differ from those of src
+ * by exactly that electron (its bonds and U are not used here).  Each target
+ * state has at most one source state: its string of that spin with the site
+ * toggled, ranked by the forward map (Eq. 3).  Sign: the operator order of H
+ * (Sec. II.A, up operators left of down operators, site index growing from
+ * right to left): (-1)^(electrons of that spin above the site), times
+ * (-1)^(n_up) for a down operator.  spin 0 = up, 1 = down.  x and y must not
+ * overlap.  Asynchronous.  Errors: PDZ_EINVAL (null pointer, site or spin or
+ * op out of range, dst not the neighbouring sector, overlap, other device). */
+pdz_status pdz_fermion_op(pdz_problem src, pdz_problem dst, int32_t site, int32_t spin, int32_t op, pdz_dtype dt,
+                          const void* x, void* y, void* stream);
+
+/* After pdz_lanczos on `ws` (same options; refine >= 1 if a Ritz vector was
+ * requested): the n = min(steps, max_n) recurrence coefficients alpha[0..n)
+ * and beta[0..n] (beta[0] = 0, beta[k] for k >= 1 the norm of the k-th
+ * residual; T_n has diagonal alpha and off-diagonal beta[1..n-1]), and the
+ * norm of the start vector.  Host arrays of max_n and max_n + 1 doubles.
+ * Synchronous.  Errors: PDZ_EINVAL. */
+pdz_status pdz_lanczos_coefficients(pdz_problem p, const pdz_lanczos_opts* o, const void* ws, size_t ws_bytes,
+                                    int32_t max_n, double* alpha, double* beta, double* norm0, int32_t* n_out);
+
+/* Continued fraction of the resolvent <v0|(w - H)^{-1}|v0> from n Lanczos
+ * coefficients started at v0 (norm2 = |v0|^2):
+ *   g(w) = norm2 / (w - alpha[0] - beta[1]^2 / (w - alpha[1] - ... - beta[n-1]^2 / (w - alpha[n-1]))),
+ * for the nw complex points w = w_re + i w_im; exact for the Krylov space of
+ * dimension n.  Host arrays; no device work.  Errors: PDZ_EINVAL. */
+pdz_status pdz_continued_fraction(const double* alpha, const double* beta, int32_t n, double norm2,
+                                  const double* w_re, const double* w_im, int32_t nw, double* g_re, double* g_im);
+
 /* Bytes of device workspace pdz_lanczos needs for these options. */
 pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, size_t* bytes);
 

@@ -192,11 +192,14 @@ class Problem:
         _lib.check(lib().pdz_lanczos_workspace_size(self._h, ctypes.byref(opts), ctypes.byref(n)))
         return n.value
 
-    def lanczos(self, v0=None, ritz=None, workspace=None, stream=None, allow_noconv=True, history=False, **kw):
+    def lanczos(self, v0=None, ritz=None, workspace=None, stream=None, allow_noconv=True, history=False,
+                coefficients=False, **kw):
         """Lowest eigenvalue by the device-resident Lanczos of libpdz.
 
         Returns a dict with E0, resid_est, E0_refined, resid_refined, seconds,
-        iters, converged, status.
+        iters, converged, restart_iters, status; with history=True the Ritz value
+        of every step ("thetas"); with coefficients=True the recurrence
+        coefficients ("alpha", "beta") and the start vector's norm ("norm0").
         """
         import torch
         if ritz is not None:
@@ -220,6 +223,17 @@ class Problem:
             _lib.check(lib().pdz_lanczos_history(self._h, ctypes.byref(o), ctypes.c_void_p(workspace.data_ptr()),
                                                  workspace.numel(), o.max_iter, buf, ctypes.byref(n)))
             out["thetas"] = list(buf[:n.value])
+        if coefficients:
+            m = max(1, o.max_iter)
+            a = (ctypes.c_double * m)()
+            b = (ctypes.c_double * (m + 1))()
+            nrm = ctypes.c_double()
+            n = ctypes.c_int32()
+            _lib.check(lib().pdz_lanczos_coefficients(self._h, ctypes.byref(o), ctypes.c_void_p(workspace.data_ptr()),
+                                                      workspace.numel(), m, a, b, ctypes.byref(nrm), ctypes.byref(n)))
+            out["alpha"] = list(a[:n.value])
+            out["beta"] = list(b[:n.value + 1])
+            out["norm0"] = nrm.value
         return out
 
 
@@ -323,6 +337,33 @@ class Batch:
                                      workspace.numel(), res, _stream_handle(stream))
         _lib.check(st, allow=(_lib.PDZ_ENOCONV,) if allow_noconv else ())
         return [{f: getattr(r, f) for f, _ in LanczosResult._fields_} for r in res], st
+
+
+def fermion_op(src, dst, site, spin, op, x, y=None, stream=None):
+    """y = c_{site,spin} x (op 0) or c+_{site,spin} x (op 1), from the sector of Problem `src` to that of
+    Problem `dst` (one electron of that spin fewer or more); spin 0 = up, 1 = down."""
+    import torch
+    if y is None:
+        y = torch.empty(dst.D, dtype=x.dtype, device=x.device)
+    _lib.check(lib().pdz_fermion_op(src.handle, dst.handle, int(site), int(spin), int(op), _dtype_code(
+        "f64" if x.dtype == torch.float64 else "f32"), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+        _stream_handle(stream)))
+    return y
+
+
+def continued_fraction(alpha, beta, norm2, w):
+    """<v0|(w - H)^{-1}|v0> from Lanczos coefficients (alpha[0..n), beta[0..n]), |v0|^2 and complex points w."""
+    import numpy as np
+    w = np.atleast_1d(np.asarray(w, dtype=np.complex128))
+    n = len(alpha)
+    a = (ctypes.c_double * max(1, n))(*alpha)
+    b = (ctypes.c_double * max(1, n))(*list(beta)[:max(1, n)])
+    wr = (ctypes.c_double * len(w))(*w.real)
+    wi = (ctypes.c_double * len(w))(*w.imag)
+    gr = (ctypes.c_double * len(w))()
+    gi = (ctypes.c_double * len(w))()
+    _lib.check(lib().pdz_continued_fraction(a, b, n, float(norm2), wr, wi, len(w), gr, gi))
+    return np.array(gr[:]) + 1j * np.array(gi[:])
 
 
 def rank(n_sites, n, bits, stream=None):

@@ -95,6 +95,15 @@ _SIGNATURES = {
                                      ctypes.POINTER(LanczosResult), _P]),
     "pdz_lanczos_kernel_times": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.c_int32,
                                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), _P]),
+    "pdz_lanczos_coefficients": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
+    "pdz_fermion_op": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                        _P]),
+    "pdz_continued_fraction": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                                ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "pdz_lanczos_history": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "pdz_batch_create": (ctypes.c_int32, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),

@@ -8,43 +8,13 @@
 // and m by one.  C(i, m) = 0 for i < m.  Both are exact integer arithmetic;
 // the binomial table is staged in LDS.
 #include "pdz_internal.h"
+#include "perfect_hash.h"
 
 namespace pdz {
 
 namespace {
 
 constexpr int kHashBlock = 256;
-
-__device__ __forceinline__ void stage_binom(uint32_t* sC, const uint32_t* __restrict__ gC) {
-    for (int k = threadIdx.x; k < kBinomStride * kBinomStride; k += blockDim.x) sC[k] = gC[k];
-    __syncthreads();
-}
-
-__device__ __forceinline__ uint32_t forward_map(uint32_t phi, const uint32_t* sC) {
-    uint32_t idx = 0;
-    int m = 0;
-    while (phi) {
-        const int i = __builtin_ctz(phi);
-        phi &= phi - 1u;
-        ++m;
-        idx += sC[i * kBinomStride + m];
-    }
-    return idx;
-}
-
-__device__ __forceinline__ uint32_t backward_map(uint32_t p, int n, int N, const uint32_t* sC) {
-    uint32_t phi = 0;
-    int m = n;
-    for (int i = N - 1; i >= 0 && m > 0; --i) {
-        const uint32_t c = sC[i * kBinomStride + m];
-        if (p >= c) {
-            phi |= 1u << i;
-            p -= c;
-            --m;
-        }
-    }
-    return phi;
-}
 
 __global__ __launch_bounds__(kHashBlock) void k_rank(const uint32_t* __restrict__ gC, int N, int n,
                                                      const uint32_t* __restrict__ bits, uint64_t count,

@@ -1141,6 +1141,30 @@ pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, 
     return ok();
 }
 
+pdz_status pdz_lanczos_coefficients(pdz_problem p, const pdz_lanczos_opts* o, const void* ws, size_t ws_bytes,
+                                    int32_t max_n, double* alpha, double* beta, double* norm0, int32_t* n_out) {
+    if (!p || !ws || !alpha || !beta || !norm0 || !n_out) return fail(PDZ_EINVAL, "NULL argument");
+    pdz_status st = check_opts(o);
+    if (st != PDZ_OK) return st;
+    pdz_lanczos_opts oo = *o;
+    if (oo.reorth) oo.use_graph = 0;
+    const Layout L = make_layout(p, &oo);
+    if (ws_bytes < L.total) return fail(PDZ_EINVAL, "workspace smaller than pdz_lanczos_workspace_size");
+    Ctl h;
+    PDZ_HIP(hipMemcpy(&h, static_cast<const char*>(ws) + L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    int n = h.k < max_n ? h.k : max_n;
+    if (n < 0) n = 0;
+    if (n > 0) {
+        PDZ_HIP(hipMemcpy(alpha, static_cast<const char*>(ws) + L.alpha, (size_t)n * sizeof(double),
+                          hipMemcpyDeviceToHost));
+        PDZ_HIP(hipMemcpy(beta, static_cast<const char*>(ws) + L.beta, (size_t)(n + 1) * sizeof(double),
+                          hipMemcpyDeviceToHost));
+    }
+    *norm0 = h.norm0;
+    *n_out = n;
+    return ok();
+}
+
 pdz_status pdz_lanczos_history(pdz_problem p, const pdz_lanczos_opts* o, const void* ws, size_t ws_bytes,
                                int32_t max_n, double* theta_host, int32_t* n_out) {
     if (!p || !ws || !theta_host || !n_out) return fail(PDZ_EINVAL, "NULL argument");

@@ -202,6 +202,52 @@ def batched_bench(torch, pdz, synth, reps, rel=1e-8):
     return out
 
 
+def dynamics_bench(torch, pdz, synth, steps=100, reps=10):
+    """Electron-removal resolvent on the 4x4 NN+NNN cluster: ground state (FP32 Lanczos + FP64 refinement),
+    c_(0,up) into the 7 + 8 sector (D = 147,232,800), `steps` FP32 Lanczos steps there and the continued
+    fraction of <phi|(w - H)^(-1)|phi> on a grid."""
+    import numpy as np
+    from paper_1707_03974_amd import dynamics
+    w = synth.workload("torus4x4_nnn")
+    g = pdz.Problem.from_workload(w)
+    psi = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r0 = g.lanczos(ritz=psi, storage="f32", tol=1e-7, max_iter=400, refine=1, keep_basis=1)
+    torch.cuda.synchronize()
+    t_gs = time.perf_counter() - t0
+    psi32 = psi.float()
+    del psi
+    tgt = dynamics.neighbour_problem(g, 0, 0)
+    phi = torch.empty(tgt.D, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        pdz.fermion_op(g, tgt, 0, 0, 0, psi32, phi, stream=stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        pdz.fermion_op(g, tgt, 0, 0, 0, psi32, phi, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    op_ms = ev0.elapsed_time(ev1) / reps
+    op_bytes = 2.0 * tgt.D * 4      # one source row read per target row, the target written
+    del phi
+    E0 = r0["E0_refined"]
+    pts = np.linspace(-16.0, 8.0, 481) + 0.1j     # covers the 7 + 8 sector's spectrum seen from phi
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R, res = dynamics.resolvent(g, psi32, 0, 0, 0, pts, steps=steps, storage="f32", target=tgt)
+    torch.cuda.synchronize()
+    t_res = time.perf_counter() - t0
+    A = -R.imag / np.pi       # spectral weight of the removal part against w = E0 - omega
+    return {"workload": "torus4x4_nnn, c_(0,up): 8+8 -> 7+8", "D_target": tgt.D, "E0": E0,
+            "ground_state_s": t_gs, "fermion_op_ms": op_ms, "fermion_op_algorithmic_GBs": op_bytes / (op_ms * 1e-3) / 1e9,
+            "lanczos_steps": res["iters"], "resolvent_s": t_res, "norm2": res["norm0"] ** 2,
+            "weight_on_grid": float(A.sum() * (pts[1].real - pts[0].real)),   # -> norm2 (sum rule) as the window widens
+            "first_levels": [float(x) for x in res["alpha"][:3]]}
+
+
 def learned_bench(torch, pdz, synth, steps=3000):
     """Learned start on the 4x4 cluster with 7 + 7 electrons at U = 5 against random starts (time to E0 at 1e-8)."""
     import statistics
@@ -308,6 +354,7 @@ def main():
     ap.add_argument("--no-time-to-e0", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-dynamics", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 32-cluster batched section and print its JSON object")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -409,6 +456,11 @@ def main():
         learned_res = learned_bench(torch, pdz, synth)
         _log(f"learned start: {json.dumps({k: v for k, v in learned_res.items() if k != 'compare'})}")
 
+    dyn = None
+    if not args.no_dynamics:
+        dyn = dynamics_bench(torch, pdz, synth)
+        _log(f"dynamics: {dyn}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -447,6 +499,7 @@ def main():
         "time_to_E0_1e-8": tte,
         "batched": batched,
         "learned_start": learned_res,
+        "dynamics": dyn,
         "copy_calibration": copy,
         "hv_plans": tuned,
         "cpu_baseline": cpu,

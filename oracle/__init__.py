@@ -18,7 +18,9 @@ Everything here is the plain definition, written from the paper:
   re-orthogonalisation and LAPACK's tridiagonal eigensolver;
 * the random start vector is SplitMix64 (Steele, Lea, Flood, OOPSLA 2014);
 * fermion operators between sectors and the resolvent of the dynamical
-  correlations are the operator algebra above and a spectral sum (dynamics.py).
+  correlations are the operator algebra above and a spectral sum (dynamics.py);
+* total-momentum sectors (Sec. IV.A) are sorted lists of (up, down) orbital
+  strings and Eq. (4) applied term by term with the same algebra (momentum.py).
 
 The oracle shares no code with the HIP path.  Its inputs come from synth/.
 """
@@ -30,5 +32,6 @@ from .lanczos import lanczos, LanczosResult
 from .splitmix import splitmix64_mix, splitmix64_outputs, start_vector
 from . import mlp
 from . import dynamics
+from . import momentum
 
 __all__ = [n for n in dir() if not n.startswith("_")]

@@ -73,7 +73,9 @@ typedef struct {
     int32_t max_hops_up; /* most hops out of one up-sector state            */
     int32_t max_hops_dn; /* most hops out of one down-sector state          */
     int32_t device;      /* HIP device the handle lives on                  */
-    int32_t hv_path;     /* 0: sector hop tables, 1: on-the-fly ranks        */
+    int32_t hv_path;     /* 0: sector hop tables, 1: on-the-fly ranks,
+                            2: momentum space (D_up: every up string,
+                            D_dn: every down string, hops_*: 0)        */
 } pdz_info;
 
 /* ------------------------------------------------------------------ problems */
@@ -296,6 +298,59 @@ pdz_status pdz_lanczos(pdz_problem p, const pdz_lanczos_opts* o, const void* v0,
  * argument, ws too small). */
 pdz_status pdz_lanczos_history(pdz_problem p, const pdz_lanczos_opts* o, const void* ws, size_t ws_bytes,
                                int32_t max_n, double* theta_host, int32_t* n_out);
+
+/* ----------------------------------------- translation symmetry (momentum) */
+
+/* Band energies of a translation-invariant hopping (Sec. IV.A): for an
+ * L1 x L2 periodic cluster with sites s = x + L1*y and the bonds of Eq. 1,
+ * eps[k] = -(1/N) sum_bonds t 2 cos(k . (r_j - r_i)) at the momentum
+ * k = (2 pi/L1 (k mod L1), 2 pi/L2 (k div L1)), N = L1 L2 values (for the
+ * square lattice with t and t': -2t(cos kx + cos ky) - 4t' cos kx cos ky).
+ * Host only.  Errors: PDZ_ERANGE (N outside [1, 32]); PDZ_EINVAL (NULL, bad
+ * bond, a bond list not invariant under the lattice translations). */
+pdz_status pdz_kspace_band(int32_t L1, int32_t L2, const pdz_bond* bonds, int32_t n_bonds, double* eps);
+
+/* Hubbard problem in momentum space restricted to total momentum K (Sec. IV.A,
+ * Eq. 4): H = sum_{k,s} eps_k n_{k,s} + (U/N) sum_{k,k',q} c+_{k+q,up}
+ * c+_{k'-q,dn} c_{k',dn} c_{k,up} on the states of n_up + n_dn electrons whose
+ * orbital momenta sum to K (orbital i = momentum i as in pdz_kspace_band;
+ * momenta add modulo the Brillouin zone).  eps: N host doubles.
+ * Basis order and index: the spin-full k-space forward map of Sec. IV.A with
+ * the extended counts C_i^m(k) (Eq. 5, reading i as the number of orbitals
+ * 0..i-1) and Ct_i^m(k) (Eq. 7): states ordered by the up string, then the
+ * down string, as integers; a vector is the ragged matrix X[up string][rank
+ * of the down string among those of momentum K - K_up].  Signs: within one
+ * spin, c+_a c_b gives (-1)^(electrons strictly between a and b) (the operator
+ * order of Sec. II.A).  The returned handle works with pdz_problem_info,
+ * pdz_hv, pdz_lanczos* and pdz_problem_destroy (no launch plans, batches or
+ * fermion operators).  Synchronous: builds the down strings of every momentum
+ * (backward map), their move table (forward map) and the row table on the
+ * device and checks that the spin-full forward map lays the rows end to end.
+ * Errors: PDZ_ERANGE (N outside [1, 32], empty sector, a row longer than 8192
+ * down strings, counts beyond 32 bits); PDZ_EINVAL (NULL, fillings outside
+ * [0, N], K outside [0, N), non-finite eps or U); PDZ_EDEVICE (a map left its
+ * range: a library fault); PDZ_ENOMEM / PDZ_EHIP. */
+pdz_status pdz_kspace_problem_create(int32_t L1, int32_t L2, const double* eps, double U, int32_t n_up,
+                                     int32_t n_dn, int32_t K, pdz_problem* out);
+
+/* Spin-full k-space forward map: idx[t] = index of (up[t], dn[t]) in the
+ * sector of p.  Device arrays of count elements.  A pair with the wrong
+ * fillings, bits beyond N or another total momentum gets idx = 2^64 - 1 and
+ * sets bit 1 of the device error word (pdz_device_errors).  Asynchronous.
+ * Errors: PDZ_EINVAL (NULL, not a momentum-space problem). */
+pdz_status pdz_kspace_rank(pdz_problem p, const uint32_t* up, const uint32_t* dn, uint64_t count, uint64_t* idx,
+                           void* stream);
+
+/* Spin-full k-space backward map: (up[t], dn[t]) of index idx[t].  An index
+ * >= D gives 0xFFFFFFFF in both and sets bit 2 of the device error word.
+ * Device arrays.  Asynchronous.  Errors: PDZ_EINVAL. */
+pdz_status pdz_kspace_unrank(pdz_problem p, const uint64_t* idx, uint64_t count, uint32_t* up, uint32_t* dn,
+                             void* stream);
+
+/* Shape of a momentum-space problem: cluster sides, K, longest row (down
+ * strings of one momentum) and number of non-empty rows.  Any output may be
+ * NULL.  Errors: PDZ_EINVAL (NULL p, not a momentum-space problem). */
+pdz_status pdz_kspace_info(pdz_problem p, int32_t* L1, int32_t* L2, int32_t* K, uint32_t* row_max, uint64_t* rows);
 
 /* ---------------------------------------------------------------- batches */
 

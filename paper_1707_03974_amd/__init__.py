@@ -8,7 +8,7 @@ import ctypes
 from . import _lib
 from ._lib import PdzError, PDZ_F64, PDZ_F32, LanczosOpts, LanczosResult
 
-__all__ = ["Problem", "Batch", "rank", "unrank", "device_errors", "PdzError", "PDZ_F64", "PDZ_F32", "lib",
+__all__ = ["Problem", "KProblem", "kspace_band", "Batch", "rank", "unrank", "device_errors", "PdzError", "PDZ_F64", "PDZ_F32", "lib",
            "LanczosOpts", "LanczosResult"]
 
 
@@ -235,6 +235,73 @@ class Problem:
             out["beta"] = list(b[:n.value + 1])
             out["norm0"] = nrm.value
         return out
+
+
+def _bond_array(bonds):
+    arr = (_lib.Bond * max(1, len(bonds)))()
+    for k, b in enumerate(bonds):
+        i, j, t = (b.i, b.j, b.t) if hasattr(b, "i") else b
+        arr[k] = _lib.Bond(int(i), int(j), float(t))
+    return arr
+
+
+def kspace_band(L1, L2, bonds):
+    """Band energies eps_k (N = L1*L2 values) of a translation-invariant bond list (pdz_kspace_band)."""
+    n = L1 * L2
+    out = (ctypes.c_double * max(1, n))()
+    _lib.check(lib().pdz_kspace_band(int(L1), int(L2), _bond_array(bonds) if bonds else None, len(bonds), out))
+    return [out[k] for k in range(n)]
+
+
+class KProblem(Problem):
+    """Hubbard problem in momentum space at total momentum K (Sec. IV.A, Eq. 4).
+
+    hv, lanczos, D and nnz work as for Problem; the vector is in the k-space
+    forward map's order (up string, then down string).
+    """
+
+    def __init__(self, L1, L2, eps, U, n_up, n_dn, K):
+        L = lib()
+        n = L1 * L2
+        e = (ctypes.c_double * max(1, n))(*[float(v) for v in eps])
+        if len(eps) != n:
+            raise ValueError("eps needs L1 * L2 values")
+        h = ctypes.c_void_p()
+        _lib.check(L.pdz_kspace_problem_create(int(L1), int(L2), e, float(U), int(n_up), int(n_dn), int(K),
+                                               ctypes.byref(h)))
+        self._h = h
+        self.L1, self.L2, self.K = L1, L2, K
+        self.eps = [float(v) for v in eps]
+        self.n_sites, self.U, self.n_up, self.n_dn = n, U, n_up, n_dn
+        self.bonds = []
+        self.info = self._info()
+        rm, nr = ctypes.c_uint32(), ctypes.c_uint64()
+        _lib.check(L.pdz_kspace_info(self._h, None, None, None, ctypes.byref(rm), ctypes.byref(nr)))
+        self.info["row_max"], self.info["rows"] = rm.value, nr.value
+
+    @classmethod
+    def from_bonds(cls, L1, L2, bonds, U, n_up, n_dn, K):
+        return cls(L1, L2, kspace_band(L1, L2, bonds), U, n_up, n_dn, K)
+
+    def rank(self, up, dn, stream=None):
+        """Spin-full k-space forward map of device 32-bit tensors up, dn (bit patterns of the strings) -> int64
+        tensor (bit pattern of the uint64 index; -1 marks a pair outside the sector)."""
+        import torch
+        out = torch.empty(up.numel(), dtype=torch.int64, device=up.device)
+        _lib.check(lib().pdz_kspace_rank(self._h, ctypes.c_void_p(up.data_ptr()), ctypes.c_void_p(dn.data_ptr()),
+                                         up.numel(), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def unrank(self, idx, stream=None):
+        """Spin-full k-space backward map of a device int64 tensor -> (up, dn) int32 tensors holding the
+        strings' bit patterns."""
+        import torch
+        up = torch.empty(idx.numel(), dtype=torch.int32, device=idx.device)
+        dn = torch.empty(idx.numel(), dtype=torch.int32, device=idx.device)
+        _lib.check(lib().pdz_kspace_unrank(self._h, ctypes.c_void_p(idx.data_ptr()), idx.numel(),
+                                           ctypes.c_void_p(up.data_ptr()), ctypes.c_void_p(dn.data_ptr()),
+                                           _stream_handle(stream)))
+        return up, dn
 
 
 class Batch:

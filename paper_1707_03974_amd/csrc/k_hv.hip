@@ -1273,6 +1273,10 @@ bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan) {
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                      const int* skip, unsigned passes, const HvSplit* split) {
     if (split && p->hv_path != 0) return fail(PDZ_EINVAL, "split H.v needs the table path");
+    if (p->ks) {
+        if (passes != (kPassDown | kPassUp)) return fail(PDZ_EINVAL, "a momentum-space H.v has no separate passes");
+        return launch_hvk(p, dt, x, y, s, skip);
+    }
     if (dt == PDZ_F64)
         return run_hv<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip,
                               passes, split);

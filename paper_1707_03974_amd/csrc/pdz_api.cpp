@@ -45,6 +45,7 @@ pdz_status device_ctx(DeviceCtx** out) {
         PDZ_HIP(hipMemcpy(c.binom, C.data(), C.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         pdz_status hs = hv_prepare();
         if (hs == PDZ_OK) hs = batch_prepare();
+        if (hs == PDZ_OK) hs = kspace_prepare();
         if (hs != PDZ_OK) return hs;
         c.cu_count = prop.multiProcessorCount;
         c.lds_per_block = prop.sharedMemPerBlock;
@@ -99,6 +100,7 @@ static void destroy_problem(pdz_problem_s* p) {
     if (p->d_bonds) (void)hipFree(p->d_bonds);
     if (p->d_coef64) (void)hipFree(p->d_coef64);
     if (p->d_coef32) (void)hipFree(p->d_coef32);
+    kspace_free(p->ks);
     (void)hipSetDevice(prev);
     delete p;
 }

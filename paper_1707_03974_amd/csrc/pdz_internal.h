@@ -49,6 +49,7 @@ struct SectorTables {
 }  // namespace pdz
 
 namespace pdz {
+struct KSpace;   // momentum-space sector tables (k_kspace.hip)
 // H.v launch plan for one precision (0 = automatic choice).
 struct HvPlan {
     int down = 0;    // 1: one row per group, hop table loaded up front; 2: one row, table in a loop;
@@ -72,7 +73,8 @@ struct pdz_problem_s {
     std::vector<double> coef_host;       // signed hop amplitudes
     double* d_coef64 = nullptr;
     float* d_coef32 = nullptr;
-    int hv_path = 0;                     // 0 tables, 1 on the fly
+    int hv_path = 0;                     // 0 tables, 1 on the fly, 2 momentum space (ks)
+    pdz::KSpace* ks = nullptr;           // momentum-space sector (Sec. IV.A), else NULL
     pdz::HvPlan plan[2];                 // per pdz_dtype
 };
 
@@ -133,6 +135,11 @@ pdz_status build_sector_tables(const uint32_t* d_binom, int N, int n, const Bond
 pdz_status build_compact_table(SectorTables* st, int ncoef, hipStream_t s);
 pdz_status hv_prepare();   // per-device kernel attributes, called once outside any capture
 pdz_status batch_prepare();   // the same for the batched H.v kernels
+pdz_status kspace_prepare();  // the same for the momentum-space H.v kernels
+void kspace_free(KSpace* ks);
+// y = H x on a momentum-space problem (every pass at once; no split form)
+pdz_status launch_hvk(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
+                      const int* skip);
 // Candidate plans valid for this problem and precision; the first is the default.
 std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt);
 bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan);

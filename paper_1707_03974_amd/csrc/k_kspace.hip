@@ -62,7 +62,12 @@ struct KSpace {
     uint32_t* d_dn_str = nullptr;   // D_dn: down strings, grouped by momentum, ascending within
     double* d_eps_dn = nullptr;     // D_dn: band energy of each down string
     uint8_t* d_dcnt = nullptr;      // D_dn x N: down moves of (string, q), [momentum][q][rank]
-    uint32_t* d_dtab = nullptr;     // entries: source rank | sign << 31, slot major per (momentum, q)
+    void* d_dtab = nullptr;         // entries: source rank | sign in the top bit (16 bits when every
+                                    // momentum has < 2^15 down strings, else 32), slot major per (momentum, q)
+    bool dtab16 = false;
+    int uslots = 0;                 // most up moves of one string for one q
+    uint64_t* d_upm = nullptr;      // D_up x (N-1) x uslots: source row start | sign << 63 of each up
+                                    // move, in electron order, ~0 past the last
     uint32_t* d_up_str = nullptr;   // D_up: every up string, ascending (backward map of Sec. III)
     uint64_t* d_row_off = nullptr;  // D_up: start of the row of each up string
     uint8_t* d_row_kd = nullptr;    // D_up: momentum K - K_up of the row's down strings
@@ -74,7 +79,6 @@ namespace {
 
 constexpr int kKBlock = 256;
 constexpr int kKMaxZ = 32 * kKBlock;   // longest row (down strings of one momentum) the H.v kernel takes
-constexpr uint32_t kNegBit = 0x80000000u;
 
 struct KArgs {
     const uint8_t* kadd;
@@ -87,14 +91,16 @@ struct KArgs {
     const uint32_t* dn_str;
     const double* eps_dn;
     const uint8_t* dcnt;
-    const uint32_t* dtab;
+    const void* dtab;
+    const uint64_t* upm;
     const uint32_t* up_str;
     const uint64_t* row_off;
     const uint8_t* row_kd;
     const double* eps_up;
     const uint32_t* rows;
     uint64_t nrows, D_up, D_dn, D;
-    int N, n_up, n_dn, nmax, K;
+    int N, n_up, n_dn, nmax, K, uslots, slots;
+    uint32_t Lmax;
     double u_n;      // U / N
     double diag_u;   // (U / N) n_up n_dn: the q = 0 part of the interaction
 };
@@ -204,8 +210,10 @@ __global__ __launch_bounds__(kKBlock) void k_kdn_states(const KArgs a, uint32_t*
 // Down-move table: for target string d' (momentum kd) and q != 0, every
 // electron p' (ascending) with p' + q empty gives the source string
 // d' - p' + (p' + q) of momentum kd + q; its rank comes from the forward map.
-__global__ __launch_bounds__(kKBlock) void k_kdn_moves(const KArgs a, int slots, uint8_t* dcnt, uint32_t* dtab,
+template <typename TE>
+__global__ __launch_bounds__(kKBlock) void k_kdn_moves(const KArgs a, int slots, uint8_t* dcnt, TE* dtab,
                                                         uint32_t* err) {
+    constexpr TE neg = (TE)((TE)1 << (8 * sizeof(TE) - 1));
     __shared__ uint8_t skadd[kMaxSites * kMaxSites];
     stage_kadd(skadd, a.kadd, a.N);
     const uint64_t total = a.D_dn * (uint64_t)a.N;
@@ -232,11 +240,11 @@ __global__ __launch_bounds__(kKBlock) void k_kdn_moves(const KArgs a, int slots,
             const uint32_t src = phi ^ (1u << p) ^ (1u << pp);
             int ks = 0;
             const uint32_t d = forward_map_k(a, skadd, src, &ks);
-            if (ks != kds || d >= a.Ld[kds] || s >= slots) {
+            if (ks != kds || d >= a.Ld[kds] || d >= (uint32_t)neg || s >= slots) {
                 atomicOr(err, kErrTable);
                 continue;
             }
-            dtab[tb + (uint64_t)s * L + dp] = d | (odd_between(phi, p, pp) ? kNegBit : 0u);
+            dtab[tb + (uint64_t)s * L + dp] = (TE)(d | (odd_between(phi, p, pp) ? neg : (TE)0));
             ++s;
         }
         dcnt[cidx] = (uint8_t)s;
@@ -260,6 +268,32 @@ __global__ __launch_bounds__(kKBlock) void k_krows(const KArgs a, const uint32_t
         row_kd[r] = (uint8_t)kd;
         row_off[r] = row_offset(a, skadd, phi, kd);
         eps_up[r] = band_sum(a.eps, phi);
+    }
+}
+
+// Up-move table: for up string r (row momentum kd) and q != 0, every electron
+// p (ascending) with p - q empty gives the source up string r - p + (p - q),
+// whose row (down momentum kd + q) starts at the spin-full forward map of it.
+__global__ __launch_bounds__(kKBlock) void k_kup_moves(const KArgs a, uint64_t* upm) {
+    __shared__ uint8_t skadd[kMaxSites * kMaxSites];
+    stage_kadd(skadd, a.kadd, a.N);
+    const uint64_t nq = (uint64_t)(a.N - 1);
+    const uint64_t total = a.D_up * nq;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = t / nq;
+        const int q = (int)(t % nq) + 1;
+        const uint32_t phi = a.up_str[r];
+        const int kds = skadd[a.row_kd[r] * a.N + q];
+        uint64_t* out = upm + t * a.uslots;
+        int s = 0;
+        for (uint32_t bits = phi; bits && s < a.uslots; bits &= bits - 1u) {
+            const int p = __builtin_ctz(bits);
+            const int pm = ksub(skadd, a.N, p, q);
+            if ((phi >> pm) & 1u) continue;
+            const uint32_t src = phi ^ (1u << p) ^ (1u << pm);
+            out[s++] = row_offset(a, skadd, src, kds) | (odd_between(phi, p, pm) ? (1ull << 63) : 0ull);
+        }
+        for (; s < a.uslots; ++s) out[s] = ~0ull;
     }
 }
 
@@ -321,22 +355,118 @@ __global__ __launch_bounds__(kKBlock) void k_kunrank(const KArgs a, const uint64
 // string (row); E elements of the row per thread.  Rows are taken in the
 // order of their down momentum, a contiguous range per XCD (work group b runs
 // on XCD b mod 8), so the down-move tables a range needs stay in that XCD's L2.
+// Per momentum transfer q: Z_q = sum over the row's up moves of +-(source row)
+// is staged in LDS (contiguous row reads), then every element gathers its
+// down moves from Z_q.  Z is double buffered: the staging of the next q and
+// the gathers of this one share a phase, one barrier per q.
+constexpr uint64_t kMoveNone = ~0ull;
+constexpr uint64_t kMoveNeg = 1ull << 63;
+
+__host__ __device__ constexpr size_t hvk_z_bytes(uint32_t Lmax, size_t es) { return ((size_t)Lmax * es + 15) & ~(size_t)15; }
+
+// Z_b[d] = sum over the nv up moves mv[0..nv) of +-(source row)[d], summed in
+// move order.  Two moves at a time: the 2E loads of a thread are independent.
 template <typename T, int E>
+__device__ __forceinline__ void hvk_stage(const T* __restrict__ x, const uint64_t* mv, int nv, uint32_t Ls, T* Zb) {
+    T z[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) z[e] = (T)0;
+    int m = 0;
+    for (; m + 1 < nv; m += 2) {
+        const uint64_t e0 = mv[m], e1 = mv[m + 1];
+        const T* r0 = x + (e0 & ~kMoveNeg);
+        const T* r1 = x + (e1 & ~kMoveNeg);
+        T v0[E], v1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t d = threadIdx.x + e * kKBlock;
+            v0[e] = d < Ls ? r0[d] : (T)0;
+            v1[e] = d < Ls ? r1[d] : (T)0;
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            z[e] += (e0 & kMoveNeg) ? -v0[e] : v0[e];
+            z[e] += (e1 & kMoveNeg) ? -v1[e] : v1[e];
+        }
+    }
+    if (m < nv) {
+        const uint64_t e0 = mv[m];
+        const T* r0 = x + (e0 & ~kMoveNeg);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t d = threadIdx.x + e * kKBlock;
+            const T v = d < Ls ? r0[d] : (T)0;
+            z[e] += (e0 & kMoveNeg) ? -v : v;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t d = threadIdx.x + e * kKBlock;
+        if (d < Ls) Zb[d] = z[e];
+    }
+}
+
+// acc[e] += sum over the down moves of element tid + e*256 of +-Z[source]:
+// counts of all E elements first, then the table entries four slots at a time
+// (independent loads), then the LDS reads in slot order.
+template <typename T, int E, typename TE>
+__device__ __forceinline__ void hvk_gather(const TE* __restrict__ dtab, const uint8_t* __restrict__ cnt, uint64_t tb,
+                                           uint32_t L, int slots, const T* Z, T* acc) {
+    constexpr TE neg = (TE)((TE)1 << (8 * sizeof(TE) - 1));
+    constexpr int SB = 4;
+    int c[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t dp = threadIdx.x + e * kKBlock;
+        c[e] = dp < L ? (int)cnt[dp] : 0;
+    }
+    for (int s0 = 0; s0 < slots; s0 += SB) {
+        TE ent[SB][E];
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const uint32_t dp = threadIdx.x + e * kKBlock;
+                ent[j][e] = (s0 + j < c[e]) ? dtab[tb + (uint64_t)(s0 + j) * L + dp] : (TE)0;
+            }
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (s0 + j < c[e]) {
+                    const T v = Z[ent[j][e] & (TE)~neg];
+                    acc[e] += (ent[j][e] & neg) ? -v : v;
+                }
+    }
+}
+
+template <typename T, int E, typename TE>
 __global__ __launch_bounds__(kKBlock) void k_hvk(const KArgs a, const T* __restrict__ x, T* __restrict__ y,
                                                   const int* skip) {
     if (skip && *skip) return;
     extern __shared__ __align__(16) unsigned char kdyn[];
-    T* Z = reinterpret_cast<T*>(kdyn);
+    const size_t zb = hvk_z_bytes(a.Lmax, sizeof(T));
+    T* Zbuf[2] = {reinterpret_cast<T*>(kdyn), reinterpret_cast<T*>(kdyn + zb)};
+    uint64_t* smv = reinterpret_cast<uint64_t*>(kdyn + 2 * zb);   // (N-1) x uslots up moves of this row
     __shared__ uint8_t skadd[kMaxSites * kMaxSites];
-    __shared__ uint64_t s_moff[kMaxSites];
-    __shared__ int s_mneg[kMaxSites];   // 0 / 1 sign, -1: no move from this electron
+    __shared__ int snv[kMaxSites];                                 // valid up moves per q
     const uint64_t per = (a.nrows + 7) / 8;
     const uint64_t row = (uint64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (row >= a.nrows) return;
-    stage_kadd(skadd, a.kadd, a.N);
     const uint32_t r = a.rows[row];
-    const uint32_t phi = a.up_str[r];
+    const int nmv = (a.N - 1) * a.uslots;
+    for (int i = threadIdx.x; i < nmv; i += kKBlock) smv[i] = a.upm[(uint64_t)r * nmv + i];
+    stage_kadd(skadd, a.kadd, a.N);   // its barrier also publishes smv
     const int kd = a.row_kd[r];
+    if (threadIdx.x >= 1 && threadIdx.x < a.N) {   // moves of q = threadIdx.x, 0 when its source rows are empty
+        const int q = threadIdx.x;
+        int n = 0;
+        if (a.Ld[skadd[kd * a.N + q]] > 0)
+            while (n < a.uslots && smv[(q - 1) * a.uslots + n] != kMoveNone) ++n;
+        snv[q] = n;
+    }
+    __syncthreads();
+    const TE* __restrict__ dtab = static_cast<const TE*>(a.dtab);
     const uint32_t L = a.Ld[kd];
     const uint64_t off = a.row_off[r];
     const uint64_t dbase = a.dn_off[kd];
@@ -344,57 +474,23 @@ __global__ __launch_bounds__(kKBlock) void k_hvk(const KArgs a, const T* __restr
     T acc[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = (T)0;
-    // the electron of phi that thread tid < n_up moves
-    uint32_t my_p = 0;
-    {
-        uint32_t b = phi;
-        for (int c = 0; c < tid && b; ++c) b &= b - 1u;
-        my_p = b ? (uint32_t)__builtin_ctz(b) : 0u;
-    }
-    for (int q = 1; q < a.N; ++q) {
-        const int kds = skadd[kd * a.N + q];
-        const uint32_t Ls = a.Ld[kds];
-        if (Ls == 0) continue;   // uniform
-        if (tid < a.n_up) {   // up move p -> p - q of this thread's electron
-            const int p = (int)my_p;
-            const int pm = ksub(skadd, a.N, p, q);
-            if ((phi >> pm) & 1u) {
-                s_mneg[tid] = -1;
-            } else {
-                const uint32_t src = phi ^ (1u << p) ^ (1u << pm);
-                s_moff[tid] = row_offset(a, skadd, src, kds);
-                s_mneg[tid] = odd_between(phi, p, pm) ? 1 : 0;
-            }
-        }
+    auto next_q = [&](int q0) {   // next q >= q0 with at least one up move into non-empty rows (uniform)
+        int q = q0;
+        while (q < a.N && snv[q] == 0) ++q;
+        return q;
+    };
+    int q = next_q(1);
+    if (q < a.N) hvk_stage<T, E>(x, smv + (q - 1) * a.uslots, snv[q], a.Ld[skadd[kd * a.N + q]], Zbuf[0]);
+    __syncthreads();
+    int b = 0;
+    while (q < a.N) {
+        const int qn = next_q(q + 1);
+        if (qn < a.N) hvk_stage<T, E>(x, smv + (qn - 1) * a.uslots, snv[qn], a.Ld[skadd[kd * a.N + qn]], Zbuf[b ^ 1]);
+        hvk_gather<T, E, TE>(dtab, a.dcnt + dbase * a.N + (uint64_t)q * L, a.tb_off[kd * a.N + q], L, a.slots,
+                             Zbuf[b], acc);
         __syncthreads();
-        for (uint32_t d = tid; d < Ls; d += kKBlock) {
-            T z = (T)0;
-            for (int m = 0; m < a.n_up; ++m) {
-                const int sg = s_mneg[m];
-                if (sg < 0) continue;
-                const T v = x[s_moff[m] + d];
-                z += sg ? -v : v;
-            }
-            Z[d] = z;
-        }
-        __syncthreads();
-        const uint64_t tb = a.tb_off[kd * a.N + q];
-        const uint8_t* cnt = a.dcnt + dbase * a.N + (uint64_t)q * L;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t dp = tid + e * kKBlock;
-            if (dp < L) {
-                const int c = cnt[dp];
-                T sum = acc[e];
-                for (int s = 0; s < c; ++s) {
-                    const uint32_t ent = a.dtab[tb + (uint64_t)s * L + dp];
-                    const T v = Z[ent & ~kNegBit];
-                    sum += (ent & kNegBit) ? -v : v;
-                }
-                acc[e] = sum;
-            }
-        }
-        __syncthreads();
+        q = qn;
+        b ^= 1;
     }
     const double eu = a.eps_up[r] + a.diag_u;
 #pragma unroll
@@ -407,10 +503,17 @@ __global__ __launch_bounds__(kKBlock) void k_hvk(const KArgs a, const T* __restr
     }
 }
 
+size_t hvk_lds_bytes(uint32_t Lmax, size_t es, int N, int uslots) {
+    return 2 * hvk_z_bytes(Lmax, es) + (size_t)(N > 1 ? N - 1 : 0) * uslots * 8;
+}
+
 template <typename T, int E>
 pdz_status set_hvk_lds() {
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvk<T, E>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kKMaxZ * sizeof(T))));
+    const int bytes = (int)hvk_lds_bytes(kKMaxZ, sizeof(T), kMaxSites, kMaxSites);
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvk<T, E, uint16_t>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvk<T, E, uint32_t>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return ok();
 }
 
@@ -421,9 +524,12 @@ int hvk_elems(uint32_t Lmax) {
 }
 
 template <typename T, int E>
-void launch_hvk_e(const KArgs& a, const T* x, T* y, hipStream_t s, const int* skip, size_t lds) {
+void launch_hvk_e(const KArgs& a, bool t16, const T* x, T* y, hipStream_t s, const int* skip, size_t lds) {
     const uint64_t per = (a.nrows + 7) / 8;
-    hipLaunchKernelGGL((k_hvk<T, E>), dim3((unsigned)(8 * per)), dim3(kKBlock), lds, s, a, x, y, skip);
+    if (t16)
+        hipLaunchKernelGGL((k_hvk<T, E, uint16_t>), dim3((unsigned)(8 * per)), dim3(kKBlock), lds, s, a, x, y, skip);
+    else
+        hipLaunchKernelGGL((k_hvk<T, E, uint32_t>), dim3((unsigned)(8 * per)), dim3(kKBlock), lds, s, a, x, y, skip);
 }
 
 KArgs kargs(const pdz_problem_s* p) {
@@ -440,6 +546,10 @@ KArgs kargs(const pdz_problem_s* p) {
     a.eps_dn = ks->d_eps_dn;
     a.dcnt = ks->d_dcnt;
     a.dtab = ks->d_dtab;
+    a.upm = ks->d_upm;
+    a.uslots = ks->uslots;
+    a.slots = ks->slots;
+    a.Lmax = ks->Lmax;
     a.up_str = ks->d_up_str;
     a.row_off = ks->d_row_off;
     a.row_kd = ks->d_row_kd;
@@ -470,14 +580,15 @@ template <typename T>
 pdz_status run_hvk(const pdz_problem_s* p, const T* x, T* y, hipStream_t s, const int* skip) {
     const KArgs a = kargs(p);
     if (a.nrows == 0) return ok();
-    const size_t lds = (size_t)p->ks->Lmax * sizeof(T);
+    const size_t lds = hvk_lds_bytes(p->ks->Lmax, sizeof(T), p->ks->N, p->ks->uslots);
+    const bool t16 = p->ks->dtab16;
     switch (hvk_elems(p->ks->Lmax)) {
-        case 1: launch_hvk_e<T, 1>(a, x, y, s, skip, lds); break;
-        case 2: launch_hvk_e<T, 2>(a, x, y, s, skip, lds); break;
-        case 4: launch_hvk_e<T, 4>(a, x, y, s, skip, lds); break;
-        case 8: launch_hvk_e<T, 8>(a, x, y, s, skip, lds); break;
-        case 16: launch_hvk_e<T, 16>(a, x, y, s, skip, lds); break;
-        case 32: launch_hvk_e<T, 32>(a, x, y, s, skip, lds); break;
+        case 1: launch_hvk_e<T, 1>(a, t16, x, y, s, skip, lds); break;
+        case 2: launch_hvk_e<T, 2>(a, t16, x, y, s, skip, lds); break;
+        case 4: launch_hvk_e<T, 4>(a, t16, x, y, s, skip, lds); break;
+        case 8: launch_hvk_e<T, 8>(a, t16, x, y, s, skip, lds); break;
+        case 16: launch_hvk_e<T, 16>(a, t16, x, y, s, skip, lds); break;
+        case 32: launch_hvk_e<T, 32>(a, t16, x, y, s, skip, lds); break;
         default: return fail(PDZ_ERANGE, "momentum sector row longer than the kernel supports");
     }
     PDZ_HIP(hipGetLastError());
@@ -503,7 +614,7 @@ void kspace_free(KSpace* ks) {
     if (!ks) return;
     void* ptrs[] = {ks->d_kadd, ks->d_Ck, ks->d_Ct, ks->d_Ld, ks->d_dn_off, ks->d_tb_off, ks->d_eps,
                     ks->d_dn_str, ks->d_eps_dn, ks->d_dcnt, ks->d_dtab, ks->d_up_str, ks->d_row_off,
-                    ks->d_row_kd, ks->d_eps_up, ks->d_rows};
+                    ks->d_row_kd, ks->d_eps_up, ks->d_rows, ks->d_upm};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete ks;
@@ -585,6 +696,8 @@ pdz_status kspace_build(pdz_problem_s* p, int L1, int L2, const double* eps, int
     if (ks->Lmax > (uint32_t)kKMaxZ) return fail(PDZ_ERANGE, "a momentum sector's down strings exceed the H.v kernel's row limit");
     p->D = D;
     ks->slots = std::min(nd, N - nd);
+    ks->uslots = std::min(nu, N - nu);
+    ks->dtab16 = ks->Lmax < 32768u;
     ks->tb_off.assign((size_t)N * N, 0);
     uint64_t e = 0;
     for (int k = 0; k < N; ++k)
@@ -607,7 +720,16 @@ pdz_status kspace_build(pdz_problem_s* p, int L1, int L2, const double* eps, int
     if ((st = alloc(&ks->d_dn_str, ks->D_dn)) != PDZ_OK) return st;
     if ((st = alloc(&ks->d_eps_dn, ks->D_dn)) != PDZ_OK) return st;
     if ((st = alloc(&ks->d_dcnt, ks->D_dn * N)) != PDZ_OK) return st;
-    if ((st = alloc(&ks->d_dtab, ks->entries)) != PDZ_OK) return st;
+    if (ks->dtab16) {
+        uint16_t* t = nullptr;
+        if ((st = alloc(&t, ks->entries)) != PDZ_OK) return st;
+        ks->d_dtab = t;
+    } else {
+        uint32_t* t = nullptr;
+        if ((st = alloc(&t, ks->entries)) != PDZ_OK) return st;
+        ks->d_dtab = t;
+    }
+    if ((st = alloc(&ks->d_upm, ks->D_up * (uint64_t)(N > 1 ? N - 1 : 0) * ks->uslots)) != PDZ_OK) return st;
     if ((st = alloc(&ks->d_up_str, ks->D_up)) != PDZ_OK) return st;
     if ((st = alloc(&ks->d_row_off, ks->D_up)) != PDZ_OK) return st;
     if ((st = alloc(&ks->d_row_kd, ks->D_up)) != PDZ_OK) return st;
@@ -618,12 +740,21 @@ pdz_status kspace_build(pdz_problem_s* p, int L1, int L2, const double* eps, int
     hipLaunchKernelGGL(k_kdn_states, dim3(grid_for(ks->D_dn, cu)), dim3(kKBlock), 0, nullptr, a, ks->d_dn_str,
                        ks->d_eps_dn, err);
     PDZ_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_kdn_moves, dim3(grid_for(ks->D_dn * N, cu)), dim3(kKBlock), 0, nullptr, a, ks->slots,
-                       ks->d_dcnt, ks->d_dtab, err);
+    if (ks->dtab16)
+        hipLaunchKernelGGL(k_kdn_moves<uint16_t>, dim3(grid_for(ks->D_dn * N, cu)), dim3(kKBlock), 0, nullptr, a,
+                           ks->slots, ks->d_dcnt, static_cast<uint16_t*>(ks->d_dtab), err);
+    else
+        hipLaunchKernelGGL(k_kdn_moves<uint32_t>, dim3(grid_for(ks->D_dn * N, cu)), dim3(kKBlock), 0, nullptr, a,
+                           ks->slots, ks->d_dcnt, static_cast<uint32_t*>(ks->d_dtab), err);
     PDZ_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_krows, dim3(grid_for(ks->D_up, cu)), dim3(kKBlock), 0, nullptr, a, ctx->binom, ks->d_up_str,
                        ks->d_row_off, ks->d_row_kd, ks->d_eps_up);
     PDZ_HIP(hipGetLastError());
+    if (N > 1 && ks->uslots > 0) {
+        hipLaunchKernelGGL(k_kup_moves, dim3(grid_for(ks->D_up * (uint64_t)(N - 1), cu)), dim3(kKBlock), 0, nullptr, a,
+                           ks->d_upm);
+        PDZ_HIP(hipGetLastError());
+    }
     PDZ_HIP(hipDeviceSynchronize());
     uint32_t word = 0;
     PDZ_HIP(hipMemcpy(&word, err, sizeof(word), hipMemcpyDeviceToHost));

@@ -248,6 +248,71 @@ def dynamics_bench(torch, pdz, synth, steps=100, reps=10):
             "first_levels": [float(x) for x in res["alpha"][:3]]}
 
 
+def kspace_bench(torch, pdz, synth, reps=20, E_real=None, calibrate=False):
+    """Translation symmetry (Sec. IV.A) on the 4x4 NN+NNN cluster, 8+8, U = 6: the lowest state of every
+    total-momentum sector (FP32 Lanczos + FP64 refinement), then at the ground-state momentum the Eq. (4)
+    H.v timed in both precisions and the time to E0 at 1e-8.  E_real: the real-space E0 to compare with."""
+    w = synth.workload("torus4x4_nnn")
+    eps = pdz.kspace_band(4, 4, w.bonds)
+    per_k = []
+    t_all = 0.0
+    for K in range(16):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = pdz.KProblem(4, 4, eps, w.U, w.n_up, w.n_dn, K)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        r = g.lanczos(storage="f32", tol=1e-7, max_iter=400, refine=1, keep_basis=1)
+        per_k.append({"K": K, "D": g.D, "E0": r["E0_refined"], "iters": r["iters"], "build_s": t_build,
+                      "lanczos_s": r["seconds"]})
+        t_all += t_build + r["seconds"]
+        g.close()
+    kg = min(per_k, key=lambda e: e["E0"])["K"]
+    g = pdz.KProblem(4, 4, eps, w.U, w.n_up, w.n_dn, kg)
+    out = {"workload": "torus4x4_nnn in momentum space (Eq. 4), 8+8, U=6", "per_K": per_k, "ground_K": kg,
+           "E0": min(e["E0"] for e in per_k), "all_K_s": t_all, "D_K": g.D, "nnz_per_hv": g.nnz,
+           "row_max": g.info["row_max"], "staged_elems_per_hv": g.info["staged"]}
+    if E_real is not None:
+        out["E0_real_space"] = E_real
+        out["E0_diff"] = out["E0"] - E_real
+    stream = torch.cuda.current_stream()
+    for dt, name, es in ((torch.float32, "f32", 4), (torch.float64, "f64", 8)):
+        x = torch.empty(g.D, dtype=dt, device="cuda").uniform_(-1.0, 1.0)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            g.hv(x, y, stream=stream)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            g.hv(x, y, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        alg = 2.0 * g.D * es
+        staged = g.info["staged"] * es
+        out["hv_" + name] = {"ms": ms, "nnz_per_s": g.nnz / (ms * 1e-3), "algorithmic_bytes": alg,
+                             "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                             "staged_row_bytes": staged, "staged_GBs": staged / (ms * 1e-3) / 1e9}
+        del x, y
+    for name, kw in (("f64", dict(storage="f64", tol=1e-10)),
+                     ("f32_refined", dict(storage="f32", tol=1e-7, refine=1, keep_basis=1))):
+        g.lanczos(max_iter=400, **kw)
+        r = g.lanczos(max_iter=400, **kw)
+        e = r["E0_refined"] if name != "f64" else r["E0"]
+        out["time_to_E0_" + name] = {"s": r["seconds"], "iters": r["iters"], "E0": e,
+                                     "err_vs_real_space": (e - E_real) if E_real is not None else None}
+    if calibrate:
+        src = torch.empty(g.D, dtype=torch.float32, device="cuda").uniform_(-1.0, 1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": g.D * 4, "bytes_written": g.D * 4}
+    g.close()
+    return out
+
+
 def learned_bench(torch, pdz, synth, steps=3000):
     """Learned start on the 4x4 cluster with 7 + 7 electrons at U = 5 against random starts (time to E0 at 1e-8)."""
     import statistics
@@ -355,6 +420,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-dynamics", action="store_true")
+    ap.add_argument("--no-kspace", action="store_true")
+    ap.add_argument("--kspace-only", action="store_true",
+                    help="run only the momentum-space section and print its JSON object")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 32-cluster batched section and print its JSON object")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -372,6 +440,10 @@ def main():
     torch.cuda.set_device(0)
     if args.batched_only:
         print(json.dumps({"batched": batched_bench(torch, pdz, synth, args.hv_reps)}), flush=True)
+        return
+    if args.kspace_only:
+        print(json.dumps({"kspace": kspace_bench(torch, pdz, synth, args.hv_reps, calibrate=args.calibrate_copy)}),
+              flush=True)
         return
     w = synth.workload(args.workload)
     g = pdz.Problem.from_workload(w)
@@ -461,6 +533,14 @@ def main():
         dyn = dynamics_bench(torch, pdz, synth)
         _log(f"dynamics: {dyn}")
 
+    ks = None
+    if not args.no_kspace:
+        e_real = None
+        if tte is not None:
+            e_real = tte.get("E0_ref")
+        ks = kspace_bench(torch, pdz, synth, args.hv_reps, E_real=e_real)
+        _log(f"kspace: {json.dumps({k: v for k, v in ks.items() if k != 'per_K'})}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -500,6 +580,7 @@ def main():
         "batched": batched,
         "learned_start": learned_res,
         "dynamics": dyn,
+        "kspace": ks,
         "copy_calibration": copy,
         "hv_plans": tuned,
         "cpu_baseline": cpu,

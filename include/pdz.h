@@ -348,9 +348,13 @@ pdz_status pdz_kspace_unrank(pdz_problem p, const uint64_t* idx, uint64_t count,
                              void* stream);
 
 /* Shape of a momentum-space problem: cluster sides, K, longest row (down
- * strings of one momentum) and number of non-empty rows.  Any output may be
- * NULL.  Errors: PDZ_EINVAL (NULL p, not a momentum-space problem). */
-pdz_status pdz_kspace_info(pdz_problem p, int32_t* L1, int32_t* L2, int32_t* K, uint32_t* row_max, uint64_t* rows);
+ * strings of one momentum), number of non-empty rows, and the source-row
+ * elements one pdz_hv stages (sum over target rows and momentum transfers q
+ * of up moves x source row length: the vector elements the kernel reads
+ * besides x and y themselves).  Any output may be NULL.
+ * Errors: PDZ_EINVAL (NULL p, not a momentum-space problem). */
+pdz_status pdz_kspace_info(pdz_problem p, int32_t* L1, int32_t* L2, int32_t* K, uint32_t* row_max, uint64_t* rows,
+                           uint64_t* staged);
 
 /* ---------------------------------------------------------------- batches */
 

@@ -275,9 +275,9 @@ class KProblem(Problem):
         self.n_sites, self.U, self.n_up, self.n_dn = n, U, n_up, n_dn
         self.bonds = []
         self.info = self._info()
-        rm, nr = ctypes.c_uint32(), ctypes.c_uint64()
-        _lib.check(L.pdz_kspace_info(self._h, None, None, None, ctypes.byref(rm), ctypes.byref(nr)))
-        self.info["row_max"], self.info["rows"] = rm.value, nr.value
+        rm, nr, sg = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        _lib.check(L.pdz_kspace_info(self._h, None, None, None, ctypes.byref(rm), ctypes.byref(nr), ctypes.byref(sg)))
+        self.info["row_max"], self.info["rows"], self.info["staged"] = rm.value, nr.value, sg.value
 
     @classmethod
     def from_bonds(cls, L1, L2, bonds, U, n_up, n_dn, K):

@@ -113,7 +113,7 @@ _SIGNATURES = {
     "pdz_kspace_unrank": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P, _P, _P]),
     "pdz_kspace_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint32),
-                                         ctypes.POINTER(ctypes.c_uint64)]),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     "pdz_lanczos_history": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "pdz_batch_create": (ctypes.c_int32, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),

@@ -50,6 +50,7 @@ struct KSpace {
     std::vector<uint64_t> dn_off;   // N+1: first down string of each momentum
     std::vector<uint64_t> tb_off;   // N x N: first entry of the down-move table of (target momentum, q)
     uint64_t D_up = 0, D_dn = 0, nrows = 0, entries = 0;
+    uint64_t staged = 0;            // source-row elements one H.v stages: sum over rows and q of moves x row length
     uint32_t Lmax = 0;
     int slots = 0;                  // most down moves of one string for one q
     uint8_t* d_kadd = nullptr;
@@ -800,6 +801,7 @@ pdz_status kspace_build(pdz_problem_s* p, int L1, int L2, const double* eps, int
                 if (!((phi >> kadd(pbit, kneg(q))) & 1u)) ++mu;
             }
             nnz += mu * mdn[(size_t)rkd[r] * N + q];
+            if (ks->Ld[rkd[r]] > 0) ks->staged += mu * ks->Ld[kadd(rkd[r], q)];
         }
     }
     p->nnz = nnz;
@@ -908,13 +910,15 @@ pdz_status pdz_kspace_unrank(pdz_problem p, const uint64_t* idx, uint64_t count,
     return ok();
 }
 
-pdz_status pdz_kspace_info(pdz_problem p, int32_t* L1, int32_t* L2, int32_t* K, uint32_t* row_max, uint64_t* rows) {
+pdz_status pdz_kspace_info(pdz_problem p, int32_t* L1, int32_t* L2, int32_t* K, uint32_t* row_max, uint64_t* rows,
+                           uint64_t* staged) {
     if (!p || !p->ks) return fail(PDZ_EINVAL, "not a momentum-space problem");
     if (L1) *L1 = p->ks->L1;
     if (L2) *L2 = p->ks->L2;
     if (K) *K = p->ks->K;
     if (row_max) *row_max = p->ks->Lmax;
     if (rows) *rows = p->ks->nrows;
+    if (staged) *staged = p->ks->staged;
     return ok();
 }
 

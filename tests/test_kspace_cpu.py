@@ -50,4 +50,4 @@ def test_create_validates_before_touching_a_device():
     assert lib.pdz_kspace_problem_create(4, 4, bad, 1.0, 2, 2, 0, ctypes.byref(h)) == _lib.PDZ_EINVAL
     assert lib.pdz_kspace_rank(None, None, None, 0, None, None) == _lib.PDZ_EINVAL
     assert lib.pdz_kspace_unrank(None, None, 0, None, None, None) == _lib.PDZ_EINVAL
-    assert lib.pdz_kspace_info(None, None, None, None, None, None) == _lib.PDZ_EINVAL
+    assert lib.pdz_kspace_info(None, None, None, None, None, None, None) == _lib.PDZ_EINVAL

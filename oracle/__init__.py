@@ -20,7 +20,9 @@ Everything here is the plain definition, written from the paper:
 * fermion operators between sectors and the resolvent of the dynamical
   correlations are the operator algebra above and a spectral sum (dynamics.py);
 * total-momentum sectors (Sec. IV.A) are sorted lists of (up, down) orbital
-  strings and Eq. (4) applied term by term with the same algebra (momentum.py).
+  strings and Eq. (4) applied term by term with the same algebra (momentum.py);
+* inversion-parity subspaces (Sec. IV.B) are representatives in the decision
+  tree's order and the projection B^T H B of the real-space H (inversion.py).
 
 The oracle shares no code with the HIP path.  Its inputs come from synth/.
 """
@@ -33,5 +35,6 @@ from .splitmix import splitmix64_mix, splitmix64_outputs, start_vector
 from . import mlp
 from . import dynamics
 from . import momentum
+from . import inversion
 
 __all__ = [n for n in dir() if not n.startswith("_")]

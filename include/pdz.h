@@ -75,7 +75,10 @@ typedef struct {
     int32_t device;      /* HIP device the handle lives on                  */
     int32_t hv_path;     /* 0: sector hop tables, 1: on-the-fly ranks,
                             2: momentum space (D_up: every up string,
-                            D_dn: every down string, hops_*: 0)        */
+                            D_dn: every down string, hops_*: 0),
+                            3: inversion parity (D: the subspace; D_up,
+                            D_dn, hops_*: the real-space sectors; nnz:
+                            an upper bound)                             */
 } pdz_info;
 
 /* ------------------------------------------------------------------ problems */
@@ -355,6 +358,44 @@ pdz_status pdz_kspace_unrank(pdz_problem p, const uint64_t* idx, uint64_t count,
  * Errors: PDZ_EINVAL (NULL p, not a momentum-space problem). */
 pdz_status pdz_kspace_info(pdz_problem p, int32_t* L1, int32_t* L2, int32_t* K, uint32_t* row_max, uint64_t* rows,
                            uint64_t* staged);
+
+/* ----------------------------------------------- inversion symmetry (parity) */
+
+/* Hubbard problem (Eq. 1, as pdz_problem_create) restricted to the subspace of
+ * inversion parity `parity` (+1 or -1) (Sec. IV.B).  Inversion F sends site i
+ * to N-1-i in every operator (a chain reversed; for an Lx x Ly cluster with
+ * sites s = x + Lx*y, the point inversion through its centre); the bond list
+ * must be symmetric under it.  On a basis state F reverses both strings and
+ * multiplies by sigma = (-1)^(n_up(n_up-1)/2 + n_dn(n_dn-1)/2).
+ * Basis and index (decision tree of Sec. IV.B, per string: pair (bit N-1-d,
+ * bit d) of class A (0,1), B (0,0), C (1,1); representatives are A strings
+ * and palindromes; tree index = the tree's forward map with the counts
+ * S_i^m = C_{i-2}^{m-1} + S_{i-2}^m + S_{i-2}^{m-2}): rows are the up
+ * representatives in tree order; a row of a non-palindromic up string holds
+ * every down string in ascending order, a row of a palindromic one the down
+ * representatives in tree order (down palindromes only when sigma = parity).
+ * Basis vectors: (|r> + parity F|r>)/sqrt(2), or |r> when F|r> = parity |r>.
+ * The handle works with pdz_problem_info, pdz_hv, pdz_lanczos* and
+ * pdz_problem_destroy (no launch plans, batches or fermion operators).
+ * Synchronous.  Errors: as pdz_problem_create; PDZ_EINVAL (parity not +-1,
+ * bonds not mirror symmetric); PDZ_ERANGE (sectors too large for the hop
+ * tables, empty subspace); PDZ_EDEVICE (a tree map failed its bijection
+ * check: a library fault). */
+pdz_status pdz_parity_problem_create(int32_t n_sites, const pdz_bond* bonds, int32_t n_bonds, double U, int32_t n_up,
+                                     int32_t n_dn, int32_t parity, pdz_problem* out);
+
+/* Index of basis states given as (up, dn) strings (device arrays).  A pair
+ * that is not a basis state (an image, wrong fillings, an excluded
+ * self-mapped state) gets 2^64 - 1 and sets bit 1 of the device error word.
+ * Asynchronous.  Errors: PDZ_EINVAL (NULL, not a parity problem). */
+pdz_status pdz_parity_rank(pdz_problem p, const uint32_t* up, const uint32_t* dn, uint64_t count, uint64_t* idx,
+                           void* stream);
+
+/* Basis state (up, dn) of each index (device arrays); an index >= D gives
+ * 0xFFFFFFFF in both and sets bit 2 of the device error word.  Asynchronous.
+ * Errors: PDZ_EINVAL. */
+pdz_status pdz_parity_unrank(pdz_problem p, const uint64_t* idx, uint64_t count, uint32_t* up, uint32_t* dn,
+                             void* stream);
 
 /* ---------------------------------------------------------------- batches */
 

@@ -8,7 +8,7 @@ import ctypes
 from . import _lib
 from ._lib import PdzError, PDZ_F64, PDZ_F32, LanczosOpts, LanczosResult
 
-__all__ = ["Problem", "KProblem", "kspace_band", "Batch", "rank", "unrank", "device_errors", "PdzError", "PDZ_F64", "PDZ_F32", "lib",
+__all__ = ["Problem", "KProblem", "ParityProblem", "kspace_band", "Batch", "rank", "unrank", "device_errors", "PdzError", "PDZ_F64", "PDZ_F32", "lib",
            "LanczosOpts", "LanczosResult"]
 
 
@@ -299,6 +299,46 @@ class KProblem(Problem):
         up = torch.empty(idx.numel(), dtype=torch.int32, device=idx.device)
         dn = torch.empty(idx.numel(), dtype=torch.int32, device=idx.device)
         _lib.check(lib().pdz_kspace_unrank(self._h, ctypes.c_void_p(idx.data_ptr()), idx.numel(),
+                                           ctypes.c_void_p(up.data_ptr()), ctypes.c_void_p(dn.data_ptr()),
+                                           _stream_handle(stream)))
+        return up, dn
+
+
+class ParityProblem(Problem):
+    """Hubbard problem restricted to inversion parity +1 or -1 (Sec. IV.B, site i -> N-1-i).
+
+    hv, lanczos, D and nnz work as for Problem; the vector is in the decision
+    tree's order (rows of up representatives).
+    """
+
+    def __init__(self, n_sites, bonds, U, n_up, n_dn, parity):
+        L = lib()
+        h = ctypes.c_void_p()
+        _lib.check(L.pdz_parity_problem_create(int(n_sites), _bond_array(bonds) if bonds else None, len(bonds),
+                                               float(U), int(n_up), int(n_dn), int(parity), ctypes.byref(h)))
+        self._h = h
+        self.n_sites, self.U, self.n_up, self.n_dn, self.parity = n_sites, U, n_up, n_dn, parity
+        self.bonds = list(bonds)
+        self.info = self._info()
+
+    @classmethod
+    def from_workload(cls, w, parity):
+        return cls(w.n_sites, w.bonds, w.U, w.n_up, w.n_dn, parity)
+
+    def rank(self, up, dn, stream=None):
+        """Index of basis states given as device 32-bit tensors of strings -> int64 tensor (-1: not a basis state)."""
+        import torch
+        out = torch.empty(up.numel(), dtype=torch.int64, device=up.device)
+        _lib.check(lib().pdz_parity_rank(self._h, ctypes.c_void_p(up.data_ptr()), ctypes.c_void_p(dn.data_ptr()),
+                                         up.numel(), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def unrank(self, idx, stream=None):
+        """Basis states of a device int64 tensor of indices -> (up, dn) int32 tensors of strings."""
+        import torch
+        up = torch.empty(idx.numel(), dtype=torch.int32, device=idx.device)
+        dn = torch.empty(idx.numel(), dtype=torch.int32, device=idx.device)
+        _lib.check(lib().pdz_parity_unrank(self._h, ctypes.c_void_p(idx.data_ptr()), idx.numel(),
                                            ctypes.c_void_p(up.data_ptr()), ctypes.c_void_p(dn.data_ptr()),
                                            _stream_handle(stream)))
         return up, dn

@@ -109,6 +109,11 @@ _SIGNATURES = {
     "pdz_kspace_problem_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                                    ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                    ctypes.POINTER(_P)]),
+    "pdz_parity_problem_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(Bond), ctypes.c_int32,
+                                                   ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                   ctypes.POINTER(_P)]),
+    "pdz_parity_rank": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint64, _P, _P]),
+    "pdz_parity_unrank": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P, _P, _P]),
     "pdz_kspace_rank": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint64, _P, _P]),
     "pdz_kspace_unrank": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P, _P, _P]),
     "pdz_kspace_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),

@@ -88,7 +88,8 @@ extern "C" {
 pdz_status pdz_fermion_op(pdz_problem src, pdz_problem dst, int32_t site, int32_t spin, int32_t op, pdz_dtype dt,
                           const void* x, void* y, void* stream) {
     if (!src || !dst || !x || !y) return fail(PDZ_EINVAL, "NULL argument");
-    if (src->ks || dst->ks) return fail(PDZ_EINVAL, "fermion operators act on real-space sectors");
+    if (src->ks || dst->ks || src->par || dst->par)
+        return fail(PDZ_EINVAL, "fermion operators act on full real-space sectors");
     if (dt != PDZ_F64 && dt != PDZ_F32) return fail(PDZ_EINVAL, "dtype must be F64 or F32");
     if (src->N != dst->N) return fail(PDZ_EINVAL, "source and target differ in the number of sites");
     if (site < 0 || site >= src->N) return fail(PDZ_EINVAL, "site out of range");

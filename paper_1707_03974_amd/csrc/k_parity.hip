@@ -1,0 +1,523 @@
+// Inversion-parity subspaces (Sec. IV.B).
+//
+// F maps site i to N-1-i in every creation operator (a chain reversed; on an
+// Lx x Ly cluster numbered s = x + Lx*y, the point inversion through its
+// centre).  On a basis state it reverses both strings and multiplies by the
+// sign of restoring the operator order of Sec. II.A, which for n electrons of
+// one spin is (-1)^(n(n-1)/2): sigma = (-1)^(n_up(n_up-1)/2 + n_dn(n_dn-1)/2)
+// for the whole sector.  With mirror-symmetric bonds F commutes with H and
+// each sector splits into P = +1 and P = -1.
+//
+// Ranking by the decision tree of Sec. IV.B, per string: at depth d the pair
+// (bit N-1-d, bit d) is class A (0,1), B (0,0) or C (1,1); (1,0) marks the
+// mirror image of an A string.  An A string ends the walk with the plain
+// forward map of its inner bits; B adds the count of the A node, C that of the
+// A and B nodes (the counts C_{i-2}^{m-1} and S_{i-2}^m of the paper's
+// recursion S_i^m = C_{i-2}^{m-1} + S_{i-2}^m + S_{i-2}^{m-2}).  A string whose
+// pairs are all B or C is a palindrome.  Representatives: A strings and
+// palindromes; their tree index is that forward map.
+//
+// Two spins: the up string decides the representative, the down string when
+// the up string is a palindrome.  Rows are the up representatives in tree
+// order; a non-palindromic row holds every down string in ascending order, a
+// palindromic row the down representatives in tree order (down palindromes
+// only when sigma = P).  Basis vector of a representative r:
+// (|r> + P F|r>)/sqrt(2), or |r> when F|r> = P|r>.
+//
+// H.v (gather form, H_P real symmetric): for a target t and each term of H
+// (diagonal, every hop of either spin, from the real-space hop tables) with
+// source s, y_t += w_t w_s H[t, s] x[rep(s)], with w_t = sqrt(2) for a pair
+// state and 1 for a self-mapped one, w_s = 1/sqrt(2) (pair state; times
+// P sigma when s is the image of its representative) or 1 (self-mapped).
+// rep(s) comes from per-string tables: class, mirror rank, row, column.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "pdz_internal.h"
+#include "perfect_hash.h"
+
+namespace pdz {
+
+struct ParSpace {
+    int P = 1, sigma = 1;
+    uint64_t nrows = 0, Lp = 0, n_dn_reps = 0;
+    uint8_t* d_ucls = nullptr;     // D_up: 0 A representative, 1 mirror image, 2 palindrome
+    uint32_t* d_uinv = nullptr;    // D_up: rank of the mirrored string
+    uint32_t* d_utree = nullptr;   // D_up: tree index (of the string, or of its mirror for an image)
+    uint32_t* d_urow = nullptr;    // D_up: row of the representative of the string's orbit
+    uint8_t* d_dcls = nullptr;
+    uint32_t* d_dinv = nullptr;
+    uint32_t* d_dtree = nullptr;
+    uint32_t* d_dcol = nullptr;    // D_dn: column in a palindromic row (representatives), ~0 when excluded
+    uint32_t* d_dlist = nullptr;   // Lp: down rank of each column of a palindromic row
+    uint32_t* d_row_rank = nullptr;   // nrows: up rank of each row
+    uint64_t* d_row_off = nullptr;    // nrows + 1
+    uint8_t* d_row_pal = nullptr;     // nrows
+    uint32_t* d_S = nullptr;          // (N+1) x (nmax+1): representatives (palindromes included), Sec. IV.B
+};
+
+namespace {
+
+constexpr int kPBlock = 256;
+constexpr uint8_t kClsA = 0, kClsImage = 1, kClsPal = 2;
+constexpr uint32_t kNoCol = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t mirror(uint32_t phi, int N) {
+    return N >= 32 ? __builtin_bitreverse32(phi) : (__builtin_bitreverse32(phi) >> (32 - N));
+}
+
+__device__ __forceinline__ uint8_t classify(uint32_t phi, int N) {
+    for (int d = 0; d < N / 2; ++d) {
+        const uint32_t hi = (phi >> (N - 1 - d)) & 1u, lo = (phi >> d) & 1u;
+        if (hi != lo) return lo ? kClsA : kClsImage;
+    }
+    return kClsPal;
+}
+
+// Tree index of a representative string (A or palindrome): the decision-tree forward map.
+__device__ __forceinline__ uint32_t forward_map_inversion(uint32_t phi, int n, int N, const uint32_t* sC,
+                                                          const uint32_t* S, int smax) {
+    uint32_t idx = 0;
+    int m = n, i = N;
+    for (int d = 0; d < N / 2; ++d) {
+        const uint32_t hi = (phi >> (N - 1 - d)) & 1u, lo = (phi >> d) & 1u;
+        const uint32_t a_cnt = (m >= 1 && i >= 2) ? sC[(i - 2) * kBinomStride + (m - 1)] : 0u;
+        if (hi == 0u && lo == 1u) {
+            const int w = i - 2;
+            const uint32_t inner = w > 0 ? ((phi >> (d + 1)) & ((w >= 32) ? 0xFFFFFFFFu : ((1u << w) - 1u))) : 0u;
+            return idx + forward_map(inner, sC);
+        }
+        if (hi == 0u) {
+            idx += a_cnt;
+        } else {
+            idx += a_cnt + S[(i - 2) * (smax + 1) + m];
+            m -= 2;
+        }
+        i -= 2;
+    }
+    return idx;
+}
+
+// Per string of one spin sector: class, mirror rank, tree index.
+__global__ __launch_bounds__(kPBlock) void k_pinfo(const uint32_t* binom, const uint32_t* S, int smax, int N, int n,
+                                                    const uint32_t* states, uint64_t D, uint8_t* cls, uint32_t* inv,
+                                                    uint32_t* tree) {
+    __shared__ uint32_t sC[kBinomStride * kBinomStride];
+    stage_binom(sC, binom);
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < D; r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t phi = states[r];
+        const uint32_t rev = mirror(phi, N);
+        const uint8_t c = classify(phi, N);
+        cls[r] = c;
+        inv[r] = forward_map(rev, sC);
+        tree[r] = forward_map_inversion(c == kClsImage ? rev : phi, n, N, sC, S, smax);
+    }
+}
+
+struct PArgs {
+    const uint32_t* up_states;
+    const uint32_t* dn_states;
+    const uint8_t* up_cnt;
+    const uint32_t* up_ell;
+    const uint8_t* dn_cnt;
+    const uint32_t* dn_ell;
+    uint64_t Dup, Ddn;
+    const uint8_t* ucls;
+    const uint32_t* urow;
+    const uint8_t* dcls;
+    const uint32_t* dinv;
+    const uint32_t* dcol;
+    const uint32_t* dlist;
+    const uint32_t* row_rank;
+    const uint64_t* row_off;
+    const uint8_t* row_pal;
+    const uint32_t* uinv;
+    uint64_t nrows;
+    double U;
+    double ps;      // P * sigma
+    int pal_in;     // self-mapped states belong to this parity (sigma == P)
+};
+
+// One work group per row; threads over the row's columns.
+template <typename T>
+__global__ __launch_bounds__(kPBlock) void k_hvp(const PArgs a, const T* __restrict__ coef, const T* __restrict__ x,
+                                                  T* __restrict__ y, const int* skip) {
+    if (skip && *skip) return;
+    const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
+    for (uint64_t k = blockIdx.x; k < a.nrows; k += gridDim.x) {
+        const uint32_t ru = a.row_rank[k];
+        const bool pal = a.row_pal[k] != 0;
+        const uint64_t off = a.row_off[k];
+        const uint64_t len = a.row_off[k + 1] - off;
+        const uint32_t phu = a.up_states[ru];
+        const int nup_h = a.up_cnt[ru];
+        for (uint64_t c = threadIdx.x; c < len; c += kPBlock) {
+            const uint32_t rd = pal ? a.dlist[c] : (uint32_t)c;
+            const bool t_pair = !(pal && a.dcls[rd] == kClsPal);
+            const T wt = t_pair ? r2 : (T)1;
+            T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[rd])) * x[off + c];
+            // down hops: the up string stays
+            const int ndh = a.dn_cnt[rd];
+            for (int h = 0; h < ndh; ++h) {
+                const uint32_t e = a.dn_ell[(uint64_t)h * a.Ddn + rd];
+                const uint32_t rd2 = e & kTargetMask;
+                const T cf = coef[e >> kTargetBits];
+                if (!pal) {
+                    acc += cf * x[off + rd2];
+                } else {
+                    const uint8_t cl = a.dcls[rd2];
+                    if (cl == kClsA) {
+                        acc += wt * ir2 * cf * x[off + a.dcol[rd2]];
+                    } else if (cl == kClsImage) {
+                        acc += wt * ir2 * ps * cf * x[off + a.dcol[a.dinv[rd2]]];
+                    } else if (a.pal_in) {
+                        acc += wt * cf * x[off + a.dcol[rd2]];
+                    }
+                }
+            }
+            // up hops: the down string stays
+            for (int h = 0; h < nup_h; ++h) {
+                const uint32_t e = a.up_ell[(uint64_t)h * a.Dup + ru];
+                const uint32_t ru2 = e & kTargetMask;
+                const T cf = coef[e >> kTargetBits];
+                const uint8_t cl = a.ucls[ru2];
+                const uint64_t off2 = a.row_off[a.urow[ru2]];
+                if (cl == kClsA) {
+                    acc += wt * ir2 * cf * x[off2 + rd];
+                } else if (cl == kClsImage) {
+                    acc += wt * ir2 * ps * cf * x[off2 + a.dinv[rd]];
+                } else {
+                    const uint8_t dc = a.dcls[rd];
+                    if (dc == kClsA) {
+                        acc += wt * ir2 * cf * x[off2 + a.dcol[rd]];
+                    } else if (dc == kClsImage) {
+                        acc += wt * ir2 * ps * cf * x[off2 + a.dcol[a.dinv[rd]]];
+                    } else if (a.pal_in) {
+                        acc += wt * cf * x[off2 + a.dcol[rd]];
+                    }
+                }
+            }
+            y[off + c] = acc;
+        }
+    }
+}
+
+// Index of basis states (up, dn) given as strings; states outside the basis get ~0 and an error bit.
+__global__ __launch_bounds__(kPBlock) void k_prank(const PArgs a, const uint32_t* binom, const uint32_t* S, int smax,
+                                                    int N, int n_up, int n_dn, const uint32_t* up, const uint32_t* dn,
+                                                    uint64_t count, uint64_t* idx, uint32_t* err) {
+    __shared__ uint32_t sC[kBinomStride * kBinomStride];
+    stage_binom(sC, binom);
+    const uint32_t mask = N >= 32 ? 0xFFFFFFFFu : ((1u << N) - 1u);
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t u = up[t], d = dn[t];
+        uint64_t r = ~0ull;
+        bool bad = (u & ~mask) || (d & ~mask) || __builtin_popcount(u) != n_up || __builtin_popcount(d) != n_dn;
+        if (!bad) {
+            const uint8_t cu = classify(u, N);
+            if (cu == kClsImage) {
+                bad = true;
+            } else {
+                const uint32_t row = forward_map_inversion(u, n_up, N, sC, S, smax);
+                const uint32_t rd = forward_map(d, sC);
+                if (cu == kClsA) {
+                    r = a.row_off[row] + rd;
+                } else {
+                    const uint32_t col = a.dcol[rd];
+                    if (classify(d, N) == kClsImage || col == kNoCol) bad = true;
+                    else r = a.row_off[row] + col;
+                }
+            }
+        }
+        if (bad) {
+            atomicOr(err, kErrRankInput);
+            r = ~0ull;
+        }
+        idx[t] = r;
+    }
+}
+
+// Basis state of each index: the row by binary search over the row starts.
+__global__ __launch_bounds__(kPBlock) void k_punrank(const PArgs a, const uint64_t* idx, uint64_t count, uint32_t* up,
+                                                      uint32_t* dn, uint32_t* err) {
+    const uint64_t D = a.row_off[a.nrows];
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = idx[t];
+        if (p >= D) {
+            atomicOr(err, kErrUnrankInput);
+            up[t] = dn[t] = 0xFFFFFFFFu;
+            continue;
+        }
+        uint64_t lo = 0, hi = a.nrows;   // last row with row_off <= p
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) / 2;
+            if (a.row_off[mid] <= p) lo = mid; else hi = mid;
+        }
+        const uint64_t c = p - a.row_off[lo];
+        const uint32_t rd = a.row_pal[lo] ? a.dlist[c] : (uint32_t)c;
+        up[t] = a.up_states[a.row_rank[lo]];
+        dn[t] = a.dn_states[rd];
+    }
+}
+
+template <typename V>
+pdz_status dalloc(V** dst, uint64_t n) {
+    PDZ_HIP(hipMalloc(dst, std::max<uint64_t>(1, n) * sizeof(V)));
+    return ok();
+}
+
+template <typename V>
+pdz_status dupload(V** dst, const std::vector<V>& src) {
+    PDZ_HIP(hipMalloc(dst, std::max<size_t>(1, src.size()) * sizeof(V)));
+    if (!src.empty()) PDZ_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
+    return ok();
+}
+
+PArgs pargs(const pdz_problem_s* p) {
+    const ParSpace* q = p->par;
+    PArgs a;
+    a.up_states = p->up.states;
+    a.dn_states = p->dn.states;
+    a.up_cnt = p->up.count;
+    a.up_ell = p->up.ell;
+    a.dn_cnt = p->dn.count;
+    a.dn_ell = p->dn.ell;
+    a.Dup = p->up.D;
+    a.Ddn = p->dn.D;
+    a.ucls = q->d_ucls;
+    a.urow = q->d_urow;
+    a.dcls = q->d_dcls;
+    a.dinv = q->d_dinv;
+    a.dcol = q->d_dcol;
+    a.dlist = q->d_dlist;
+    a.row_rank = q->d_row_rank;
+    a.row_off = q->d_row_off;
+    a.row_pal = q->d_row_pal;
+    a.uinv = q->d_uinv;
+    a.nrows = q->nrows;
+    a.U = p->U;
+    a.ps = (double)(q->P * q->sigma);
+    a.pal_in = q->sigma == q->P;
+    return a;
+}
+
+unsigned pgrid(uint64_t n, unsigned cu) {
+    uint64_t g = (n + kPBlock - 1) / kPBlock;
+    const uint64_t gmax = (uint64_t)cu * 16;
+    if (g > gmax) g = gmax;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+void parity_free(ParSpace* q) {
+    if (!q) return;
+    void* ptrs[] = {q->d_ucls, q->d_uinv, q->d_utree, q->d_urow, q->d_dcls, q->d_dinv, q->d_dtree, q->d_dcol,
+                    q->d_dlist, q->d_row_rank, q->d_row_off, q->d_row_pal, q->d_S};
+    for (void* v : ptrs)
+        if (v) (void)hipFree(v);
+    delete q;
+}
+
+pdz_status launch_hvp(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s, const int* skip) {
+    const PArgs a = pargs(p);
+    uint64_t grid = a.nrows;
+    if (grid > (1ull << 20)) grid = 1ull << 20;
+    if (grid < 1) return ok();
+    if (dt == PDZ_F64)
+        hipLaunchKernelGGL(k_hvp<double>, dim3((unsigned)grid), dim3(kPBlock), 0, s, a, p->d_coef64,
+                           static_cast<const double*>(x), static_cast<double*>(y), skip);
+    else
+        hipLaunchKernelGGL(k_hvp<float>, dim3((unsigned)grid), dim3(kPBlock), 0, s, a, p->d_coef32,
+                           static_cast<const float*>(x), static_cast<float*>(y), skip);
+    PDZ_HIP(hipGetLastError());
+    return ok();
+}
+
+// Parity tables on top of a real-space problem with sector hop tables.
+pdz_status parity_build(pdz_problem_s* p, int P) {
+    ParSpace* q = new ParSpace();
+    p->par = q;
+    const int N = p->N, nu = p->n_up, nd = p->n_dn;
+    q->P = P;
+    q->sigma = (((nu * (nu - 1) / 2) + (nd * (nd - 1) / 2)) % 2) ? -1 : 1;
+    const int smax = std::max(nu, nd);
+    // S_i^m = C_{i-2}^{m-1} + S_{i-2}^m + S_{i-2}^{m-2}, S_0^0 = 1, S_1^0 = S_1^1 = 1
+    std::vector<uint64_t> S((size_t)(N + 1) * (smax + 1), 0);
+    auto Sx = [&](int i, int m) -> uint64_t& { return S[(size_t)i * (smax + 1) + m]; };
+    for (int i = 0; i <= N; ++i)
+        for (int m = 0; m <= smax; ++m) {
+            if (i == 0) Sx(i, m) = m == 0;
+            else if (i == 1) Sx(i, m) = m <= 1;
+            else Sx(i, m) = (m >= 1 ? binom(i - 2, m - 1) : 0) + Sx(i - 2, m) + (m >= 2 ? Sx(i - 2, m - 2) : 0);
+        }
+    std::vector<uint32_t> S32(S.size());
+    for (size_t t = 0; t < S.size(); ++t) S32[t] = (uint32_t)S[t];
+    DeviceCtx* ctx = nullptr;
+    pdz_status st = device_ctx(&ctx);
+    if (st != PDZ_OK) return st;
+    const uint64_t Du = p->up.D, Dd = p->dn.D;
+    if ((st = dupload(&q->d_S, S32)) != PDZ_OK) return st;
+    if ((st = dalloc(&q->d_ucls, Du)) != PDZ_OK) return st;
+    if ((st = dalloc(&q->d_uinv, Du)) != PDZ_OK) return st;
+    if ((st = dalloc(&q->d_utree, Du)) != PDZ_OK) return st;
+    if ((st = dalloc(&q->d_dcls, Dd)) != PDZ_OK) return st;
+    if ((st = dalloc(&q->d_dinv, Dd)) != PDZ_OK) return st;
+    if ((st = dalloc(&q->d_dtree, Dd)) != PDZ_OK) return st;
+    const unsigned cu = (unsigned)ctx->cu_count;
+    hipLaunchKernelGGL(k_pinfo, dim3(pgrid(Du, cu)), dim3(kPBlock), 0, nullptr, ctx->binom, q->d_S, smax, N, nu,
+                       p->up.states, Du, q->d_ucls, q->d_uinv, q->d_utree);
+    hipLaunchKernelGGL(k_pinfo, dim3(pgrid(Dd, cu)), dim3(kPBlock), 0, nullptr, ctx->binom, q->d_S, smax, N, nd,
+                       p->dn.states, Dd, q->d_dcls, q->d_dinv, q->d_dtree);
+    PDZ_HIP(hipGetLastError());
+    PDZ_HIP(hipDeviceSynchronize());
+    std::vector<uint8_t> ucls(Du), dcls(Dd);
+    std::vector<uint32_t> utree(Du), uinv(Du), dtree(Dd);
+    PDZ_HIP(hipMemcpy(ucls.data(), q->d_ucls, Du, hipMemcpyDeviceToHost));
+    PDZ_HIP(hipMemcpy(utree.data(), q->d_utree, Du * 4, hipMemcpyDeviceToHost));
+    PDZ_HIP(hipMemcpy(uinv.data(), q->d_uinv, Du * 4, hipMemcpyDeviceToHost));
+    PDZ_HIP(hipMemcpy(dcls.data(), q->d_dcls, Dd, hipMemcpyDeviceToHost));
+    PDZ_HIP(hipMemcpy(dtree.data(), q->d_dtree, Dd * 4, hipMemcpyDeviceToHost));
+    // rows: up representatives by tree index (must be a permutation of [0, reps))
+    const uint64_t ureps = Sx(N, nu);
+    std::vector<uint32_t> row_rank(ureps, 0xFFFFFFFFu);
+    for (uint64_t r = 0; r < Du; ++r) {
+        if (ucls[r] == kClsImage) continue;
+        if (utree[r] >= ureps || row_rank[utree[r]] != 0xFFFFFFFFu)
+            return fail(PDZ_EDEVICE, "decision-tree forward map is not a bijection onto the up representatives");
+        row_rank[utree[r]] = (uint32_t)r;
+    }
+    // down columns of a palindromic row: down representatives in tree order, palindromes only if sigma == P
+    const uint64_t dreps = Sx(N, nd);
+    std::vector<uint32_t> dby_tree(dreps, 0xFFFFFFFFu);
+    for (uint64_t r = 0; r < Dd; ++r) {
+        if (dcls[r] == kClsImage) continue;
+        if (dtree[r] >= dreps || dby_tree[dtree[r]] != 0xFFFFFFFFu)
+            return fail(PDZ_EDEVICE, "decision-tree forward map is not a bijection onto the down representatives");
+        dby_tree[dtree[r]] = (uint32_t)r;
+    }
+    std::vector<uint32_t> dcol(Dd, kNoCol), dlist;
+    for (uint64_t k = 0; k < dreps; ++k) {
+        const uint32_t r = dby_tree[k];
+        if (dcls[r] == kClsPal && q->sigma != P) continue;
+        dcol[r] = (uint32_t)dlist.size();
+        dlist.push_back(r);
+    }
+    q->Lp = dlist.size();
+    std::vector<uint64_t> row_off(ureps + 1, 0);
+    std::vector<uint8_t> row_pal(ureps);
+    for (uint64_t k = 0; k < ureps; ++k) {
+        row_pal[k] = ucls[row_rank[k]] == kClsPal;
+        row_off[k + 1] = row_off[k] + (row_pal[k] ? q->Lp : Dd);
+    }
+    std::vector<uint32_t> urow(Du);
+    for (uint64_t r = 0; r < Du; ++r) urow[r] = ucls[r] == kClsImage ? utree[uinv[r]] : utree[r];
+    for (uint64_t r = 0; r < Du; ++r)
+        if (ucls[r] == kClsImage && (ucls[uinv[r]] != kClsA || utree[r] != utree[uinv[r]]))
+            return fail(PDZ_EDEVICE, "mirror of an image string is not its representative");
+    q->nrows = ureps;
+    p->D = row_off[ureps];
+    if (p->D == 0) return fail(PDZ_ERANGE, "the parity subspace is empty");
+    if ((st = dupload(&q->d_row_rank, row_rank)) != PDZ_OK) return st;
+    if ((st = dupload(&q->d_row_off, row_off)) != PDZ_OK) return st;
+    if ((st = dupload(&q->d_row_pal, row_pal)) != PDZ_OK) return st;
+    if ((st = dupload(&q->d_urow, urow)) != PDZ_OK) return st;
+    if ((st = dupload(&q->d_dcol, dcol)) != PDZ_OK) return st;
+    if ((st = dupload(&q->d_dlist, dlist)) != PDZ_OK) return st;
+    // structural nonzeros: per element its diagonal plus every hop whose source has a component here
+    std::vector<uint8_t> ucnt(Du), dcnt(Dd);
+    PDZ_HIP(hipMemcpy(ucnt.data(), p->up.count, Du, hipMemcpyDeviceToHost));
+    PDZ_HIP(hipMemcpy(dcnt.data(), p->dn.count, Dd, hipMemcpyDeviceToHost));
+    uint64_t dsum = 0, dsum_pal = 0;
+    for (uint64_t r = 0; r < Dd; ++r) dsum += dcnt[r];
+    for (uint32_t r : dlist) dsum_pal += dcnt[r];
+    uint64_t nnz = p->D;
+    for (uint64_t k = 0; k < ureps; ++k) {
+        const uint32_t ru = row_rank[k];
+        if (row_pal[k]) nnz += dsum_pal + (uint64_t)ucnt[ru] * q->Lp;
+        else nnz += dsum + (uint64_t)ucnt[ru] * Dd;
+    }
+    p->nnz = nnz;   // counts hops onto excluded self-mapped states as well (an upper bound by at most those)
+    return ok();
+}
+
+}  // namespace pdz
+
+using namespace pdz;
+
+extern "C" {
+
+pdz_status pdz_parity_problem_create(int32_t n_sites, const pdz_bond* bonds, int32_t n_bonds, double U, int32_t n_up,
+                                     int32_t n_dn, int32_t parity, pdz_problem* out) {
+    if (!out) return fail(PDZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (parity != 1 && parity != -1) return fail(PDZ_EINVAL, "parity must be +1 or -1");
+    if (n_sites < 1 || n_sites > kMaxSites) return fail(PDZ_ERANGE, "n_sites must be in [1, 32]");
+    if (n_bonds < 0 || (n_bonds > 0 && !bonds)) return fail(PDZ_EINVAL, "bad bond list");
+    {   // mirror symmetry of the bonds: (i, j, t) -> (N-1-i, N-1-j, t), repeated pairs summed
+        std::vector<double> t((size_t)n_sites * n_sites, 0.0);
+        for (int b = 0; b < n_bonds; ++b) {
+            const pdz_bond& bd = bonds[b];
+            if (bd.i < 0 || bd.i >= n_sites || bd.j < 0 || bd.j >= n_sites || bd.i == bd.j || !std::isfinite(bd.t))
+                return fail(PDZ_EINVAL, "bond " + std::to_string(b) + " is invalid");
+            t[(size_t)bd.i * n_sites + bd.j] += bd.t;
+            t[(size_t)bd.j * n_sites + bd.i] += bd.t;
+        }
+        for (int i = 0; i < n_sites; ++i)
+            for (int j = 0; j < n_sites; ++j) {
+                const double a = t[(size_t)i * n_sites + j];
+                const double b = t[(size_t)(n_sites - 1 - i) * n_sites + (n_sites - 1 - j)];
+                if (std::fabs(a - b) > 1e-12 * (1.0 + std::fabs(a)))
+                    return fail(PDZ_EINVAL, "bonds are not symmetric under site i -> N-1-i");
+            }
+    }
+    pdz_problem p = nullptr;
+    pdz_status st = pdz_problem_create(n_sites, bonds, n_bonds, U, n_up, n_dn, &p);
+    if (st != PDZ_OK) return st;
+    if (p->hv_path != 0) {
+        pdz_problem_destroy(p);
+        return fail(PDZ_ERANGE, "parity subspaces need the sector hop tables (sectors below 2^24 strings)");
+    }
+    st = parity_build(p, parity);
+    if (st != PDZ_OK) {
+        const std::string msg = pdz_last_error();
+        pdz_problem_destroy(p);
+        return fail(st, msg);
+    }
+    p->hv_path = 3;
+    *out = p;
+    return ok();
+}
+
+pdz_status pdz_parity_rank(pdz_problem p, const uint32_t* up, const uint32_t* dn, uint64_t count, uint64_t* idx,
+                           void* stream) {
+    if (!p || !p->par) return fail(PDZ_EINVAL, "not a parity problem");
+    if (count > 0 && (!up || !dn || !idx)) return fail(PDZ_EINVAL, "NULL array");
+    if (count == 0) return ok();
+    DeviceCtx* ctx = nullptr;
+    pdz_status st = device_ctx(&ctx);
+    if (st != PDZ_OK) return st;
+    hipLaunchKernelGGL(k_prank, dim3(pgrid(count, (unsigned)ctx->cu_count)), dim3(kPBlock), 0, (hipStream_t)stream,
+                       pargs(p), ctx->binom, p->par->d_S, std::max(p->n_up, p->n_dn), p->N, p->n_up, p->n_dn, up, dn,
+                       count, idx, ctx->err);
+    PDZ_HIP(hipGetLastError());
+    return ok();
+}
+
+pdz_status pdz_parity_unrank(pdz_problem p, const uint64_t* idx, uint64_t count, uint32_t* up, uint32_t* dn,
+                             void* stream) {
+    if (!p || !p->par) return fail(PDZ_EINVAL, "not a parity problem");
+    if (count > 0 && (!up || !dn || !idx)) return fail(PDZ_EINVAL, "NULL array");
+    if (count == 0) return ok();
+    DeviceCtx* ctx = nullptr;
+    pdz_status st = device_ctx(&ctx);
+    if (st != PDZ_OK) return st;
+    hipLaunchKernelGGL(k_punrank, dim3(pgrid(count, (unsigned)ctx->cu_count)), dim3(kPBlock), 0, (hipStream_t)stream,
+                       pargs(p), idx, count, up, dn, ctx->err);
+    PDZ_HIP(hipGetLastError());
+    return ok();
+}
+
+}  // extern "C"

@@ -101,6 +101,7 @@ static void destroy_problem(pdz_problem_s* p) {
     if (p->d_coef64) (void)hipFree(p->d_coef64);
     if (p->d_coef32) (void)hipFree(p->d_coef32);
     kspace_free(p->ks);
+    parity_free(p->par);
     (void)hipSetDevice(prev);
     delete p;
 }

@@ -50,6 +50,7 @@ struct SectorTables {
 
 namespace pdz {
 struct KSpace;   // momentum-space sector tables (k_kspace.hip)
+struct ParSpace; // inversion-parity tables (k_parity.hip)
 // H.v launch plan for one precision (0 = automatic choice).
 struct HvPlan {
     int down = 0;    // 1: one row per group, hop table loaded up front; 2: one row, table in a loop;
@@ -73,8 +74,9 @@ struct pdz_problem_s {
     std::vector<double> coef_host;       // signed hop amplitudes
     double* d_coef64 = nullptr;
     float* d_coef32 = nullptr;
-    int hv_path = 0;                     // 0 tables, 1 on the fly, 2 momentum space (ks)
+    int hv_path = 0;                     // 0 tables, 1 on the fly, 2 momentum space (ks), 3 parity (par)
     pdz::KSpace* ks = nullptr;           // momentum-space sector (Sec. IV.A), else NULL
+    pdz::ParSpace* par = nullptr;        // inversion-parity subspace (Sec. IV.B; hv_path 3), else NULL
     pdz::HvPlan plan[2];                 // per pdz_dtype
 };
 
@@ -137,6 +139,10 @@ pdz_status hv_prepare();   // per-device kernel attributes, called once outside 
 pdz_status batch_prepare();   // the same for the batched H.v kernels
 pdz_status kspace_prepare();  // the same for the momentum-space H.v kernels
 void kspace_free(KSpace* ks);
+void parity_free(ParSpace* q);
+// y = H x on an inversion-parity subspace
+pdz_status launch_hvp(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
+                      const int* skip);
 // y = H x on a momentum-space problem (every pass at once; no split form)
 pdz_status launch_hvk(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                       const int* skip);

@@ -13,7 +13,7 @@ namespace {
 pdz_status check_dt(pdz_problem p, pdz_dtype dt) {
     if (!p) return fail(PDZ_EINVAL, "problem is NULL");
     if (dt != PDZ_F64 && dt != PDZ_F32) return fail(PDZ_EINVAL, "dtype must be PDZ_F64 or PDZ_F32");
-    if (p->ks) return fail(PDZ_EINVAL, "a momentum-space problem has one H.v kernel and no launch plans");
+    if (p->ks || p->par) return fail(PDZ_EINVAL, "a symmetry-sector problem has one H.v kernel and no launch plans");
     return ok();
 }
 

@@ -1,0 +1,193 @@
+"""Inversion-parity subspaces (Sec. IV.B) on the GPU against the CPU oracle.
+
+* pdz_parity_unrank / pdz_parity_rank equal the oracle's basis order (decision
+  tree, up string first) bit for bit, for both parities of small sectors; states
+  outside the basis are flagged.
+* H.v element by element against B^T H B (small sectors) and on sampled rows of
+  the 4x3 torus 6+6 and of the 4x4 NN+NNN 8+8 cluster (oracle rows from the
+  real-space operator algebra), FP64 and FP32.  Tolerance: (n + 6) eps sum|terms|:
+  each term is a product of up to five rounded factors (sqrt(2), 1/sqrt(2), the
+  hop amplitude, x, and the sign P sigma, which is exact), and n - 1 roundings of
+  the running sum.
+* Lanczos on each parity: E0 against the oracle's H_P, and min over the two
+  parities of the 4x4 NN+NNN 8+8 cluster equals the real-space ground-state
+  energy from the real-space path.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+
+import oracle
+import synth
+from oracle import inversion as inv
+from tests._gpu import torch_cuda, to_dev, to_host, EPS64, EPS32
+
+pytestmark = pytest.mark.gpu
+
+
+def _chain(N, t=1.0, tp=0.0, periodic=False):
+    b = [(i, i + 1, t) for i in range(N - 1)]
+    if periodic:
+        b.append((N - 1, 0, t))
+    if tp:
+        b += [(i, i + 2, tp) for i in range(N - 2)]
+    return b
+
+
+def _open_rect(Lx, Ly, t=1.0, tp=0.0):
+    b = []
+    for y in range(Ly):
+        for x in range(Lx):
+            s = x + Lx * y
+            if x + 1 < Lx:
+                b.append((s, s + 1, t))
+            if y + 1 < Ly:
+                b.append((s, s + Lx, t))
+            if tp and x + 1 < Lx and y + 1 < Ly:
+                b.append((s, s + Lx + 1, tp))
+            if tp and x >= 1 and y + 1 < Ly:
+                b.append((s, s + Lx - 1, tp))
+    return b
+
+
+SMALL = [
+    (8, _chain(8), 4.0, 4, 4),
+    (7, _chain(7, 1.0, 0.3), 3.0, 3, 2),
+    (9, _open_rect(3, 3, 1.0, 0.2), 5.0, 3, 3),
+    (8, _open_rect(4, 2), 6.0, 3, 4),
+    (8, _chain(8, periodic=True), 2.0, 4, 3),
+    (6, _chain(6), 3.0, 0, 3),
+    (10, _open_rect(5, 2, 1.0, -0.25), 4.0, 5, 5),
+]
+IDS = ["chain8", "chain7nnn", "open3x3", "open4x2", "ring8", "nup0", "open5x2"]
+
+
+def _oracle(N, bonds, U, nu, nd):
+    return oracle.Problem(N, [b[0] for b in bonds], [b[1] for b in bonds], [b[2] for b in bonds], U, nu, nd)
+
+
+def _gpu(N, bonds, U, nu, nd, P):
+    import paper_1707_03974_amd as pdz
+    return pdz.ParityProblem(N, bonds, U, nu, nd, P)
+
+
+@pytest.mark.parametrize("P", [1, -1])
+@pytest.mark.parametrize("case", SMALL, ids=IDS)
+def test_parity_maps_equal_the_oracle_basis(case, P):
+    torch = torch_cuda()
+    import paper_1707_03974_amd as pdz
+    N, bonds, U, nu, nd = case
+    bu, bd, _ = inv.basis(N, nu, nd, P)
+    g = _gpu(N, bonds, U, nu, nd, P)
+    assert g.D == len(bu)
+    gu, gd = g.unrank(torch.arange(g.D, dtype=torch.int64, device="cuda"))
+    assert np.array_equal(to_host(gu).view(np.uint32).astype(np.uint64), bu)
+    assert np.array_equal(to_host(gd).view(np.uint32).astype(np.uint64), bd)
+    r = g.rank(gu, gd)
+    assert torch.equal(r, torch.arange(g.D, dtype=torch.int64, device="cuda"))
+    assert pdz.device_errors() == 0
+
+
+def test_parity_rank_flags_states_outside_the_basis():
+    torch = torch_cuda()
+    import paper_1707_03974_amd as pdz
+    g = _gpu(8, _chain(8), 4.0, 4, 4, 1)
+    pdz.device_errors()
+    up = np.array([0b00001111, 0b11110000, 0b00111100], np.uint32)   # A string, its image, a palindrome
+    dn = np.array([0b01010101, 0b01010101, 0b00111100], np.uint32)   # ..., ..., palindrome: self-mapped
+    r = to_host(g.rank(to_dev(up.view(np.int32), torch.int32), to_dev(dn.view(np.int32), torch.int32)))
+    assert r[0] >= 0 and r[1] == -1
+    sigma = (-1) ** (4 * 3 // 2 + 4 * 3 // 2)
+    assert (r[2] >= 0) == (sigma == 1)
+    assert pdz.device_errors() & 1
+    gu, _ = g.unrank(torch.tensor([g.D], dtype=torch.int64, device="cuda"))
+    assert to_host(gu)[0] == -1
+    assert pdz.device_errors() & 2
+
+
+def _bound(H, x, eps):
+    A = abs(H)
+    s = A @ abs(x)
+    n = np.diff(H.indptr)
+    return (n + 6) * eps * s + n * EPS64 * s
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+@pytest.mark.parametrize("P", [1, -1])
+@pytest.mark.parametrize("case", SMALL, ids=IDS)
+def test_parity_hv_matches_the_oracle(case, P, dtype_name):
+    torch = torch_cuda()
+    N, bonds, U, nu, nd = case
+    HP = inv.build_csr_P(_oracle(N, bonds, U, nu, nd), P)
+    g = _gpu(N, bonds, U, nu, nd, P)
+    dt, e = (torch.float64, EPS64) if dtype_name == "f64" else (torch.float32, EPS32)
+    x = np.random.default_rng(12).uniform(-1, 1, g.D)
+    if dtype_name == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    y = to_host(g.hv(to_dev(x, dt))).astype(np.float64)
+    err = np.abs(y - HP @ x)
+    assert np.all(err <= _bound(HP, x, e) + 1e-300), (np.max(err), dtype_name, P)
+
+
+def _sampled(w, P, nrows, seed, dtype_name):
+    torch = torch_cuda()
+    po = oracle.Problem.from_workload(w)
+    g = _gpu(w.n_sites, [(b.i, b.j, b.t) for b in w.bonds], w.U, w.n_up, w.n_dn, P)
+    ridx = inv.RowIndex(w.n_sites, w.n_up, w.n_dn, P)
+    assert ridx.D == g.D
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, g.D)
+    dt, e = (torch.float64, EPS64) if dtype_name == "f64" else (torch.float32, EPS32)
+    if dtype_name == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    y = to_host(g.hv(to_dev(x, dt))).astype(np.float64)
+    rows = np.unique(np.concatenate([rng.integers(0, g.D, nrows), [0, g.D - 1]]))
+    gu, gd = g.unrank(to_dev(rows, torch.int64))
+    ru, rd = to_host(gu).view(np.uint32), to_host(gd).view(np.uint32)
+    assert all(ridx.index(u, d) == k for u, d, k in zip(ru, rd, rows))
+    want, a, n = inv.hv_rows_P(po, P, ridx, x, ru, rd)
+    bound = (n + 6) * e * a + n * EPS64 * a
+    err = np.abs(y[rows] - want)
+    assert np.all(err <= bound), (np.max(err - bound), dtype_name, P)
+    return g
+
+
+@pytest.mark.parametrize("P", [1, -1])
+def test_parity_hv_sampled_rows_torus4x3(P):
+    _sampled(synth.workload("torus4x3"), P, 150, 3, "f64")
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_parity_hv_full_size_sampled_rows(dtype_name):
+    g = _sampled(synth.workload("torus4x4_nnn"), 1, 60, 8, dtype_name)
+    assert g.D > 80_000_000
+
+
+@pytest.mark.parametrize("case", [SMALL[0], SMALL[2], SMALL[3], SMALL[6]], ids=["chain8", "open3x3", "open4x2", "open5x2"])
+def test_parity_lanczos_E0_matches_the_oracle(case):
+    N, bonds, U, nu, nd = case
+    po = _oracle(N, bonds, U, nu, nd)
+    for P in (1, -1):
+        HP = inv.build_csr_P(po, P)
+        v0 = np.random.default_rng(2).uniform(-1, 1, HP.shape[0])
+        e0 = sla.eigsh(HP, k=1, which="SA", v0=v0, tol=1e-13)[0][0] if HP.shape[0] > 64 else \
+            np.linalg.eigvalsh(HP.toarray())[0]
+        g = _gpu(N, bonds, U, nu, nd, P)
+        r = g.lanczos(storage="f64", tol=1e-12, max_iter=min(400, g.D + 2))
+        assert abs(r["E0"] - e0) <= 1e-9 * max(1.0, abs(e0)), (P, r["E0"], e0)
+
+
+def test_lowest_parity_is_the_real_space_ground_state():
+    """4x4 NN+NNN torus (point inversion through the centre), 8+8, U = 6."""
+    torch_cuda()
+    import paper_1707_03974_amd as pdz
+    w = synth.workload("torus4x4_nnn")
+    real = pdz.Problem.from_workload(w)
+    e_real = real.lanczos(storage="f64", tol=1e-11, max_iter=400)["E0"]
+    real.close()
+    e = []
+    for P in (1, -1):
+        g = pdz.ParityProblem.from_workload(w, P)
+        e.append(g.lanczos(storage="f64", tol=1e-11, max_iter=400)["E0"])
+        g.close()
+    assert abs(min(e) - e_real) <= 1e-8 * abs(e_real), (e, e_real)

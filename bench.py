@@ -313,6 +313,64 @@ def kspace_bench(torch, pdz, synth, reps=20, E_real=None, calibrate=False):
     return out
 
 
+def parity_bench(torch, pdz, synth, reps=20, E_real=None, calibrate=False):
+    """Inversion symmetry (Sec. IV.B, site i -> 15 - i: the point inversion of the 4x4 torus) on the 4x4 NN+NNN
+    cluster, 8+8, U = 6: both parity subspaces (FP32 Lanczos + FP64 refinement), the H.v of the lower one timed
+    in both precisions, and its time to E0 at 1e-8."""
+    w = synth.workload("torus4x4_nnn")
+    out = {"workload": "torus4x4_nnn restricted to inversion parity, 8+8, U=6", "parities": []}
+    for P in (1, -1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = pdz.ParityProblem.from_workload(w, P)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        r = g.lanczos(storage="f32", tol=1e-7, max_iter=400, refine=1, keep_basis=1)
+        out["parities"].append({"P": P, "D": g.D, "nnz_bound": g.nnz, "build_s": t_build, "E0": r["E0_refined"],
+                                "iters": r["iters"], "lanczos_s": r["seconds"]})
+        g.close()
+    best = min(out["parities"], key=lambda e: e["E0"])
+    out["ground_P"], out["E0"] = best["P"], best["E0"]
+    if E_real is not None:
+        out["E0_real_space"] = E_real
+        out["E0_diff"] = best["E0"] - E_real
+    g = pdz.ParityProblem.from_workload(w, best["P"])
+    out["D_P"], out["nnz_per_hv"] = g.D, g.nnz
+    stream = torch.cuda.current_stream()
+    for dt, name, es in ((torch.float32, "f32", 4), (torch.float64, "f64", 8)):
+        x = torch.empty(g.D, dtype=dt, device="cuda").uniform_(-1.0, 1.0)
+        y = torch.empty_like(x)
+        for _ in range(2):
+            g.hv(x, y, stream=stream)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            g.hv(x, y, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        alg = 2.0 * g.D * es
+        out["hv_" + name] = {"ms": ms, "nnz_per_s": g.nnz / (ms * 1e-3), "algorithmic_bytes": alg,
+                             "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        del x, y
+    for name, kw in (("f64", dict(storage="f64", tol=1e-10)),
+                     ("f32_refined", dict(storage="f32", tol=1e-7, refine=1, keep_basis=1))):
+        r = g.lanczos(max_iter=400, **kw)
+        e = r["E0_refined"] if name != "f64" else r["E0"]
+        out["time_to_E0_" + name] = {"s": r["seconds"], "iters": r["iters"], "E0": e,
+                                     "err_vs_real_space": (e - E_real) if E_real is not None else None}
+    if calibrate:
+        src = torch.empty(g.D, dtype=torch.float32, device="cuda").uniform_(-1.0, 1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": g.D * 4, "bytes_written": g.D * 4}
+    g.close()
+    return out
+
+
 def learned_bench(torch, pdz, synth, steps=3000):
     """Learned start on the 4x4 cluster with 7 + 7 electrons at U = 5 against random starts (time to E0 at 1e-8)."""
     import statistics
@@ -421,6 +479,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-dynamics", action="store_true")
     ap.add_argument("--no-kspace", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--parity-only", action="store_true",
+                    help="run only the inversion-parity section and print its JSON object")
     ap.add_argument("--kspace-only", action="store_true",
                     help="run only the momentum-space section and print its JSON object")
     ap.add_argument("--batched-only", action="store_true",
@@ -440,6 +501,10 @@ def main():
     torch.cuda.set_device(0)
     if args.batched_only:
         print(json.dumps({"batched": batched_bench(torch, pdz, synth, args.hv_reps)}), flush=True)
+        return
+    if args.parity_only:
+        print(json.dumps({"parity": parity_bench(torch, pdz, synth, args.hv_reps, calibrate=args.calibrate_copy)}),
+              flush=True)
         return
     if args.kspace_only:
         print(json.dumps({"kspace": kspace_bench(torch, pdz, synth, args.hv_reps, calibrate=args.calibrate_copy)}),
@@ -541,6 +606,12 @@ def main():
         ks = kspace_bench(torch, pdz, synth, args.hv_reps, E_real=e_real)
         _log(f"kspace: {json.dumps({k: v for k, v in ks.items() if k != 'per_K'})}")
 
+    par = None
+    if not args.no_parity:
+        e_real = tte.get("E0_ref") if tte is not None else None
+        par = parity_bench(torch, pdz, synth, args.hv_reps, E_real=e_real)
+        _log(f"parity: {json.dumps(par)}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -581,6 +652,7 @@ def main():
         "learned_start": learned_res,
         "dynamics": dyn,
         "kspace": ks,
+        "parity": par,
         "copy_calibration": copy,
         "hv_plans": tuned,
         "cpu_baseline": cpu,

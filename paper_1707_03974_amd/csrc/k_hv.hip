@@ -1273,10 +1273,6 @@ bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan) {
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                      const int* skip, unsigned passes, const HvSplit* split) {
     if (split && p->hv_path != 0) return fail(PDZ_EINVAL, "split H.v needs the table path");
-    if (p->ks || p->par) {
-        if (passes != (kPassDown | kPassUp)) return fail(PDZ_EINVAL, "a symmetry-sector H.v has no separate passes");
-        return p->ks ? launch_hvk(p, dt, x, y, s, skip) : launch_hvp(p, dt, x, y, s, skip);
-    }
     if (dt == PDZ_F64)
         return run_hv<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip,
                               passes, split);

@@ -679,13 +679,13 @@ struct Run {
         if (c.ndn > 0) {
             HvSplit sd;   // down pass (no z: it would be cleared after a down-only launch)
             sd.dotp_dn = partial();
-            pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown, &sd);
+            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown, &sd);
             if (st != PDZ_OK) return st;
             mark(1);
             HvSplit su;
             su.z = zbuf();
             su.dotp_up = partial() + c.ndn;
-            st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done(), kPassUp, &su);
+            st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassUp, &su);
             if (st != PDZ_OK) return st;
             mark(2);
             hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn,
@@ -693,7 +693,7 @@ struct Run {
             hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), c.ndn, partial2(),
                                (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
         } else {
-            pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done());
+            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done());
             if (st != PDZ_OK) return st;
             mark(1);
             mark(2);
@@ -721,7 +721,7 @@ struct Run {
         sp.z = zbuf();
         sp.dotp_dn = partial();
         sp.dotp_up = partial() + c.ndn;
-        pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sp);
+        pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sp);
         if (st != PDZ_OK) return st;
         hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn, (uint64_t)c.nup,
                            partial2(), done());
@@ -751,7 +751,7 @@ struct Run {
         f.fsc = sc();
         f.fkidx = kptr();
         f.fnorm = partial3();
-        pdz_status st = launch_hv(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassDown, &f);
+        pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassDown, &f);
         if (st != PDZ_OK) return st;
         mark(1);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial3(), c.ndn, beta(), kptr(), 1,
@@ -763,7 +763,7 @@ struct Run {
         HvSplit u;
         u.z = zbuf();
         u.dotp_up = partial() + c.ndn;
-        st = launch_hv(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassUp, &u);
+        st = launch_hv_any(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassUp, &u);
         if (st != PDZ_OK) return st;
         mark(3);
         hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn, (uint64_t)c.nup,
@@ -835,7 +835,7 @@ struct Run {
     // `reorth_nvec` > 0: re-orthogonalise against basis(0..reorth_nvec-1).
     pdz_status step(T* v, T* vp, T* w, int reorth_nvec) {
         const unsigned g = grid_elems(D);
-        pdz_status st = launch_hv(p, (pdz_dtype)o->storage, v, w, s, done());
+        pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, v, w, s, done());
         if (st != PDZ_OK) return st;
         hipLaunchKernelGGL((k_dot_partial<T, T>), dim3(kRedGrid), dim3(kRedBlock), 0, s, v, w, D, partial(), done());
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, alpha(), kptr(), 0,
@@ -995,7 +995,7 @@ struct Run {
                     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, ctl(), j, 0);
                     HvSplit sp;
                     sp.z = zbuf();
-                    st = launch_hv(p, (pdz_dtype)o->storage, q, w, s, nullptr, kPassDown | kPassUp,
+                    st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, nullptr, kPassDown | kPassUp,
                                    counts.ndn > 0 ? &sp : nullptr);
                     if (st != PDZ_OK) return st;
                     launch_update_scaled<T>(w, counts.ndn > 0 ? (const T*)zbuf() : (const T*)nullptr, q, qp, D,
@@ -1011,7 +1011,7 @@ struct Run {
                            (int)kStoreSqrt, (const int*)nullptr, err);
         hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kRedBlock), 0, s, y(), D, scr, (const int*)nullptr, 0,
                            (const int*)nullptr);
-        pdz_status st = launch_hv(p, PDZ_F64, y(), hy(), s, nullptr);
+        pdz_status st = launch_hv_any(p, PDZ_F64, y(), hy(), s, nullptr);
         if (st != PDZ_OK) return st;
         hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(kRedGrid), dim3(kRedBlock), 0, s, y(), hy(), D,
                            partial(), (const int*)nullptr);

@@ -73,6 +73,16 @@ uint64_t binom(int n, int k) {
     return r;
 }
 
+pdz_status launch_hv_any(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
+                         const int* skip, unsigned passes, const HvSplit* split) {
+    if (p->ks || p->par) {
+        if (split || passes != (kPassDown | kPassUp))
+            return fail(PDZ_EINVAL, "a symmetry-sector H.v has no separate passes");
+        return p->ks ? launch_hvk(p, dt, x, y, s, skip) : launch_hvp(p, dt, x, y, s, skip);
+    }
+    return launch_hv(p, dt, x, y, s, skip, passes, split);
+}
+
 }  // namespace pdz
 
 using namespace pdz;
@@ -336,7 +346,7 @@ pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* str
     int dev = 0;
     PDZ_HIP(hipGetDevice(&dev));
     if (dev != p->device) return fail(PDZ_EINVAL, "problem lives on another device");
-    return launch_hv(p, dt, x, y, (hipStream_t)stream);
+    return launch_hv_any(p, dt, x, y, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -179,9 +179,15 @@ struct HvSplit {
     double* fnorm = nullptr;
 };
 bool hv_fused_available(const pdz_problem_s* p, pdz_dtype dt);
+// H.v of a real-space problem (k_hv.hip)
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                      const int* skip = nullptr, unsigned passes = kPassDown | kPassUp,
                      const HvSplit* split = nullptr);
+// H.v of any problem: momentum and parity sectors go to their kernels (every
+// pass at once, no split form), real-space problems to launch_hv.
+pdz_status launch_hv_any(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
+                         const int* skip = nullptr, unsigned passes = kPassDown | kPassUp,
+                         const HvSplit* split = nullptr);
 bool hv_dot_counts(const pdz_problem_s* p, pdz_dtype dt, int* n_dn, int* n_up);   // false: no split path
 size_t hv_dot_count_max(const pdz_problem_s* p, pdz_dtype dt);   // n_dn + n_up over every valid plan
 

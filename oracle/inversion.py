@@ -25,9 +25,10 @@ Definitions used here:
   notes): a state's representative is decided by its up string, and by its
   down string when the up string is a palindrome.  Basis order: up
   representatives in tree order; behind a non-palindromic up string every
-  down string in ascending order; behind a palindromic up string the down
-  representatives in tree order, down palindromes only when the state is
-  itself even (F|s> = P|s>).
+  down string, in mirror pairs: each down representative in tree order
+  followed by its mirror image (a down palindrome alone); behind a
+  palindromic up string the down representatives in tree order, down
+  palindromes only when the state is itself even (F|s> = P|s>).
 * Basis vector of a representative r: (|r> + P F|r>) / sqrt(2), or |r> for a
   state with F|r> = +-|r> (kept only when F|r> = P|r>).
 * H_P = B^T H B with B the matrix of those basis vectors and H the real-space
@@ -123,10 +124,20 @@ def tree_order(N, n):
     return sorted(reps, key=lambda s: tree_key(s, N))
 
 
+def full_row_order(N, n):
+    """Down strings of a non-palindromic row: representatives in tree order, each followed by its mirror."""
+    out = []
+    for r in tree_order(N, n):
+        out.append(r)
+        if classify(r, N)[0] == "A":
+            out.append(reverse(r, N))
+    return out
+
+
 def basis(N, n_up, n_dn, P):
     """The parity-P basis as parallel arrays (up, dn, kind): kind 2 for a pair
     state (|r> + P F|r>)/sqrt(2), 1 for a state that F maps onto +-itself."""
-    dn_all = [int(s) for s in sector_list(N, n_dn)]
+    dn_all = full_row_order(N, n_dn)
     dn_reps = tree_order(N, n_dn)
     up, dn, kind = [], [], []
     for u in tree_order(N, n_up):
@@ -195,7 +206,7 @@ class RowIndex:
     def __init__(self, N, n_up, n_dn, P):
         self.N, self.P = N, P
         self.ups = tree_order(N, n_up)
-        self.dn_all = [int(s) for s in sector_list(N, n_dn)]
+        self.dn_all = full_row_order(N, n_dn)
         self.dn_col_full = {d: k for k, d in enumerate(self.dn_all)}
         self.offsets, self.pal_cols = {}, {}
         off = 0

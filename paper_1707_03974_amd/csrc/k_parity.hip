@@ -19,9 +19,11 @@
 //
 // Two spins: the up string decides the representative, the down string when
 // the up string is a palindrome.  Rows are the up representatives in tree
-// order; a non-palindromic row holds every down string in ascending order, a
-// palindromic row the down representatives in tree order (down palindromes
-// only when sigma = P).  Basis vector of a representative r:
+// order; a non-palindromic row holds every down string in mirror pairs (each
+// down representative in tree order followed by its mirror image, a
+// palindrome alone), so that the mirror of a column is its neighbour; a
+// palindromic row holds the down representatives in tree order (down
+// palindromes only when sigma = P).  Basis vector of a representative r:
 // (|r> + P F|r>)/sqrt(2), or |r> when F|r> = P|r>.
 //
 // H.v (gather form, H_P real symmetric): for a target t and each term of H
@@ -52,9 +54,20 @@ struct ParSpace {
     uint32_t* d_dtree = nullptr;
     uint32_t* d_dcol = nullptr;    // D_dn: column in a palindromic row (representatives), ~0 when excluded
     uint32_t* d_dlist = nullptr;   // Lp: down rank of each column of a palindromic row
+    uint32_t* d_dcolf = nullptr;   // D_dn: column of each down string in a full row
+    uint32_t* d_dlistf = nullptr;  // D_dn: down rank of each column of a full row
+    uint32_t* d_fmir = nullptr;    // D_dn: column of the mirror of a full row's column
+    uint8_t* d_fcnt = nullptr;     // D_dn: down hops of a full row's column
+    uint32_t* d_fell = nullptr;    // max_hops x D_dn: those hops as target column | amplitude index << 24
+    uint64_t* d_fup = nullptr;     // n_full x max_hops: up hops of each full row, source row start |
+                                   // class << 40 | amplitude index << 48, ~0 past the last
+    int fup_stride = 0;
     uint32_t* d_row_rank = nullptr;   // nrows: up rank of each row
     uint64_t* d_row_off = nullptr;    // nrows + 1
     uint8_t* d_row_pal = nullptr;     // nrows
+    uint32_t* d_rows_full = nullptr;  // rows of non-palindromic up strings (every down string)
+    uint32_t* d_rows_pal = nullptr;   // rows of palindromic up strings
+    uint64_t n_full = 0, n_pal = 0;
     uint32_t* d_S = nullptr;          // (N+1) x (nmax+1): representatives (palindromes included), Sec. IV.B
 };
 
@@ -130,54 +143,97 @@ struct PArgs {
     const uint32_t* dinv;
     const uint32_t* dcol;
     const uint32_t* dlist;
+    const uint32_t* dcolf;
+    const uint32_t* dlistf;
+    const uint32_t* fmir;
+    const uint8_t* fcnt;
+    const uint32_t* fell;
+    const uint64_t* fup;
+    int fup_stride;
     const uint32_t* row_rank;
     const uint64_t* row_off;
     const uint8_t* row_pal;
     const uint32_t* uinv;
-    uint64_t nrows;
+    const uint32_t* rows;   // the rows a launch covers
+    uint64_t nrows, nlist, Lp;
     double U;
     double ps;      // P * sigma
     int pal_in;     // self-mapped states belong to this parity (sigma == P)
 };
 
-// One work group per row; threads over the row's columns.
+// Rows of palindromic up strings (few): one work group per row, threads over
+// its columns (down representatives).
 template <typename T>
 __global__ __launch_bounds__(kPBlock) void k_hvp(const PArgs a, const T* __restrict__ coef, const T* __restrict__ x,
                                                   T* __restrict__ y, const int* skip) {
     if (skip && *skip) return;
     const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
-    for (uint64_t k = blockIdx.x; k < a.nrows; k += gridDim.x) {
+    // work group b: row b / chunks, columns (b % chunks) * kPBlock + thread
+    const uint64_t chunks = (a.Lp + kPBlock - 1) / kPBlock;
+    for (uint64_t b = blockIdx.x; b < a.nlist * chunks; b += gridDim.x) {
+        const uint64_t k = a.rows[b / chunks];
         const uint32_t ru = a.row_rank[k];
-        const bool pal = a.row_pal[k] != 0;
         const uint64_t off = a.row_off[k];
         const uint64_t len = a.row_off[k + 1] - off;
         const uint32_t phu = a.up_states[ru];
         const int nup_h = a.up_cnt[ru];
-        for (uint64_t c = threadIdx.x; c < len; c += kPBlock) {
-            const uint32_t rd = pal ? a.dlist[c] : (uint32_t)c;
-            const bool t_pair = !(pal && a.dcls[rd] == kClsPal);
-            const T wt = t_pair ? r2 : (T)1;
+        const uint64_t c = (b % chunks) * kPBlock + threadIdx.x;
+        if (c < len) {
+            const uint32_t rd = a.dlist[c];
+            const T wt = a.dcls[rd] == kClsPal ? (T)1 : r2;
             T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[rd])) * x[off + c];
-            // down hops: the up string stays
             const int ndh = a.dn_cnt[rd];
-            for (int h = 0; h < ndh; ++h) {
+            for (int h = 0; h < ndh; ++h) {   // the up string stays: a column of this row
                 const uint32_t e = a.dn_ell[(uint64_t)h * a.Ddn + rd];
                 const uint32_t rd2 = e & kTargetMask;
                 const T cf = coef[e >> kTargetBits];
-                if (!pal) {
-                    acc += cf * x[off + rd2];
-                } else {
-                    const uint8_t cl = a.dcls[rd2];
-                    if (cl == kClsA) {
-                        acc += wt * ir2 * cf * x[off + a.dcol[rd2]];
-                    } else if (cl == kClsImage) {
-                        acc += wt * ir2 * ps * cf * x[off + a.dcol[a.dinv[rd2]]];
-                    } else if (a.pal_in) {
-                        acc += wt * cf * x[off + a.dcol[rd2]];
-                    }
-                }
+                const uint8_t cl = a.dcls[rd2];
+                if (cl == kClsA)
+                    acc += wt * ir2 * cf * x[off + a.dcol[rd2]];
+                else if (cl == kClsImage)
+                    acc += wt * ir2 * ps * cf * x[off + a.dcol[a.dinv[rd2]]];
+                else if (a.pal_in)
+                    acc += wt * cf * x[off + a.dcol[rd2]];
             }
-            // up hops: the down string stays
+            for (int h = 0; h < nup_h; ++h) {   // one hop never leaves a palindrome a palindrome: a full row
+                const uint32_t e = a.up_ell[(uint64_t)h * a.Dup + ru];
+                const uint32_t ru2 = e & kTargetMask;
+                const T cf = coef[e >> kTargetBits];
+                const uint64_t off2 = a.row_off[a.urow[ru2]];
+                if (a.ucls[ru2] == kClsA)
+                    acc += wt * ir2 * cf * x[off2 + a.dcolf[rd]];
+                else
+                    acc += wt * ir2 * ps * cf * x[off2 + a.dcolf[a.dinv[rd]]];
+            }
+            y[off + c] = acc;
+        }
+    }
+}
+
+// Rows of non-palindromic up strings (nearly all the work): one work group per
+// row, threads over its columns.  Down hops stay in the row (column-space hop
+// table); an up hop reads the source row at the same column (representative)
+// or at the mirror column, its neighbour (image): both coalesced.
+template <typename T>
+__global__ __launch_bounds__(kPBlock) void k_hvp_full(const PArgs a, const T* __restrict__ coef,
+                                                       const T* __restrict__ x, T* __restrict__ y, const int* skip) {
+    if (skip && *skip) return;
+    const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
+    const uint32_t Dd = (uint32_t)a.Ddn;
+    for (uint64_t kk = blockIdx.x; kk < a.nlist; kk += gridDim.x) {
+        const uint64_t k = a.rows[kk];
+        const uint32_t ru = a.row_rank[k];
+        const uint64_t off = a.row_off[k];
+        const uint32_t phu = a.up_states[ru];
+        const int nup_h = a.up_cnt[ru];
+        for (uint32_t c = threadIdx.x; c < Dd; c += kPBlock) {
+            const uint32_t rd = a.dlistf[c];
+            T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[rd])) * x[off + c];
+            const int ndh = a.fcnt[c];
+            for (int h = 0; h < ndh; ++h) {
+                const uint32_t e = a.fell[(uint64_t)h * Dd + c];
+                acc += coef[e >> kTargetBits] * x[off + (e & kTargetMask)];
+            }
             for (int h = 0; h < nup_h; ++h) {
                 const uint32_t e = a.up_ell[(uint64_t)h * a.Dup + ru];
                 const uint32_t ru2 = e & kTargetMask;
@@ -185,21 +241,240 @@ __global__ __launch_bounds__(kPBlock) void k_hvp(const PArgs a, const T* __restr
                 const uint8_t cl = a.ucls[ru2];
                 const uint64_t off2 = a.row_off[a.urow[ru2]];
                 if (cl == kClsA) {
-                    acc += wt * ir2 * cf * x[off2 + rd];
+                    acc += r2 * ir2 * cf * x[off2 + c];
                 } else if (cl == kClsImage) {
-                    acc += wt * ir2 * ps * cf * x[off2 + a.dinv[rd]];
-                } else {
+                    acc += r2 * ir2 * ps * cf * x[off2 + a.fmir[c]];
+                } else {   // palindromic source up string: its row holds representatives only
                     const uint8_t dc = a.dcls[rd];
-                    if (dc == kClsA) {
-                        acc += wt * ir2 * cf * x[off2 + a.dcol[rd]];
-                    } else if (dc == kClsImage) {
-                        acc += wt * ir2 * ps * cf * x[off2 + a.dcol[a.dinv[rd]]];
-                    } else if (a.pal_in) {
-                        acc += wt * cf * x[off2 + a.dcol[rd]];
-                    }
+                    if (dc == kClsA)
+                        acc += r2 * ir2 * cf * x[off2 + a.dcol[rd]];
+                    else if (dc == kClsImage)
+                        acc += r2 * ir2 * ps * cf * x[off2 + a.dcol[a.dinv[rd]]];
+                    else if (a.pal_in)
+                        acc += r2 * cf * x[off2 + a.dcol[rd]];
                 }
             }
             y[off + c] = acc;
+        }
+    }
+}
+
+// The same with the row staged in LDS first (the down hops read LDS) and the
+// row's up hops resolved once per row into LDS (source row start, kind,
+// amplitude), so that the inner loop issues its up-hop loads back to back
+// instead of walking hop table -> class -> row -> row start for every column.
+// 1024 threads keep 16 waves per CU while a row of up to 150 KB holds the LDS.
+constexpr int kPLdsBlock = 1024;
+constexpr size_t kPRowLds = 150 * 1024;
+constexpr int kPMaxHops = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kPLdsBlock) void k_hvp_full_lds(const PArgs a, const T* __restrict__ coef,
+                                                              const T* __restrict__ x, T* __restrict__ y,
+                                                              const int* skip) {
+    if (skip && *skip) return;
+    extern __shared__ __align__(16) unsigned char pdyn[];
+    T* R = reinterpret_cast<T*>(pdyn);
+    __shared__ uint64_t s_off[kPMaxHops];
+    __shared__ T s_cf[kPMaxHops];
+    __shared__ uint8_t s_kind[kPMaxHops];   // class of the source up string
+    __shared__ int s_pal_any;               // some up hop of this row reaches a palindromic up string
+    const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
+    const uint32_t Dd = (uint32_t)a.Ddn;
+    for (uint64_t kk = blockIdx.x; kk < a.nlist; kk += gridDim.x) {
+        const uint64_t k = a.rows[kk];
+        const uint32_t ru = a.row_rank[k];
+        const uint64_t off = a.row_off[k];
+        const uint32_t phu = a.up_states[ru];
+        const int nup_h = a.up_cnt[ru];
+        __syncthreads();   // the previous row's reads of R and the hop arrays are done
+        if (threadIdx.x == 0) s_pal_any = 0;
+        for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) R[c] = x[off + c];
+        __syncthreads();
+        if (threadIdx.x < (unsigned)nup_h) {
+            const uint32_t e = a.up_ell[(uint64_t)threadIdx.x * a.Dup + ru];
+            const uint32_t ru2 = e & kTargetMask;
+            const uint8_t cl = a.ucls[ru2];
+            s_cf[threadIdx.x] = coef[e >> kTargetBits];
+            s_kind[threadIdx.x] = cl;
+            s_off[threadIdx.x] = a.row_off[a.urow[ru2]];
+            if (cl == kClsPal) s_pal_any = 1;   // every writer stores the same value
+        }
+        __syncthreads();
+        const bool any_pal = nup_h > 0 && s_pal_any;
+        for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) {
+            const uint32_t rd = a.dlistf[c];
+            const uint32_t cm = a.fmir[c];
+            // column and weight of this element's down string in a palindromic source row
+            uint32_t pcol = 0;
+            T pfac = (T)0;
+            if (any_pal) {
+                const uint8_t dc = a.dcls[rd];
+                if (dc == kClsA) {
+                    pcol = a.dcol[rd];
+                    pfac = r2 * ir2;
+                } else if (dc == kClsImage) {
+                    pcol = a.dcol[a.dinv[rd]];
+                    pfac = r2 * ir2 * ps;
+                } else if (a.pal_in) {
+                    pcol = a.dcol[rd];
+                    pfac = r2;
+                }
+            }
+            T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[rd])) * R[c];
+            const int ndh = a.fcnt[c];
+            for (int h = 0; h < ndh; ++h) {
+                const uint32_t e = a.fell[(uint64_t)h * Dd + c];
+                acc += coef[e >> kTargetBits] * R[e & kTargetMask];
+            }
+            // up hops four at a time: the four loads are issued before any is used
+            for (int h0 = 0; h0 < nup_h; h0 += 4) {
+                T v[4], f[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int h = h0 + j;
+                    v[j] = (T)0;
+                    f[j] = (T)0;
+                    if (h < nup_h) {
+                        const uint8_t cl = s_kind[h];
+                        const uint32_t col = cl == kClsA ? c : (cl == kClsImage ? cm : pcol);
+                        const T fac = cl == kClsA ? r2 * ir2 : (cl == kClsImage ? r2 * ir2 * ps : pfac);
+                        if (fac != (T)0) {
+                            v[j] = x[s_off[h] + col];
+                            f[j] = fac * s_cf[h];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (h0 + j < nup_h && f[j] != (T)0) acc += f[j] * v[j];
+            }
+            y[off + c] = acc;
+        }
+    }
+}
+
+// Two-pass form for full rows.  Down pass: the row staged in LDS, diagonal and
+// down hops, y written.  Up pass: work groups over (row, slab of kPCw
+// columns), four rows per group; slabs are dealt out XCD by XCD (work group b
+// runs on XCD b mod 8) and each XCD walks its slabs one at a time over every
+// row, so the slab (all rows at those columns) stays in that XCD's L2 while 34
+// rows read it.  Each row's up hops come from one precomputed 64-bit entry
+// (source row start, class, amplitude): no dependent lookups.
+constexpr int kPCw = 64;
+constexpr int kPUpRows = 4;
+constexpr uint64_t kFupNone = ~0ull;
+
+template <typename T>
+__global__ __launch_bounds__(kPLdsBlock) void k_hvp_down(const PArgs a, const T* __restrict__ coef,
+                                                          const T* __restrict__ x, T* __restrict__ y,
+                                                          const int* skip) {
+    if (skip && *skip) return;
+    extern __shared__ __align__(16) unsigned char pdyn[];
+    T* R = reinterpret_cast<T*>(pdyn);
+    __shared__ T s_coef[kMaxCoef];
+    for (int i = threadIdx.x; i < kMaxCoef; i += kPLdsBlock) s_coef[i] = coef[i];
+    const uint32_t Dd = (uint32_t)a.Ddn;
+    for (uint64_t kk = blockIdx.x; kk < a.nlist; kk += gridDim.x) {
+        const uint64_t k = a.rows[kk];
+        const uint64_t off = a.row_off[k];
+        const uint32_t phu = a.up_states[a.row_rank[k]];
+        __syncthreads();
+        for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) R[c] = x[off + c];
+        __syncthreads();
+        for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) {
+            T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[a.dlistf[c]])) * R[c];
+            const int ndh = a.fcnt[c];
+            for (int h0 = 0; h0 < ndh; h0 += 8) {   // eight table entries in flight, then their LDS reads
+                uint32_t e[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) e[j] = h0 + j < ndh ? a.fell[(uint64_t)(h0 + j) * Dd + c] : 0u;
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (h0 + j < ndh) acc += s_coef[e[j] >> kTargetBits] * R[e[j] & kTargetMask];
+            }
+            y[off + c] = acc;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPUpRows * kPCw) void k_hvp_up(const PArgs a, const T* __restrict__ coef,
+                                                             const T* __restrict__ x, T* __restrict__ y,
+                                                             const int* skip, uint64_t nslab) {
+    if (skip && *skip) return;
+    const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
+    const uint64_t groups = (a.nlist + kPUpRows - 1) / kPUpRows;   // work groups per slab
+    const uint64_t per_xcd = (nslab + 7) / 8;                        // slabs per XCD
+    const uint64_t xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+    const uint64_t slab = (j / groups) * 8 + xcd;                   // slab-major within the XCD
+    if (j / groups >= per_xcd || slab >= nslab) return;
+    const uint64_t kk = (j % groups) * kPUpRows + threadIdx.x / kPCw;   // one row per wave
+    if (kk >= a.nlist) return;                                       // whole wave
+    const uint32_t c = (uint32_t)(slab * kPCw + threadIdx.x % kPCw);
+    const bool live = c < (uint32_t)a.Ddn;                           // lanes past the row's end only help load
+    const uint64_t k = a.rows[kk];
+    const uint64_t off = a.row_off[k];
+    // the row's up hops: lane h holds entry h and its amplitude; the loop broadcasts them
+    const int lane = threadIdx.x % kPCw;
+    const uint64_t my_e = lane < a.fup_stride ? a.fup[kk * a.fup_stride + lane] : kFupNone;
+    const T my_cf = my_e != kFupNone ? coef[(my_e >> 48) & 0xFFu] : (T)0;
+    const int nh = __popcll(__ballot(my_e != kFupNone));   // entries are contiguous from 0
+    const uint32_t cm = live ? a.fmir[c] : 0u;
+    uint32_t pcol = 0;
+    T pfac = (T)0;
+    bool pal_ready = false;
+    T acc = (T)0;
+    for (int h0 = 0; h0 < nh; h0 += 8) {
+        T v[8], f[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const int h = h0 + jj < nh ? h0 + jj : 0;
+            const uint64_t e = __shfl(my_e, h, kPCw);
+            const T cf = __shfl(my_cf, h, kPCw);
+            v[jj] = (T)0;
+            f[jj] = (T)0;
+            if (h0 + jj < nh && live) {
+                const uint8_t cl = (uint8_t)((e >> 40) & 3u);
+                if (cl == kClsPal && !pal_ready) {   // this element's column in a palindromic row
+                    const uint32_t rd = a.dlistf[c];
+                    const uint8_t dc = a.dcls[rd];
+                    if (dc == kClsA) {
+                        pcol = a.dcol[rd];
+                        pfac = r2 * ir2;
+                    } else if (dc == kClsImage) {
+                        pcol = a.dcol[a.dinv[rd]];
+                        pfac = r2 * ir2 * ps;
+                    } else if (a.pal_in) {
+                        pcol = a.dcol[rd];
+                        pfac = r2;
+                    }
+                    pal_ready = true;
+                }
+                const uint32_t col = cl == kClsA ? c : (cl == kClsImage ? cm : pcol);
+                const T fac = cl == kClsA ? r2 * ir2 : (cl == kClsImage ? r2 * ir2 * ps : pfac);
+                if (fac != (T)0) {
+                    v[jj] = x[(e & 0xFFFFFFFFFFull) + col];
+                    f[jj] = fac * cf;
+                }
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj)
+            if (f[jj] != (T)0) acc += f[jj] * v[jj];
+    }
+    if (live) y[off + c] += acc;
+}
+
+// Full-row down-hop table in column space.
+__global__ __launch_bounds__(kPBlock) void k_pcolhops(const PArgs a, int max_hops, uint8_t* fcnt, uint32_t* fell) {
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.Ddn; c += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t rd = a.dlistf[c];
+        const int n = a.dn_cnt[rd];
+        fcnt[c] = (uint8_t)n;
+        for (int h = 0; h < n && h < max_hops; ++h) {
+            const uint32_t e = a.dn_ell[(uint64_t)h * a.Ddn + rd];
+            fell[(uint64_t)h * a.Ddn + c] = a.dcolf[e & kTargetMask] | (e & ~kTargetMask);
         }
     }
 }
@@ -223,7 +498,7 @@ __global__ __launch_bounds__(kPBlock) void k_prank(const PArgs a, const uint32_t
                 const uint32_t row = forward_map_inversion(u, n_up, N, sC, S, smax);
                 const uint32_t rd = forward_map(d, sC);
                 if (cu == kClsA) {
-                    r = a.row_off[row] + rd;
+                    r = a.row_off[row] + a.dcolf[rd];
                 } else {
                     const uint32_t col = a.dcol[rd];
                     if (classify(d, N) == kClsImage || col == kNoCol) bad = true;
@@ -256,7 +531,7 @@ __global__ __launch_bounds__(kPBlock) void k_punrank(const PArgs a, const uint64
             if (a.row_off[mid] <= p) lo = mid; else hi = mid;
         }
         const uint64_t c = p - a.row_off[lo];
-        const uint32_t rd = a.row_pal[lo] ? a.dlist[c] : (uint32_t)c;
+        const uint32_t rd = a.row_pal[lo] ? a.dlist[c] : a.dlistf[c];
         up[t] = a.up_states[a.row_rank[lo]];
         dn[t] = a.dn_states[rd];
     }
@@ -292,11 +567,21 @@ PArgs pargs(const pdz_problem_s* p) {
     a.dinv = q->d_dinv;
     a.dcol = q->d_dcol;
     a.dlist = q->d_dlist;
+    a.dcolf = q->d_dcolf;
+    a.dlistf = q->d_dlistf;
+    a.fmir = q->d_fmir;
+    a.fcnt = q->d_fcnt;
+    a.fell = q->d_fell;
+    a.fup = q->d_fup;
+    a.fup_stride = q->fup_stride;
     a.row_rank = q->d_row_rank;
     a.row_off = q->d_row_off;
     a.row_pal = q->d_row_pal;
     a.uinv = q->d_uinv;
+    a.rows = nullptr;
+    a.nlist = 0;
     a.nrows = q->nrows;
+    a.Lp = q->Lp;
     a.U = p->U;
     a.ps = (double)(q->P * q->sigma);
     a.pal_in = q->sigma == q->P;
@@ -315,25 +600,66 @@ unsigned pgrid(uint64_t n, unsigned cu) {
 void parity_free(ParSpace* q) {
     if (!q) return;
     void* ptrs[] = {q->d_ucls, q->d_uinv, q->d_utree, q->d_urow, q->d_dcls, q->d_dinv, q->d_dtree, q->d_dcol,
-                    q->d_dlist, q->d_row_rank, q->d_row_off, q->d_row_pal, q->d_S};
+                    q->d_dlist, q->d_row_rank, q->d_row_off, q->d_row_pal, q->d_S, q->d_rows_full, q->d_rows_pal,
+                    q->d_dcolf, q->d_dlistf, q->d_fmir, q->d_fcnt, q->d_fell, q->d_fup};
     for (void* v : ptrs)
         if (v) (void)hipFree(v);
     delete q;
 }
 
-pdz_status launch_hvp(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s, const int* skip) {
-    const PArgs a = pargs(p);
-    uint64_t grid = a.nrows;
-    if (grid > (1ull << 20)) grid = 1ull << 20;
-    if (grid < 1) return ok();
-    if (dt == PDZ_F64)
-        hipLaunchKernelGGL(k_hvp<double>, dim3((unsigned)grid), dim3(kPBlock), 0, s, a, p->d_coef64,
-                           static_cast<const double*>(x), static_cast<double*>(y), skip);
-    else
-        hipLaunchKernelGGL(k_hvp<float>, dim3((unsigned)grid), dim3(kPBlock), 0, s, a, p->d_coef32,
-                           static_cast<const float*>(x), static_cast<float*>(y), skip);
+namespace {
+
+template <typename T>
+pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipStream_t s, const int* skip) {
+    const ParSpace* q = p->par;
+    PArgs a = pargs(p);
+    if (q->n_full > 0) {
+        a.rows = q->d_rows_full;
+        a.nlist = q->n_full;
+        const unsigned grid = (unsigned)std::min<uint64_t>(q->n_full, 1ull << 20);
+        const size_t lds = (size_t)a.Ddn * sizeof(T);
+        if (lds <= kPRowLds && q->d_fup && q->fup_stride <= kPCw) {
+            hipLaunchKernelGGL(k_hvp_down<T>, dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y, skip);
+            const uint64_t nslab = (a.Ddn + kPCw - 1) / kPCw;
+            const uint64_t pairs = (q->n_full + kPUpRows - 1) / kPUpRows;
+            const uint64_t per_xcd = (nslab + 7) / 8;
+            const uint64_t g = 8 * per_xcd * pairs;
+            if (g >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
+            hipLaunchKernelGGL(k_hvp_up<T>, dim3((unsigned)g), dim3(kPUpRows * kPCw), 0, s, a, coef, x, y, skip, nslab);
+        } else if (lds <= kPRowLds && p->up.max_hops <= kPMaxHops)
+            hipLaunchKernelGGL(k_hvp_full_lds<T>, dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y, skip);
+        else
+            hipLaunchKernelGGL(k_hvp_full<T>, dim3(grid), dim3(kPBlock), 0, s, a, coef, x, y, skip);
+    }
+    if (q->n_pal > 0) {
+        a.rows = q->d_rows_pal;
+        a.nlist = q->n_pal;
+        const uint64_t g = q->n_pal * ((q->Lp + kPBlock - 1) / kPBlock);
+        hipLaunchKernelGGL(k_hvp<T>, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(g, 1), 1ull << 20)),
+                           dim3(kPBlock), 0, s, a, coef, x, y, skip);
+    }
     PDZ_HIP(hipGetLastError());
     return ok();
+}
+
+}  // namespace
+
+pdz_status parity_prepare() {
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_full_lds<double>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_full_lds<float>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<double>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<float>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
+    return ok();
+}
+
+pdz_status launch_hvp(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s, const int* skip) {
+    if (dt == PDZ_F64)
+        return run_hvp<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip);
+    return run_hvp<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip);
 }
 
 // Parity tables on top of a real-space problem with sector hop tables.
@@ -406,6 +732,20 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
         dlist.push_back(r);
     }
     q->Lp = dlist.size();
+    std::vector<uint32_t> dinv(Dd);
+    PDZ_HIP(hipMemcpy(dinv.data(), q->d_dinv, Dd * 4, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> dlistf, dcolf(Dd, kNoCol), fmir(Dd);
+    for (uint64_t k = 0; k < dreps; ++k) {   // each representative, then its mirror
+        const uint32_t r = dby_tree[k];
+        dlistf.push_back(r);
+        if (dcls[r] == kClsA) dlistf.push_back(dinv[r]);
+    }
+    if (dlistf.size() != Dd) return fail(PDZ_EDEVICE, "mirror pairs do not cover the down sector");
+    for (uint64_t c = 0; c < Dd; ++c) {
+        if (dcolf[dlistf[c]] != kNoCol) return fail(PDZ_EDEVICE, "a down string appears twice in a full row");
+        dcolf[dlistf[c]] = (uint32_t)c;
+    }
+    for (uint64_t c = 0; c < Dd; ++c) fmir[c] = dcolf[dinv[dlistf[c]]];
     std::vector<uint64_t> row_off(ureps + 1, 0);
     std::vector<uint8_t> row_pal(ureps);
     for (uint64_t k = 0; k < ureps; ++k) {
@@ -426,6 +766,46 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
     if ((st = dupload(&q->d_urow, urow)) != PDZ_OK) return st;
     if ((st = dupload(&q->d_dcol, dcol)) != PDZ_OK) return st;
     if ((st = dupload(&q->d_dlist, dlist)) != PDZ_OK) return st;
+    if ((st = dupload(&q->d_dlistf, dlistf)) != PDZ_OK) return st;
+    if ((st = dupload(&q->d_dcolf, dcolf)) != PDZ_OK) return st;
+    if ((st = dupload(&q->d_fmir, fmir)) != PDZ_OK) return st;
+    const int mh = p->dn.max_hops > 0 ? p->dn.max_hops : 1;
+    if ((st = dalloc(&q->d_fcnt, Dd)) != PDZ_OK) return st;
+    if ((st = dalloc(&q->d_fell, (uint64_t)mh * Dd)) != PDZ_OK) return st;
+    {
+        const PArgs pa = pargs(p);
+        hipLaunchKernelGGL(k_pcolhops, dim3(pgrid(Dd, cu)), dim3(kPBlock), 0, nullptr, pa, mh, q->d_fcnt, q->d_fell);
+        PDZ_HIP(hipGetLastError());
+        PDZ_HIP(hipDeviceSynchronize());
+    }
+    std::vector<uint32_t> rows_full, rows_pal;
+    for (uint64_t k = 0; k < ureps; ++k) (row_pal[k] ? rows_pal : rows_full).push_back((uint32_t)k);
+    q->n_full = rows_full.size();
+    q->n_pal = rows_pal.size();
+    if ((st = dupload(&q->d_rows_full, rows_full)) != PDZ_OK) return st;
+    {   // up hops of every full row as single entries
+        const int mhu = p->up.max_hops;
+        std::vector<uint8_t> ucnt_h(Du);
+        std::vector<uint32_t> uell_h((size_t)std::max(mhu, 1) * Du);
+        PDZ_HIP(hipMemcpy(ucnt_h.data(), p->up.count, Du, hipMemcpyDeviceToHost));
+        if (mhu > 0) PDZ_HIP(hipMemcpy(uell_h.data(), p->up.ell, (size_t)mhu * Du * 4, hipMemcpyDeviceToHost));
+        const int stride = std::max(mhu, 1);
+        std::vector<uint64_t> fup((size_t)rows_full.size() * stride, kFupNone);
+        bool fits = row_off[ureps] < (1ull << 40);
+        for (size_t kk = 0; kk < rows_full.size() && fits; ++kk) {
+            const uint32_t ru = row_rank[rows_full[kk]];
+            for (int h = 0; h < ucnt_h[ru]; ++h) {
+                const uint32_t e = uell_h[(size_t)h * Du + ru];
+                const uint32_t ru2 = e & kTargetMask;
+                fup[kk * stride + h] = row_off[urow[ru2]] | ((uint64_t)ucls[ru2] << 40) | ((uint64_t)(e >> kTargetBits) << 48);
+            }
+        }
+        if (fits) {
+            q->fup_stride = stride;
+            if ((st = dupload(&q->d_fup, fup)) != PDZ_OK) return st;
+        }
+    }
+    if ((st = dupload(&q->d_rows_pal, rows_pal)) != PDZ_OK) return st;
     // structural nonzeros: per element its diagonal plus every hop whose source has a component here
     std::vector<uint8_t> ucnt(Du), dcnt(Dd);
     PDZ_HIP(hipMemcpy(ucnt.data(), p->up.count, Du, hipMemcpyDeviceToHost));

@@ -46,6 +46,7 @@ pdz_status device_ctx(DeviceCtx** out) {
         pdz_status hs = hv_prepare();
         if (hs == PDZ_OK) hs = batch_prepare();
         if (hs == PDZ_OK) hs = kspace_prepare();
+        if (hs == PDZ_OK) hs = parity_prepare();
         if (hs != PDZ_OK) return hs;
         c.cu_count = prop.multiProcessorCount;
         c.lds_per_block = prop.sharedMemPerBlock;

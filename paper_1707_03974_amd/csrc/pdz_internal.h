@@ -138,6 +138,7 @@ pdz_status build_compact_table(SectorTables* st, int ncoef, hipStream_t s);
 pdz_status hv_prepare();   // per-device kernel attributes, called once outside any capture
 pdz_status batch_prepare();   // the same for the batched H.v kernels
 pdz_status kspace_prepare();  // the same for the momentum-space H.v kernels
+pdz_status parity_prepare();  // the same for the parity H.v kernels
 void kspace_free(KSpace* ks);
 void parity_free(ParSpace* q);
 // y = H x on an inversion-parity subspace

@@ -106,6 +106,19 @@ def test_paper_counts_and_forward_map_give_the_tree_order(N, n):
     assert [inv.paper_forward_map_inversion(r, N, n) for r in reps] == list(range(len(reps)))
 
 
+def test_full_rows_hold_every_down_string_in_mirror_pairs():
+    for N, n in ((8, 4), (9, 4), (6, 3)):
+        order = inv.full_row_order(N, n)
+        assert sorted(order) == [int(s) for s in sector_list(N, n)]
+        k = 0
+        while k < len(order):
+            if inv.classify(order[k], N)[0] == "P":
+                k += 1
+            else:
+                assert inv.classify(order[k], N)[0] == "A" and order[k + 1] == inv.reverse(order[k], N)
+                k += 2
+
+
 def test_row_index_matches_the_basis_order():
     for (N, bonds, U, nu, nd) in CASES[:4]:
         for P in (1, -1):

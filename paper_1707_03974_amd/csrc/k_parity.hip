@@ -34,6 +34,7 @@
 // rep(s) comes from per-string tables: class, mirror rank, row, column.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,7 @@ struct ParSpace {
     uint64_t* d_fup = nullptr;     // n_full x max_hops: up hops of each full row, source row start |
                                    // class << 40 | amplitude index << 48, ~0 past the last
     int fup_stride = 0;
+    bool force_gather = false;     // PDZ_PARITY_GATHER=1: full rows by the one-pass gather kernel (its test)
     uint32_t* d_row_rank = nullptr;   // nrows: up rank of each row
     uint64_t* d_row_off = nullptr;    // nrows + 1
     uint8_t* d_row_pal = nullptr;     // nrows
@@ -210,10 +212,11 @@ __global__ __launch_bounds__(kPBlock) void k_hvp(const PArgs a, const T* __restr
     }
 }
 
-// Rows of non-palindromic up strings (nearly all the work): one work group per
-// row, threads over its columns.  Down hops stay in the row (column-space hop
-// table); an up hop reads the source row at the same column (representative)
-// or at the mirror column, its neighbour (image): both coalesced.
+// Rows of non-palindromic up strings in one pass, for rows too long for the
+// LDS of the two-pass form or with more up hops than a wave holds: one work
+// group per row, threads over its columns.  Down hops stay in the row
+// (column-space hop table); an up hop reads the source row at the same column
+// (representative) or at the mirror column, its neighbour (image).
 template <typename T>
 __global__ __launch_bounds__(kPBlock) void k_hvp_full(const PArgs a, const T* __restrict__ coef,
                                                        const T* __restrict__ x, T* __restrict__ y, const int* skip) {
@@ -259,100 +262,9 @@ __global__ __launch_bounds__(kPBlock) void k_hvp_full(const PArgs a, const T* __
     }
 }
 
-// The same with the row staged in LDS first (the down hops read LDS) and the
-// row's up hops resolved once per row into LDS (source row start, kind,
-// amplitude), so that the inner loop issues its up-hop loads back to back
-// instead of walking hop table -> class -> row -> row start for every column.
-// 1024 threads keep 16 waves per CU while a row of up to 150 KB holds the LDS.
+// LDS budget of the two-pass form: one staged row per work group of 1024 threads.
 constexpr int kPLdsBlock = 1024;
 constexpr size_t kPRowLds = 150 * 1024;
-constexpr int kPMaxHops = 256;
-
-template <typename T>
-__global__ __launch_bounds__(kPLdsBlock) void k_hvp_full_lds(const PArgs a, const T* __restrict__ coef,
-                                                              const T* __restrict__ x, T* __restrict__ y,
-                                                              const int* skip) {
-    if (skip && *skip) return;
-    extern __shared__ __align__(16) unsigned char pdyn[];
-    T* R = reinterpret_cast<T*>(pdyn);
-    __shared__ uint64_t s_off[kPMaxHops];
-    __shared__ T s_cf[kPMaxHops];
-    __shared__ uint8_t s_kind[kPMaxHops];   // class of the source up string
-    __shared__ int s_pal_any;               // some up hop of this row reaches a palindromic up string
-    const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
-    const uint32_t Dd = (uint32_t)a.Ddn;
-    for (uint64_t kk = blockIdx.x; kk < a.nlist; kk += gridDim.x) {
-        const uint64_t k = a.rows[kk];
-        const uint32_t ru = a.row_rank[k];
-        const uint64_t off = a.row_off[k];
-        const uint32_t phu = a.up_states[ru];
-        const int nup_h = a.up_cnt[ru];
-        __syncthreads();   // the previous row's reads of R and the hop arrays are done
-        if (threadIdx.x == 0) s_pal_any = 0;
-        for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) R[c] = x[off + c];
-        __syncthreads();
-        if (threadIdx.x < (unsigned)nup_h) {
-            const uint32_t e = a.up_ell[(uint64_t)threadIdx.x * a.Dup + ru];
-            const uint32_t ru2 = e & kTargetMask;
-            const uint8_t cl = a.ucls[ru2];
-            s_cf[threadIdx.x] = coef[e >> kTargetBits];
-            s_kind[threadIdx.x] = cl;
-            s_off[threadIdx.x] = a.row_off[a.urow[ru2]];
-            if (cl == kClsPal) s_pal_any = 1;   // every writer stores the same value
-        }
-        __syncthreads();
-        const bool any_pal = nup_h > 0 && s_pal_any;
-        for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) {
-            const uint32_t rd = a.dlistf[c];
-            const uint32_t cm = a.fmir[c];
-            // column and weight of this element's down string in a palindromic source row
-            uint32_t pcol = 0;
-            T pfac = (T)0;
-            if (any_pal) {
-                const uint8_t dc = a.dcls[rd];
-                if (dc == kClsA) {
-                    pcol = a.dcol[rd];
-                    pfac = r2 * ir2;
-                } else if (dc == kClsImage) {
-                    pcol = a.dcol[a.dinv[rd]];
-                    pfac = r2 * ir2 * ps;
-                } else if (a.pal_in) {
-                    pcol = a.dcol[rd];
-                    pfac = r2;
-                }
-            }
-            T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[rd])) * R[c];
-            const int ndh = a.fcnt[c];
-            for (int h = 0; h < ndh; ++h) {
-                const uint32_t e = a.fell[(uint64_t)h * Dd + c];
-                acc += coef[e >> kTargetBits] * R[e & kTargetMask];
-            }
-            // up hops four at a time: the four loads are issued before any is used
-            for (int h0 = 0; h0 < nup_h; h0 += 4) {
-                T v[4], f[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int h = h0 + j;
-                    v[j] = (T)0;
-                    f[j] = (T)0;
-                    if (h < nup_h) {
-                        const uint8_t cl = s_kind[h];
-                        const uint32_t col = cl == kClsA ? c : (cl == kClsImage ? cm : pcol);
-                        const T fac = cl == kClsA ? r2 * ir2 : (cl == kClsImage ? r2 * ir2 * ps : pfac);
-                        if (fac != (T)0) {
-                            v[j] = x[s_off[h] + col];
-                            f[j] = fac * s_cf[h];
-                        }
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (h0 + j < nup_h && f[j] != (T)0) acc += f[j] * v[j];
-            }
-            y[off + c] = acc;
-        }
-    }
-}
 
 // Two-pass form for full rows.  Down pass: the row staged in LDS, diagonal and
 // down hops, y written.  Up pass: work groups over (row, slab of kPCw
@@ -618,7 +530,7 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
         a.nlist = q->n_full;
         const unsigned grid = (unsigned)std::min<uint64_t>(q->n_full, 1ull << 20);
         const size_t lds = (size_t)a.Ddn * sizeof(T);
-        if (lds <= kPRowLds && q->d_fup && q->fup_stride <= kPCw) {
+        if (!q->force_gather && lds <= kPRowLds && q->d_fup && q->fup_stride <= kPCw) {
             hipLaunchKernelGGL(k_hvp_down<T>, dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y, skip);
             const uint64_t nslab = (a.Ddn + kPCw - 1) / kPCw;
             const uint64_t pairs = (q->n_full + kPUpRows - 1) / kPUpRows;
@@ -626,9 +538,7 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
             const uint64_t g = 8 * per_xcd * pairs;
             if (g >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
             hipLaunchKernelGGL(k_hvp_up<T>, dim3((unsigned)g), dim3(kPUpRows * kPCw), 0, s, a, coef, x, y, skip, nslab);
-        } else if (lds <= kPRowLds && p->up.max_hops <= kPMaxHops)
-            hipLaunchKernelGGL(k_hvp_full_lds<T>, dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y, skip);
-        else
+        } else
             hipLaunchKernelGGL(k_hvp_full<T>, dim3(grid), dim3(kPBlock), 0, s, a, coef, x, y, skip);
     }
     if (q->n_pal > 0) {
@@ -645,10 +555,6 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
 }  // namespace
 
 pdz_status parity_prepare() {
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_full_lds<double>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_full_lds<float>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<double>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<float>),
@@ -668,6 +574,10 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
     p->par = q;
     const int N = p->N, nu = p->n_up, nd = p->n_dn;
     q->P = P;
+    {
+        const char* env = std::getenv("PDZ_PARITY_GATHER");
+        q->force_gather = env && env[0] == '1';
+    }
     q->sigma = (((nu * (nu - 1) / 2) + (nd * (nd - 1) / 2)) % 2) ? -1 : 1;
     const int smax = std::max(nu, nd);
     // S_i^m = C_{i-2}^{m-1} + S_{i-2}^m + S_{i-2}^{m-2}, S_0^0 = 1, S_1^0 = S_1^1 = 1

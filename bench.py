@@ -371,6 +371,81 @@ def parity_bench(torch, pdz, synth, reps=20, E_real=None, calibrate=False):
     return out
 
 
+def hv_median_ms(torch, g, dtype, n=50, warm=5):
+    """Median duration of n back-to-back pdz_hv launches after warm-ups, each bracketed by HIP events."""
+    x = torch.empty(g.D, dtype=dtype, device="cuda").uniform_(-1.0, 1.0)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(warm):
+        g.hv(x, y, stream=stream)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    evs[0].record(stream)
+    for i in range(n):
+        g.hv(x, y, stream=stream)
+        evs[i + 1].record(stream)
+    evs[-1].synchronize()
+    t = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(n))
+    del x, y
+    return t[n // 2]
+
+
+def configs_bench(torch, pdz, synth, D_copy):
+    """H.v throughput of the other problem configurations (median of 50 launches, tuned plans), the 4x3
+    cluster also on the on-the-fly path with its 100-step Lanczos, and a measured bandwidth ceiling (a plain
+    device copy of D_copy floats)."""
+    import os
+    out = {}
+    for name in ("ring8", "torus4x3", "torus4x4_n7"):
+        w = synth.workload(name)
+        paths = [("tables", None)] + ([("on_the_fly", "1")] if name == "torus4x3" else [])
+        for path, env in paths:
+            old = os.environ.get("PDZ_HV_ONTHEFLY")
+            if env:
+                os.environ["PDZ_HV_ONTHEFLY"] = env
+            try:
+                g = pdz.Problem.from_workload(w)
+            finally:
+                if env:
+                    if old is None:
+                        del os.environ["PDZ_HV_ONTHEFLY"]
+                    else:
+                        os.environ["PDZ_HV_ONTHEFLY"] = old
+            rec = {"D": g.D, "nnz": g.nnz, "path": path}
+            for dt, dn, es in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
+                if path == "tables":
+                    g.tune(dn, reps=3)
+                ms = hv_median_ms(torch, g, dt)
+                alg = 2.0 * g.D * es
+                rec["hv_" + dn] = {"ms": ms, "nnz_per_s": g.nnz / (ms * 1e-3), "achieved_GBs": alg / (ms * 1e-3) / 1e9,
+                                   "frac": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                   "fits_on_chip": g.D * es * 2 <= 256e6}
+            if name != "torus4x4_n7":
+                ref = g.lanczos(storage="f64", tol=1e-12, max_iter=600)
+                cap = 100 if name == "torus4x3" else 600
+                r = g.lanczos(storage="f64", tol=1e-8, max_iter=cap)
+                rec["lanczos_f64"] = {"max_iter": cap, "iters": r["iters"], "converged": bool(r["converged"]),
+                                      "E0": r["E0"], "rel_err_vs_1e-12_run": abs(r["E0"] - ref["E0"]) / abs(ref["E0"]),
+                                      "seconds": r["seconds"]}
+            out[name + ("" if path == "tables" else "_on_the_fly")] = rec
+            g.close()
+    src = torch.empty(D_copy, dtype=torch.float32, device="cuda").uniform_(-1.0, 1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    ev1.record()
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1) / 10
+    out["copy_ceiling"] = {"bytes_moved": 2 * D_copy * 4, "ms": ms, "GBs": 2 * D_copy * 4 / (ms * 1e-3) / 1e9,
+                           "frac_of_8TBs": 2 * D_copy * 4 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    del src, dst
+    return out
+
+
 def learned_bench(torch, pdz, synth, steps=3000):
     """Learned start on the 4x4 cluster with 7 + 7 electrons at U = 5 against random starts (time to E0 at 1e-8)."""
     import statistics
@@ -480,6 +555,7 @@ def main():
     ap.add_argument("--no-dynamics", action="store_true")
     ap.add_argument("--no-kspace", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--parity-only", action="store_true",
                     help="run only the inversion-parity section and print its JSON object")
     ap.add_argument("--kspace-only", action="store_true",
@@ -612,6 +688,11 @@ def main():
         par = parity_bench(torch, pdz, synth, args.hv_reps, E_real=e_real)
         _log(f"parity: {json.dumps(par)}")
 
+    cfgs = None
+    if not args.no_configs:
+        cfgs = configs_bench(torch, pdz, synth, D)
+        _log(f"configs: {json.dumps(cfgs)}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -653,6 +734,7 @@ def main():
         "dynamics": dyn,
         "kspace": ks,
         "parity": par,
+        "configs": cfgs,
         "copy_calibration": copy,
         "hv_plans": tuned,
         "cpu_baseline": cpu,

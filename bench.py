@@ -520,9 +520,18 @@ def cpu_baseline(w, target_s=12.0):
     mf.rows(x, 0, R2)
     t = time.perf_counter() - t0
     nnz = row_nnz(0, R2)
+    # the same oracle on one thread, over a smaller sample (about a fifth of the time budget)
+    one = MatrixFree(po, nthreads=1)
+    R1 = int(min(po.D, max(10_000, R2 * 0.2 / max(cores, 1))))
+    t1 = time.perf_counter()
+    one.rows(x, 0, R1)
+    t1 = time.perf_counter() - t1
+    nnz1 = row_nnz(0, R1)
     return {"value": nnz / t, "unit": "nonzeros/s", "cores": cores, "kind": "oracle",
             "sample": f"rows [0, {R2}) of the same H.v ({R2 / po.D:.2%} of D, {nnz} nonzeros), FP64, "
-                      f"{t:.1f} s, {cores} OpenMP threads"}
+                      f"{t:.1f} s, {cores} OpenMP threads",
+            "single_thread": {"value": nnz1 / t1, "unit": "nonzeros/s", "cores": 1,
+                              "sample": f"rows [0, {R1}) ({nnz1} nonzeros), {t1:.1f} s"}}
 
 
 def _sector_hops(po, spin):

@@ -102,3 +102,10 @@ def test_batch_calls_reject_null_arguments_without_a_device():
     assert lib.pdz_batch_lanczos_workspace_size(None, ctypes.byref(o), ctypes.byref(n)) == _lib.PDZ_EINVAL
     res = (_lib.LanczosResult * 1)()
     assert lib.pdz_batch_lanczos(None, ctypes.byref(o), None, 0, res, None) == _lib.PDZ_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No CPU fallback: without the built HIP library the binding raises."""
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError, match="no fallback"):
+        _lib.load(os.path.join(ROOT, "does_not_exist", "libpdz.so"))

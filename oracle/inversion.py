@@ -25,8 +25,8 @@ Definitions used here:
   notes): a state's representative is decided by its up string, and by its
   down string when the up string is a palindrome.  Basis order: up
   representatives in tree order; behind a non-palindromic up string every
-  down string, in mirror pairs: each down representative in tree order
-  followed by its mirror image (a down palindrome alone); behind a
+  down string: each down A representative in tree order followed by its
+  mirror image, then the down palindromes in tree order; behind a
   palindromic up string the down representatives in tree order, down
   palindromes only when the state is itself even (F|s> = P|s>).
 * Basis vector of a representative r: (|r> + P F|r>) / sqrt(2), or |r> for a
@@ -125,13 +125,14 @@ def tree_order(N, n):
 
 
 def full_row_order(N, n):
-    """Down strings of a non-palindromic row: representatives in tree order, each followed by its mirror."""
+    """Down strings of a non-palindromic row: the A representatives in tree order, each followed by its
+    mirror, then the palindromes in tree order."""
+    reps = tree_order(N, n)
     out = []
-    for r in tree_order(N, n):
-        out.append(r)
+    for r in reps:
         if classify(r, N)[0] == "A":
-            out.append(reverse(r, N))
-    return out
+            out += [r, reverse(r, N)]
+    return out + [r for r in reps if classify(r, N)[0] == "P"]
 
 
 def basis(N, n_up, n_dn, P):

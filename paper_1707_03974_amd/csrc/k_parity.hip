@@ -20,8 +20,9 @@
 // Two spins: the up string decides the representative, the down string when
 // the up string is a palindrome.  Rows are the up representatives in tree
 // order; a non-palindromic row holds every down string in mirror pairs (each
-// down representative in tree order followed by its mirror image, a
-// palindrome alone), so that the mirror of a column is its neighbour; a
+// down representative in tree order followed by its mirror image), then the
+// down palindromes: the mirror of a column is its neighbour and pairs start at
+// even columns; a
 // palindromic row holds the down representatives in tree order (down
 // palindromes only when sigma = P).  Basis vector of a representative r:
 // (|r> + P F|r>)/sqrt(2), or |r> when F|r> = P|r>.
@@ -63,6 +64,7 @@ struct ParSpace {
     uint64_t* d_fup = nullptr;     // n_full x max_hops: up hops of each full row, source row start |
                                    // class << 40 | amplitude index << 48, ~0 past the last
     int fup_stride = 0;
+    uint64_t npair2 = 0;           // columns of a full row taken by mirror pairs (the rest: palindromes)
     bool force_gather = false;     // PDZ_PARITY_GATHER=1: full rows by the one-pass gather kernel (its test)
     uint32_t* d_row_rank = nullptr;   // nrows: up rank of each row
     uint64_t* d_row_off = nullptr;    // nrows + 1
@@ -152,6 +154,7 @@ struct PArgs {
     const uint32_t* fell;
     const uint64_t* fup;
     int fup_stride;
+    uint64_t npair2;
     const uint32_t* row_rank;
     const uint64_t* row_off;
     const uint8_t* row_pal;
@@ -267,7 +270,7 @@ constexpr int kPLdsBlock = 1024;
 constexpr size_t kPRowLds = 150 * 1024;
 
 // Two-pass form for full rows.  Down pass: the row staged in LDS, diagonal and
-// down hops, y written.  Up pass: work groups over (row, slab of kPCw
+// down hops, y written.  Up pass: work groups over (row, slab of 2 kPCw
 // columns), four rows per group; slabs are dealt out XCD by XCD (work group b
 // runs on XCD b mod 8) and each XCD walks its slabs one at a time over every
 // row, so the slab (all rows at those columns) stays in that XCD's L2 while 34
@@ -310,11 +313,20 @@ __global__ __launch_bounds__(kPLdsBlock) void k_hvp_down(const PArgs a, const T*
     }
 }
 
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+// Each thread takes two columns c0 = 2i, c0 + 1.  In the head of the row they
+// are a mirror pair: one 8- or 16-byte load of the source row at c0 serves both
+// (swapped for an image source) when the source row starts at an even index;
+// otherwise, and in the palindrome tail, two scalar loads.
 template <typename T>
 __global__ __launch_bounds__(kPUpRows * kPCw) void k_hvp_up(const PArgs a, const T* __restrict__ coef,
                                                              const T* __restrict__ x, T* __restrict__ y,
-                                                             const int* skip, uint64_t nslab) {
+                                                             const int* skip, uint64_t nslab, int vec_ok) {
     if (skip && *skip) return;
+    using V2 = typename Vec2<T>::type;
     const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
     const uint64_t groups = (a.nlist + kPUpRows - 1) / kPUpRows;   // work groups per slab
     const uint64_t per_xcd = (nslab + 7) / 8;                        // slabs per XCD
@@ -323,59 +335,85 @@ __global__ __launch_bounds__(kPUpRows * kPCw) void k_hvp_up(const PArgs a, const
     if (j / groups >= per_xcd || slab >= nslab) return;
     const uint64_t kk = (j % groups) * kPUpRows + threadIdx.x / kPCw;   // one row per wave
     if (kk >= a.nlist) return;                                       // whole wave
-    const uint32_t c = (uint32_t)(slab * kPCw + threadIdx.x % kPCw);
-    const bool live = c < (uint32_t)a.Ddn;                           // lanes past the row's end only help load
+    const uint32_t Dd = (uint32_t)a.Ddn;
+    const uint32_t c0 = (uint32_t)(slab * (2 * kPCw) + 2 * (threadIdx.x % kPCw));
+    const bool live0 = c0 < Dd, live1 = c0 + 1 < Dd;                 // lanes past the row's end only help load
+    const bool pair = c0 + 1 < (uint32_t)a.npair2;                   // c0, c0 + 1 are mirror images
     const uint64_t k = a.rows[kk];
     const uint64_t off = a.row_off[k];
-    // the row's up hops: lane h holds entry h and its amplitude; the loop broadcasts them
     const int lane = threadIdx.x % kPCw;
     const uint64_t my_e = lane < a.fup_stride ? a.fup[kk * a.fup_stride + lane] : kFupNone;
     const T my_cf = my_e != kFupNone ? coef[(my_e >> 48) & 0xFFu] : (T)0;
-    const int nh = __popcll(__ballot(my_e != kFupNone));   // entries are contiguous from 0
-    const uint32_t cm = live ? a.fmir[c] : 0u;
-    uint32_t pcol = 0;
-    T pfac = (T)0;
+    const int nh = __popcll(__ballot(my_e != kFupNone));
+    uint32_t pcol[2] = {0u, 0u};
+    T pfac[2] = {(T)0, (T)0};
     bool pal_ready = false;
-    T acc = (T)0;
-    for (int h0 = 0; h0 < nh; h0 += 8) {
-        T v[8], f[8];
+    T acc0 = (T)0, acc1 = (T)0;
+    for (int h0 = 0; h0 < nh; h0 += 4) {
+        T v0[4], v1[4], f0[4], f1[4];
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
+        for (int jj = 0; jj < 4; ++jj) {
             const int h = h0 + jj < nh ? h0 + jj : 0;
             const uint64_t e = __shfl(my_e, h, kPCw);
             const T cf = __shfl(my_cf, h, kPCw);
-            v[jj] = (T)0;
-            f[jj] = (T)0;
-            if (h0 + jj < nh && live) {
+            v0[jj] = v1[jj] = f0[jj] = f1[jj] = (T)0;
+            if (h0 + jj < nh && live0) {
                 const uint8_t cl = (uint8_t)((e >> 40) & 3u);
-                if (cl == kClsPal && !pal_ready) {   // this element's column in a palindromic row
-                    const uint32_t rd = a.dlistf[c];
-                    const uint8_t dc = a.dcls[rd];
-                    if (dc == kClsA) {
-                        pcol = a.dcol[rd];
-                        pfac = r2 * ir2;
-                    } else if (dc == kClsImage) {
-                        pcol = a.dcol[a.dinv[rd]];
-                        pfac = r2 * ir2 * ps;
-                    } else if (a.pal_in) {
-                        pcol = a.dcol[rd];
-                        pfac = r2;
+                const uint64_t off2 = e & 0xFFFFFFFFFFull;
+                if (cl == kClsPal) {   // rare: a palindromic source row holds representatives only
+                    if (!pal_ready) {
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            const uint32_t c = c0 + t;
+                            if (c >= Dd) continue;
+                            const uint32_t rd = a.dlistf[c];
+                            const uint8_t dc = a.dcls[rd];
+                            if (dc == kClsA) {
+                                pcol[t] = a.dcol[rd];
+                                pfac[t] = r2 * ir2;
+                            } else if (dc == kClsImage) {
+                                pcol[t] = a.dcol[a.dinv[rd]];
+                                pfac[t] = r2 * ir2 * ps;
+                            } else if (a.pal_in) {
+                                pcol[t] = a.dcol[rd];
+                                pfac[t] = r2;
+                            }
+                        }
+                        pal_ready = true;
                     }
-                    pal_ready = true;
-                }
-                const uint32_t col = cl == kClsA ? c : (cl == kClsImage ? cm : pcol);
-                const T fac = cl == kClsA ? r2 * ir2 : (cl == kClsImage ? r2 * ir2 * ps : pfac);
-                if (fac != (T)0) {
-                    v[jj] = x[(e & 0xFFFFFFFFFFull) + col];
-                    f[jj] = fac * cf;
+                    if (pfac[0] != (T)0) { v0[jj] = x[off2 + pcol[0]]; f0[jj] = pfac[0] * cf; }
+                    if (live1 && pfac[1] != (T)0) { v1[jj] = x[off2 + pcol[1]]; f1[jj] = pfac[1] * cf; }
+                } else {
+                    const T fac = cl == kClsA ? r2 * ir2 : r2 * ir2 * ps;
+                    T a0, a1;
+                    if (vec_ok && pair && (off2 & 1u) == 0u) {   // x + off2 + c0 is 2-element aligned
+                        const V2 w = *reinterpret_cast<const V2*>(x + off2 + c0);
+                        a0 = w.x;
+                        a1 = w.y;
+                    } else {
+                        a0 = x[off2 + c0];
+                        a1 = live1 ? x[off2 + c0 + 1] : (T)0;
+                    }
+                    if (cl == kClsImage && pair) {   // the mirror of column c0 is c0 + 1 and vice versa
+                        const T t = a0;
+                        a0 = a1;
+                        a1 = t;
+                    }
+                    v0[jj] = a0;
+                    v1[jj] = a1;
+                    f0[jj] = fac * cf;
+                    f1[jj] = live1 ? fac * cf : (T)0;
                 }
             }
         }
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj)
-            if (f[jj] != (T)0) acc += f[jj] * v[jj];
+        for (int jj = 0; jj < 4; ++jj) {
+            if (f0[jj] != (T)0) acc0 += f0[jj] * v0[jj];
+            if (f1[jj] != (T)0) acc1 += f1[jj] * v1[jj];
+        }
     }
-    if (live) y[off + c] += acc;
+    if (live0) y[off + c0] += acc0;
+    if (live1) y[off + c0 + 1] += acc1;
 }
 
 // Full-row down-hop table in column space.
@@ -486,6 +524,7 @@ PArgs pargs(const pdz_problem_s* p) {
     a.fell = q->d_fell;
     a.fup = q->d_fup;
     a.fup_stride = q->fup_stride;
+    a.npair2 = q->npair2;
     a.row_rank = q->d_row_rank;
     a.row_off = q->d_row_off;
     a.row_pal = q->d_row_pal;
@@ -532,12 +571,14 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
         const size_t lds = (size_t)a.Ddn * sizeof(T);
         if (!q->force_gather && lds <= kPRowLds && q->d_fup && q->fup_stride <= kPCw) {
             hipLaunchKernelGGL(k_hvp_down<T>, dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y, skip);
-            const uint64_t nslab = (a.Ddn + kPCw - 1) / kPCw;
+            const uint64_t nslab = (a.Ddn + 2 * kPCw - 1) / (2 * kPCw);
             const uint64_t pairs = (q->n_full + kPUpRows - 1) / kPUpRows;
             const uint64_t per_xcd = (nslab + 7) / 8;
             const uint64_t g = 8 * per_xcd * pairs;
             if (g >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
-            hipLaunchKernelGGL(k_hvp_up<T>, dim3((unsigned)g), dim3(kPUpRows * kPCw), 0, s, a, coef, x, y, skip, nslab);
+            const int vec_ok = reinterpret_cast<uintptr_t>(x) % (2 * sizeof(T)) == 0;
+            hipLaunchKernelGGL(k_hvp_up<T>, dim3((unsigned)g), dim3(kPUpRows * kPCw), 0, s, a, coef, x, y, skip, nslab,
+                               vec_ok);
         } else
             hipLaunchKernelGGL(k_hvp_full<T>, dim3(grid), dim3(kPBlock), 0, s, a, coef, x, y, skip);
     }
@@ -647,9 +688,13 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
     std::vector<uint32_t> dlistf, dcolf(Dd, kNoCol), fmir(Dd);
     for (uint64_t k = 0; k < dreps; ++k) {   // each representative, then its mirror
         const uint32_t r = dby_tree[k];
+        if (dcls[r] != kClsA) continue;
         dlistf.push_back(r);
-        if (dcls[r] == kClsA) dlistf.push_back(dinv[r]);
+        dlistf.push_back(dinv[r]);
     }
+    q->npair2 = dlistf.size();                 // the pairs fill the even-aligned head of a full row
+    for (uint64_t k = 0; k < dreps; ++k)       // then the palindromes
+        if (dcls[dby_tree[k]] == kClsPal) dlistf.push_back(dby_tree[k]);
     if (dlistf.size() != Dd) return fail(PDZ_EDEVICE, "mirror pairs do not cover the down sector");
     for (uint64_t c = 0; c < Dd; ++c) {
         if (dcolf[dlistf[c]] != kNoCol) return fail(PDZ_EDEVICE, "a down string appears twice in a full row");

@@ -110,13 +110,11 @@ def test_full_rows_hold_every_down_string_in_mirror_pairs():
     for N, n in ((8, 4), (9, 4), (6, 3)):
         order = inv.full_row_order(N, n)
         assert sorted(order) == [int(s) for s in sector_list(N, n)]
-        k = 0
-        while k < len(order):
-            if inv.classify(order[k], N)[0] == "P":
-                k += 1
-            else:
-                assert inv.classify(order[k], N)[0] == "A" and order[k + 1] == inv.reverse(order[k], N)
-                k += 2
+        npal = sum(1 for r in order if inv.classify(r, N)[0] == "P")
+        head = len(order) - npal
+        assert head % 2 == 0 and all(inv.classify(r, N)[0] == "P" for r in order[head:])
+        for k in range(0, head, 2):   # pairs at even columns: representative, then its mirror
+            assert inv.classify(order[k], N)[0] == "A" and order[k + 1] == inv.reverse(order[k], N)
 
 
 def test_row_index_matches_the_basis_order():

@@ -270,8 +270,8 @@ constexpr int kPLdsBlock = 1024;
 constexpr size_t kPRowLds = 150 * 1024;
 
 // Two-pass form for full rows.  Down pass: the row staged in LDS, diagonal and
-// down hops, y written.  Up pass: work groups over (row, slab of 2 kPCw
-// columns), four rows per group; slabs are dealt out XCD by XCD (work group b
+// down hops, y written.  Up pass: work groups over (row, slab of kPCw threads
+// x up_cols columns), four rows per group; slabs are dealt out XCD by XCD (work group b
 // runs on XCD b mod 8) and each XCD walks its slabs one at a time over every
 // row, so the slab (all rows at those columns) stays in that XCD's L2 while 34
 // rows read it.  Each row's up hops come from one precomputed 64-bit entry
@@ -317,16 +317,22 @@ template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 
-// Each thread takes two columns c0 = 2i, c0 + 1.  In the head of the row they
-// are a mirror pair: one 8- or 16-byte load of the source row at c0 serves both
-// (swapped for an image source) when the source row starts at an even index;
-// otherwise, and in the palindrome tail, two scalar loads.
+// Columns per thread: two mirror pairs in FP32 (one 16-byte load), one pair in FP64.
+template <typename T> constexpr int up_cols() { return sizeof(T) == 4 ? 4 : 2; }
+
+// Each thread takes up_cols consecutive columns starting at a multiple of
+// up_cols.  When they all lie in the head of the row (mirror pairs) and the
+// source row start is even, vector loads of the source row serve all of them,
+// pairs swapped for an image source; otherwise (the palindrome tail, the group
+// that straddles it, odd row starts) scalar loads with the mirror column from
+// the table.
 template <typename T>
 __global__ __launch_bounds__(kPUpRows * kPCw) void k_hvp_up(const PArgs a, const T* __restrict__ coef,
                                                              const T* __restrict__ x, T* __restrict__ y,
                                                              const int* skip, uint64_t nslab, int vec_ok) {
     if (skip && *skip) return;
     using V2 = typename Vec2<T>::type;
+    constexpr int CPT = up_cols<T>();
     const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
     const uint64_t groups = (a.nlist + kPUpRows - 1) / kPUpRows;   // work groups per slab
     const uint64_t per_xcd = (nslab + 7) / 8;                        // slabs per XCD
@@ -336,37 +342,46 @@ __global__ __launch_bounds__(kPUpRows * kPCw) void k_hvp_up(const PArgs a, const
     const uint64_t kk = (j % groups) * kPUpRows + threadIdx.x / kPCw;   // one row per wave
     if (kk >= a.nlist) return;                                       // whole wave
     const uint32_t Dd = (uint32_t)a.Ddn;
-    const uint32_t c0 = (uint32_t)(slab * (2 * kPCw) + 2 * (threadIdx.x % kPCw));
-    const bool live0 = c0 < Dd, live1 = c0 + 1 < Dd;                 // lanes past the row's end only help load
-    const bool pair = c0 + 1 < (uint32_t)a.npair2;                   // c0, c0 + 1 are mirror images
+    const uint32_t c0 = (uint32_t)(slab * (CPT * kPCw) + CPT * (threadIdx.x % kPCw));
+    bool live[CPT];
+#pragma unroll
+    for (int t = 0; t < CPT; ++t) live[t] = c0 + t < Dd;             // lanes past the row's end only help load
+    const bool pair = c0 + CPT - 1 < (uint32_t)a.npair2;             // all CPT columns are mirror pairs
     const uint64_t k = a.rows[kk];
     const uint64_t off = a.row_off[k];
     const int lane = threadIdx.x % kPCw;
     const uint64_t my_e = lane < a.fup_stride ? a.fup[kk * a.fup_stride + lane] : kFupNone;
     const T my_cf = my_e != kFupNone ? coef[(my_e >> 48) & 0xFFu] : (T)0;
     const int nh = __popcll(__ballot(my_e != kFupNone));
-    uint32_t pcol[2] = {0u, 0u};
-    T pfac[2] = {(T)0, (T)0};
+    uint32_t pcol[CPT];
+    T pfac[CPT];
+#pragma unroll
+    for (int t = 0; t < CPT; ++t) {
+        pcol[t] = 0u;
+        pfac[t] = (T)0;
+    }
     bool pal_ready = false;
-    T acc0 = (T)0, acc1 = (T)0;
+    T acc[CPT];
+#pragma unroll
+    for (int t = 0; t < CPT; ++t) acc[t] = (T)0;
     for (int h0 = 0; h0 < nh; h0 += 4) {
-        T v0[4], v1[4], f0[4], f1[4];
+        T v[4][CPT], f[4][CPT];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const int h = h0 + jj < nh ? h0 + jj : 0;
             const uint64_t e = __shfl(my_e, h, kPCw);
             const T cf = __shfl(my_cf, h, kPCw);
-            v0[jj] = v1[jj] = f0[jj] = f1[jj] = (T)0;
-            if (h0 + jj < nh && live0) {
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) v[jj][t] = f[jj][t] = (T)0;
+            if (h0 + jj < nh && live[0]) {
                 const uint8_t cl = (uint8_t)((e >> 40) & 3u);
                 const uint64_t off2 = e & 0xFFFFFFFFFFull;
                 if (cl == kClsPal) {   // rare: a palindromic source row holds representatives only
                     if (!pal_ready) {
 #pragma unroll
-                        for (int t = 0; t < 2; ++t) {
-                            const uint32_t c = c0 + t;
-                            if (c >= Dd) continue;
-                            const uint32_t rd = a.dlistf[c];
+                        for (int t = 0; t < CPT; ++t) {
+                            if (!live[t]) continue;
+                            const uint32_t rd = a.dlistf[c0 + t];
                             const uint8_t dc = a.dcls[rd];
                             if (dc == kClsA) {
                                 pcol[t] = a.dcol[rd];
@@ -381,39 +396,59 @@ __global__ __launch_bounds__(kPUpRows * kPCw) void k_hvp_up(const PArgs a, const
                         }
                         pal_ready = true;
                     }
-                    if (pfac[0] != (T)0) { v0[jj] = x[off2 + pcol[0]]; f0[jj] = pfac[0] * cf; }
-                    if (live1 && pfac[1] != (T)0) { v1[jj] = x[off2 + pcol[1]]; f1[jj] = pfac[1] * cf; }
+#pragma unroll
+                    for (int t = 0; t < CPT; ++t)
+                        if (live[t] && pfac[t] != (T)0) {
+                            v[jj][t] = x[off2 + pcol[t]];
+                            f[jj][t] = pfac[t] * cf;
+                        }
                 } else {
                     const T fac = cl == kClsA ? r2 * ir2 : r2 * ir2 * ps;
-                    T a0, a1;
-                    if (vec_ok && pair && (off2 & 1u) == 0u) {   // x + off2 + c0 is 2-element aligned
-                        const V2 w = *reinterpret_cast<const V2*>(x + off2 + c0);
-                        a0 = w.x;
-                        a1 = w.y;
-                    } else {
-                        a0 = x[off2 + c0];
-                        a1 = live1 ? x[off2 + c0 + 1] : (T)0;
+                    const T* src = x + off2 + c0;
+                    bool vec = vec_ok && pair && (off2 & 1u) == 0u;   // pair-aligned vector loads
+                    if (vec) {
+                        T w[CPT];
+                        bool done = false;
+                        if constexpr (CPT == 4) {
+                            if (((off2 + c0) & 3u) == 0u) {            // 16-byte aligned: one load
+                                const float4 q4 = *reinterpret_cast<const float4*>(src);
+                                w[0] = q4.x;
+                                w[1] = q4.y;
+                                w[2] = q4.z;
+                                w[3] = q4.w;
+                                done = true;
+                            }
+                        }
+                        if (!done) {
+#pragma unroll
+                            for (int t = 0; t < CPT; t += 2) {
+                                const V2 q2 = *reinterpret_cast<const V2*>(src + t);
+                                w[t] = q2.x;
+                                w[t + 1] = q2.y;
+                            }
+                        }
+#pragma unroll
+                        for (int t = 0; t < CPT; ++t)   // an image source reads the other member of the pair
+                            v[jj][t] = cl == kClsImage ? w[t ^ 1] : w[t];
+                    } else {   // scalar loads; the mirror column from the table (pairs and palindromes alike)
+#pragma unroll
+                        for (int t = 0; t < CPT; ++t)
+                            if (live[t]) v[jj][t] = x[off2 + (cl == kClsImage ? a.fmir[c0 + t] : c0 + t)];
                     }
-                    if (cl == kClsImage && pair) {   // the mirror of column c0 is c0 + 1 and vice versa
-                        const T t = a0;
-                        a0 = a1;
-                        a1 = t;
-                    }
-                    v0[jj] = a0;
-                    v1[jj] = a1;
-                    f0[jj] = fac * cf;
-                    f1[jj] = live1 ? fac * cf : (T)0;
+#pragma unroll
+                    for (int t = 0; t < CPT; ++t) f[jj][t] = live[t] ? fac * cf : (T)0;
                 }
             }
         }
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            if (f0[jj] != (T)0) acc0 += f0[jj] * v0[jj];
-            if (f1[jj] != (T)0) acc1 += f1[jj] * v1[jj];
-        }
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+            for (int t = 0; t < CPT; ++t)
+                if (f[jj][t] != (T)0) acc[t] += f[jj][t] * v[jj][t];
     }
-    if (live0) y[off + c0] += acc0;
-    if (live1) y[off + c0 + 1] += acc1;
+#pragma unroll
+    for (int t = 0; t < CPT; ++t)
+        if (live[t]) y[off + c0 + t] += acc[t];
 }
 
 // Full-row down-hop table in column space.
@@ -571,12 +606,13 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
         const size_t lds = (size_t)a.Ddn * sizeof(T);
         if (!q->force_gather && lds <= kPRowLds && q->d_fup && q->fup_stride <= kPCw) {
             hipLaunchKernelGGL(k_hvp_down<T>, dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y, skip);
-            const uint64_t nslab = (a.Ddn + 2 * kPCw - 1) / (2 * kPCw);
+            const uint64_t span = (uint64_t)up_cols<T>() * kPCw;   // columns of a slab
+            const uint64_t nslab = (a.Ddn + span - 1) / span;
             const uint64_t pairs = (q->n_full + kPUpRows - 1) / kPUpRows;
             const uint64_t per_xcd = (nslab + 7) / 8;
             const uint64_t g = 8 * per_xcd * pairs;
             if (g >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
-            const int vec_ok = reinterpret_cast<uintptr_t>(x) % (2 * sizeof(T)) == 0;
+            const int vec_ok = reinterpret_cast<uintptr_t>(x) % (up_cols<T>() * sizeof(T)) == 0;
             hipLaunchKernelGGL(k_hvp_up<T>, dim3((unsigned)g), dim3(kPUpRows * kPCw), 0, s, a, coef, x, y, skip, nslab,
                                vec_ok);
         } else

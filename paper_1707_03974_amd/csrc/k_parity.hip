@@ -66,6 +66,7 @@ struct ParSpace {
     int fup_stride = 0;
     uint64_t npair2 = 0;           // columns of a full row taken by mirror pairs (the rest: palindromes)
     bool force_gather = false;     // PDZ_PARITY_GATHER=1: full rows by the one-pass gather kernel (its test)
+    int up_lpr = 64;               // up pass lanes per row (slab width / up_cols); PDZ_PARITY_UP_LANES = 16, 32, 64
     uint32_t* d_row_rank = nullptr;   // nrows: up rank of each row
     uint64_t* d_row_off = nullptr;    // nrows + 1
     uint8_t* d_row_pal = nullptr;     // nrows
@@ -270,14 +271,16 @@ constexpr int kPLdsBlock = 1024;
 constexpr size_t kPRowLds = 150 * 1024;
 
 // Two-pass form for full rows.  Down pass: the row staged in LDS, diagonal and
-// down hops, y written.  Up pass: work groups over (row, slab of kPCw threads
-// x up_cols columns), four rows per group; slabs are dealt out XCD by XCD (work group b
-// runs on XCD b mod 8) and each XCD walks its slabs one at a time over every
-// row, so the slab (all rows at those columns) stays in that XCD's L2 while 34
-// rows read it.  Each row's up hops come from one precomputed 64-bit entry
-// (source row start, class, amplitude): no dependent lookups.
-constexpr int kPCw = 64;
-constexpr int kPUpRows = 4;
+// down hops, y written.  Up pass: work groups of kPUpBlock threads over (rows,
+// slab of LPR lanes x up_cols columns); slabs are dealt out XCD by XCD (work
+// group b runs on XCD b mod 8) and each XCD walks its slabs one at a time over
+// every row, so the slab (all rows at those columns) stays in that XCD's L2
+// while 34 rows read it.  Each row's up hops come from one precomputed 64-bit
+// entry (source row start, class, amplitude), palindromic sources last;
+// a work group decodes its rows' entries into LDS once.
+constexpr int kPUpBlock = 256;
+constexpr int kPUpNB = 8;   // hop loads in flight per lane
+constexpr int kPFupMax = 64;   // up hops per row the two-pass form takes
 constexpr uint64_t kFupNone = ~0ull;
 
 template <typename T>
@@ -320,135 +323,158 @@ template <> struct Vec2<double> { using type = double2; };
 // Columns per thread: two mirror pairs in FP32 (one 16-byte load), one pair in FP64.
 template <typename T> constexpr int up_cols() { return sizeof(T) == 4 ? 4 : 2; }
 
-// Each thread takes up_cols consecutive columns starting at a multiple of
-// up_cols.  When they all lie in the head of the row (mirror pairs) and the
-// source row start is even, vector loads of the source row serve all of them,
-// pairs swapped for an image source; otherwise (the palindrome tail, the group
-// that straddles it, odd row starts) scalar loads with the mirror column from
-// the table.
-template <typename T>
-__global__ __launch_bounds__(kPUpRows * kPCw) void k_hvp_up(const PArgs a, const T* __restrict__ coef,
-                                                             const T* __restrict__ x, T* __restrict__ y,
-                                                             const int* skip, uint64_t nslab, int vec_ok) {
+// Each lane takes up_cols consecutive columns starting at a multiple of
+// up_cols.  When they all lie in the head of the row (mirror pairs), the
+// source's columns are read as one block and an image source swaps each pair; lanes on the palindrome tail
+// (or straddling it) read single columns with the mirror column from the
+// table.  Hops from palindromic source rows (listed last) read the columns of
+// the representatives.
+template <typename T, int LPR>
+__global__ __launch_bounds__(kPUpBlock) void k_hvp_up(const PArgs a, const T* __restrict__ coef,
+                                                      const T* __restrict__ x, T* __restrict__ y, const int* skip,
+                                                      uint64_t nslab, int vec_ok) {
     if (skip && *skip) return;
     using V2 = typename Vec2<T>::type;
     constexpr int CPT = up_cols<T>();
+    constexpr int ROWS = kPUpBlock / LPR;
+    static_assert(kPUpBlock % LPR == 0 && LPR <= 64, "lanes per row");
+    extern __shared__ __align__(16) unsigned char pup[];
+    const int stride = a.fup_stride;
+    uint64_t* s_e = reinterpret_cast<uint64_t*>(pup);   // ROWS x stride entries
+    T* s_f = reinterpret_cast<T*>(s_e + ROWS * stride);   // their factors
+    __shared__ int s_n[ROWS], s_nh[ROWS];                 // hops from A / image sources, all hops
     const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
-    const uint64_t groups = (a.nlist + kPUpRows - 1) / kPUpRows;   // work groups per slab
-    const uint64_t per_xcd = (nslab + 7) / 8;                        // slabs per XCD
+    const uint64_t groups = (a.nlist + ROWS - 1) / ROWS;   // work groups per slab
+    const uint64_t per_xcd = (nslab + 7) / 8;              // slabs per XCD
     const uint64_t xcd = blockIdx.x % 8, j = blockIdx.x / 8;
-    const uint64_t slab = (j / groups) * 8 + xcd;                   // slab-major within the XCD
-    if (j / groups >= per_xcd || slab >= nslab) return;
-    const uint64_t kk = (j % groups) * kPUpRows + threadIdx.x / kPCw;   // one row per wave
-    if (kk >= a.nlist) return;                                       // whole wave
-    const uint32_t Dd = (uint32_t)a.Ddn;
-    const uint32_t c0 = (uint32_t)(slab * (CPT * kPCw) + CPT * (threadIdx.x % kPCw));
-    bool live[CPT];
-#pragma unroll
-    for (int t = 0; t < CPT; ++t) live[t] = c0 + t < Dd;             // lanes past the row's end only help load
-    const bool pair = c0 + CPT - 1 < (uint32_t)a.npair2;             // all CPT columns are mirror pairs
-    const uint64_t k = a.rows[kk];
-    const uint64_t off = a.row_off[k];
-    const int lane = threadIdx.x % kPCw;
-    const uint64_t my_e = lane < a.fup_stride ? a.fup[kk * a.fup_stride + lane] : kFupNone;
-    const T my_cf = my_e != kFupNone ? coef[(my_e >> 48) & 0xFFu] : (T)0;
-    const int nh = __popcll(__ballot(my_e != kFupNone));
-    uint32_t pcol[CPT];
-    T pfac[CPT];
-#pragma unroll
-    for (int t = 0; t < CPT; ++t) {
-        pcol[t] = 0u;
-        pfac[t] = (T)0;
+    const uint64_t slab = (j / groups) * 8 + xcd;          // slab-major within the XCD
+    if (j / groups >= per_xcd || slab >= nslab) return;    // whole work group
+    const uint64_t kk0 = (j % groups) * ROWS;
+    if (threadIdx.x < ROWS) s_n[threadIdx.x] = s_nh[threadIdx.x] = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < ROWS * stride; t += kPUpBlock) {
+        const int r = t / stride, h = t - r * stride;
+        const uint64_t e = kk0 + r < a.nlist ? a.fup[(kk0 + r) * stride + h] : kFupNone;
+        T f = (T)0;
+        if (e != kFupNone) {
+            const uint8_t cl = (uint8_t)((e >> 40) & 3u);
+            const T cf = coef[(e >> 48) & 0xFFu];
+            f = cl == kClsPal ? cf : (cl == kClsA ? r2 * ir2 : r2 * ir2 * ps) * cf;
+            atomicMax(&s_nh[r], h + 1);
+            if (cl != kClsPal) atomicMax(&s_n[r], h + 1);
+        }
+        s_e[t] = e;
+        s_f[t] = f;
     }
-    bool pal_ready = false;
+    __syncthreads();
+    const int r = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+    const uint64_t kk = kk0 + r;
+    const uint32_t Dd = (uint32_t)a.Ddn;
+    const uint32_t c0 = (uint32_t)(slab * (CPT * LPR) + CPT * lane);
+    if (kk >= a.nlist || c0 >= Dd) return;   // no barrier follows
+    const int nv = c0 + CPT <= Dd ? CPT : (int)(Dd - c0);
+    const bool pair = c0 + CPT <= (uint32_t)a.npair2;   // all CPT columns are mirror pairs
+    const uint64_t off = a.row_off[a.rows[kk]];
+    const uint64_t* er = s_e + r * stride;
+    const T* fr = s_f + r * stride;
+    const int n_np = s_n[r], nh = s_nh[r];
     T acc[CPT];
 #pragma unroll
     for (int t = 0; t < CPT; ++t) acc[t] = (T)0;
-    for (int h0 = 0; h0 < nh; h0 += 4) {
-        T v[4][CPT], f[4][CPT];
+    if (pair) {
+        // an image source contributes the other member of each pair: its
+        // products go to accI, whose columns are swapped once at the end
+        T accI[CPT];
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int h = h0 + jj < nh ? h0 + jj : 0;
-            const uint64_t e = __shfl(my_e, h, kPCw);
-            const T cf = __shfl(my_cf, h, kPCw);
+        for (int t = 0; t < CPT; ++t) accI[t] = (T)0;
+        for (int h = 0; h < n_np; h += kPUpNB) {
+            T v[kPUpNB][CPT], fa[kPUpNB], fi[kPUpNB];
+            uint64_t e[kPUpNB];
 #pragma unroll
-            for (int t = 0; t < CPT; ++t) v[jj][t] = f[jj][t] = (T)0;
-            if (h0 + jj < nh && live[0]) {
-                const uint8_t cl = (uint8_t)((e >> 40) & 3u);
-                const uint64_t off2 = e & 0xFFFFFFFFFFull;
-                if (cl == kClsPal) {   // rare: a palindromic source row holds representatives only
-                    if (!pal_ready) {
-#pragma unroll
-                        for (int t = 0; t < CPT; ++t) {
-                            if (!live[t]) continue;
-                            const uint32_t rd = a.dlistf[c0 + t];
-                            const uint8_t dc = a.dcls[rd];
-                            if (dc == kClsA) {
-                                pcol[t] = a.dcol[rd];
-                                pfac[t] = r2 * ir2;
-                            } else if (dc == kClsImage) {
-                                pcol[t] = a.dcol[a.dinv[rd]];
-                                pfac[t] = r2 * ir2 * ps;
-                            } else if (a.pal_in) {
-                                pcol[t] = a.dcol[rd];
-                                pfac[t] = r2;
-                            }
-                        }
-                        pal_ready = true;
-                    }
-#pragma unroll
-                    for (int t = 0; t < CPT; ++t)
-                        if (live[t] && pfac[t] != (T)0) {
-                            v[jj][t] = x[off2 + pcol[t]];
-                            f[jj][t] = pfac[t] * cf;
-                        }
-                } else {
-                    const T fac = cl == kClsA ? r2 * ir2 : r2 * ir2 * ps;
-                    const T* src = x + off2 + c0;
-                    bool vec = vec_ok && pair && (off2 & 1u) == 0u;   // pair-aligned vector loads
-                    if (vec) {
-                        T w[CPT];
-                        bool done = false;
-                        if constexpr (CPT == 4) {
-                            if (((off2 + c0) & 3u) == 0u) {            // 16-byte aligned: one load
-                                const float4 q4 = *reinterpret_cast<const float4*>(src);
-                                w[0] = q4.x;
-                                w[1] = q4.y;
-                                w[2] = q4.z;
-                                w[3] = q4.w;
-                                done = true;
-                            }
-                        }
-                        if (!done) {
-#pragma unroll
-                            for (int t = 0; t < CPT; t += 2) {
-                                const V2 q2 = *reinterpret_cast<const V2*>(src + t);
-                                w[t] = q2.x;
-                                w[t + 1] = q2.y;
-                            }
-                        }
-#pragma unroll
-                        for (int t = 0; t < CPT; ++t)   // an image source reads the other member of the pair
-                            v[jj][t] = cl == kClsImage ? w[t ^ 1] : w[t];
-                    } else {   // scalar loads; the mirror column from the table (pairs and palindromes alike)
-#pragma unroll
-                        for (int t = 0; t < CPT; ++t)
-                            if (live[t]) v[jj][t] = x[off2 + (cl == kClsImage ? a.fmir[c0 + t] : c0 + t)];
-                    }
-#pragma unroll
-                    for (int t = 0; t < CPT; ++t) f[jj][t] = live[t] ? fac * cf : (T)0;
-                }
+            for (int q = 0; q < kPUpNB; ++q) {   // the batch's entries first, then its loads
+                const int hq = h + q < n_np ? h + q : h;   // slots past the count reload hop h, factor 0
+                e[q] = er[hq];
+                const T f = h + q < n_np ? fr[hq] : (T)0;
+                const bool img = ((e[q] >> 40) & 3u) == kClsImage;
+                fa[q] = img ? (T)0 : f;
+                fi[q] = img ? f : (T)0;
             }
+#pragma unroll
+            for (int q = 0; q < kPUpNB; ++q) {
+                const T* src = x + (e[q] & 0xFFFFFFFFFFull) + c0;   // one wide load (any alignment)
+#pragma unroll
+                for (int t = 0; t < CPT; ++t) v[q][t] = src[t];
+            }
+#pragma unroll
+            for (int q = 0; q < kPUpNB; ++q)
+#pragma unroll
+                for (int t = 0; t < CPT; ++t) {
+                    acc[t] += fa[q] * v[q][t];
+                    accI[t] += fi[q] * v[q][t];
+                }
         }
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
+        for (int t = 0; t < CPT; ++t) acc[t] += accI[t ^ 1];
+    } else {
+        for (int h = 0; h < n_np; ++h) {
+            const uint64_t e = er[h];
+            const T f = fr[h];
+            const uint64_t off2 = e & 0xFFFFFFFFFFull;
+            const bool img = ((e >> 40) & 3u) == kClsImage;
 #pragma unroll
             for (int t = 0; t < CPT; ++t)
-                if (f[jj][t] != (T)0) acc[t] += f[jj][t] * v[jj][t];
+                if (t < nv) acc[t] += f * x[off2 + (img ? a.fmir[c0 + t] : c0 + t)];
+        }
     }
+    if (n_np < nh) {   // rare: a palindromic source row holds representatives only
+        uint32_t pcol[CPT];
+        T pfac[CPT];
 #pragma unroll
-    for (int t = 0; t < CPT; ++t)
-        if (live[t]) y[off + c0 + t] += acc[t];
+        for (int t = 0; t < CPT; ++t) {
+            pcol[t] = 0u;
+            pfac[t] = (T)0;
+            if (t >= nv) continue;
+            const uint32_t rd = a.dlistf[c0 + t];
+            const uint8_t dc = a.dcls[rd];
+            if (dc == kClsA) {
+                pcol[t] = a.dcol[rd];
+                pfac[t] = r2 * ir2;
+            } else if (dc == kClsImage) {
+                pcol[t] = a.dcol[a.dinv[rd]];
+                pfac[t] = r2 * ir2 * ps;
+            } else if (a.pal_in) {
+                pcol[t] = a.dcol[rd];
+                pfac[t] = r2;
+            }
+        }
+        for (int h = n_np; h < nh; ++h) {
+            const uint64_t off2 = er[h] & 0xFFFFFFFFFFull;
+            const T cf = fr[h];
+#pragma unroll
+            for (int t = 0; t < CPT; ++t)
+                if (pfac[t] != (T)0) acc[t] += (pfac[t] * cf) * x[off2 + pcol[t]];
+        }
+    }
+    T* yr = y + off + c0;
+    if (vec_ok && nv == CPT && ((off + c0) % CPT) == 0u) {
+        if constexpr (CPT == 4) {
+            float4 q4 = *reinterpret_cast<const float4*>(yr);
+            q4.x += acc[0];
+            q4.y += acc[1];
+            q4.z += acc[2];
+            q4.w += acc[3];
+            *reinterpret_cast<float4*>(yr) = q4;
+        } else {
+            V2 q2 = *reinterpret_cast<const V2*>(yr);
+            q2.x += acc[0];
+            q2.y += acc[1];
+            *reinterpret_cast<V2*>(yr) = q2;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t)
+            if (t < nv) yr[t] += acc[t];
+    }
 }
 
 // Full-row down-hop table in column space.
@@ -604,17 +630,28 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
         a.nlist = q->n_full;
         const unsigned grid = (unsigned)std::min<uint64_t>(q->n_full, 1ull << 20);
         const size_t lds = (size_t)a.Ddn * sizeof(T);
-        if (!q->force_gather && lds <= kPRowLds && q->d_fup && q->fup_stride <= kPCw) {
+        if (!q->force_gather && lds <= kPRowLds && q->d_fup && q->fup_stride <= kPFupMax) {
             hipLaunchKernelGGL(k_hvp_down<T>, dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y, skip);
-            const uint64_t span = (uint64_t)up_cols<T>() * kPCw;   // columns of a slab
+            const int lpr = q->up_lpr;
+            const uint64_t rows = kPUpBlock / lpr;
+            const uint64_t span = (uint64_t)up_cols<T>() * lpr;   // columns of a slab
             const uint64_t nslab = (a.Ddn + span - 1) / span;
-            const uint64_t pairs = (q->n_full + kPUpRows - 1) / kPUpRows;
+            const uint64_t groups = (q->n_full + rows - 1) / rows;
             const uint64_t per_xcd = (nslab + 7) / 8;
-            const uint64_t g = 8 * per_xcd * pairs;
+            const uint64_t g = 8 * per_xcd * groups;
             if (g >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
-            const int vec_ok = reinterpret_cast<uintptr_t>(x) % (up_cols<T>() * sizeof(T)) == 0;
-            hipLaunchKernelGGL(k_hvp_up<T>, dim3((unsigned)g), dim3(kPUpRows * kPCw), 0, s, a, coef, x, y, skip, nslab,
-                               vec_ok);
+            const size_t ulds = (size_t)rows * q->fup_stride * (sizeof(uint64_t) + sizeof(T));
+            const size_t al = up_cols<T>() * sizeof(T);
+            const int vec_ok = reinterpret_cast<uintptr_t>(x) % al == 0 && reinterpret_cast<uintptr_t>(y) % al == 0;
+            if (lpr == 16)
+                hipLaunchKernelGGL((k_hvp_up<T, 16>), dim3((unsigned)g), dim3(kPUpBlock), ulds, s, a, coef, x, y, skip,
+                                   nslab, vec_ok);
+            else if (lpr == 32)
+                hipLaunchKernelGGL((k_hvp_up<T, 32>), dim3((unsigned)g), dim3(kPUpBlock), ulds, s, a, coef, x, y, skip,
+                                   nslab, vec_ok);
+            else
+                hipLaunchKernelGGL((k_hvp_up<T, 64>), dim3((unsigned)g), dim3(kPUpBlock), ulds, s, a, coef, x, y, skip,
+                                   nslab, vec_ok);
         } else
             hipLaunchKernelGGL(k_hvp_full<T>, dim3(grid), dim3(kPBlock), 0, s, a, coef, x, y, skip);
     }
@@ -654,6 +691,13 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
     {
         const char* env = std::getenv("PDZ_PARITY_GATHER");
         q->force_gather = env && env[0] == '1';
+        const char* lanes = std::getenv("PDZ_PARITY_UP_LANES");
+        if (lanes) {
+            const std::string v(lanes);
+            if (v != "16" && v != "32" && v != "64")
+                return fail(PDZ_EINVAL, "PDZ_PARITY_UP_LANES must be 16, 32 or 64");
+            q->up_lpr = std::stoi(v);
+        }
     }
     q->sigma = (((nu * (nu - 1) / 2) + (nd * (nd - 1) / 2)) % 2) ? -1 : 1;
     const int smax = std::max(nu, nd);
@@ -785,11 +829,15 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
         bool fits = row_off[ureps] < (1ull << 40);
         for (size_t kk = 0; kk < rows_full.size() && fits; ++kk) {
             const uint32_t ru = row_rank[rows_full[kk]];
-            for (int h = 0; h < ucnt_h[ru]; ++h) {
-                const uint32_t e = uell_h[(size_t)h * Du + ru];
-                const uint32_t ru2 = e & kTargetMask;
-                fup[kk * stride + h] = row_off[urow[ru2]] | ((uint64_t)ucls[ru2] << 40) | ((uint64_t)(e >> kTargetBits) << 48);
-            }
+            int h2 = 0;
+            for (int pass = 0; pass < 2; ++pass)   // A and image sources first, palindromic ones last
+                for (int h = 0; h < ucnt_h[ru]; ++h) {
+                    const uint32_t e = uell_h[(size_t)h * Du + ru];
+                    const uint32_t ru2 = e & kTargetMask;
+                    if ((ucls[ru2] == kClsPal) != (pass == 1)) continue;
+                    fup[kk * stride + h2++] =
+                        row_off[urow[ru2]] | ((uint64_t)ucls[ru2] << 40) | ((uint64_t)(e >> kTargetBits) << 48);
+                }
         }
         if (fits) {
             q->fup_stride = stride;

@@ -300,18 +300,31 @@ __global__ __launch_bounds__(kPLdsBlock) void k_hvp_down(const PArgs a, const T*
         __syncthreads();
         for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) R[c] = x[off + c];
         __syncthreads();
-        for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) {
-            T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[a.dlistf[c]])) * R[c];
-            const int ndh = a.fcnt[c];
-            for (int h0 = 0; h0 < ndh; h0 += 8) {   // eight table entries in flight, then their LDS reads
-                uint32_t e[8];
+        // each column: its down string and hop count (prefetched one column
+        // ahead), then its table entries NB at a time, then their LDS reads.
+        // NB = 16 in FP64, whose row takes the whole LDS budget (one work group
+        // per CU); in FP32 two work groups share a CU, which needs the 8 waves
+        // per SIMD that NB = 8 keeps.
+        constexpr int NB = sizeof(T) == 8 ? 16 : 8;
+        uint32_t c = threadIdx.x;
+        uint32_t phd = c < Dd ? a.dn_states[a.dlistf[c]] : 0u;
+        int ndh = c < Dd ? a.fcnt[c] : 0;
+        for (; c < Dd; c += kPLdsBlock) {
+            const uint32_t cn = c + kPLdsBlock;
+            const uint32_t phd_n = cn < Dd ? a.dn_states[a.dlistf[cn]] : 0u;
+            const int ndh_n = cn < Dd ? a.fcnt[cn] : 0;
+            T acc = (T)(a.U * __builtin_popcount(phu & phd)) * R[c];
+            for (int h0 = 0; h0 < ndh; h0 += NB) {
+                uint32_t e[NB];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) e[j] = h0 + j < ndh ? a.fell[(uint64_t)(h0 + j) * Dd + c] : 0u;
+                for (int j = 0; j < NB; ++j) e[j] = h0 + j < ndh ? a.fell[(uint64_t)(h0 + j) * Dd + c] : 0u;
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
+                for (int j = 0; j < NB; ++j)
                     if (h0 + j < ndh) acc += s_coef[e[j] >> kTargetBits] * R[e[j] & kTargetMask];
             }
             y[off + c] = acc;
+            phd = phd_n;
+            ndh = ndh_n;
         }
     }
 }

@@ -372,12 +372,17 @@ pdz_status pdz_kspace_info(pdz_problem p, int32_t* L1, int32_t* L2, int32_t* K, 
  * and palindromes; tree index = the tree's forward map with the counts
  * S_i^m = C_{i-2}^{m-1} + S_{i-2}^m + S_{i-2}^{m-2}): rows are the up
  * representatives in tree order; a row of a non-palindromic up string holds
- * every down string in ascending order, a row of a palindromic one the down
+ * every down string in mirror pairs (each down representative in tree order
+ * followed by its mirror image, pairs at even columns) and then the down
+ * palindromes in tree order; a row of a palindromic one holds the down
  * representatives in tree order (down palindromes only when sigma = parity).
  * Basis vectors: (|r> + parity F|r>)/sqrt(2), or |r> when F|r> = parity |r>.
  * The handle works with pdz_problem_info, pdz_hv, pdz_lanczos* and
  * pdz_problem_destroy (no launch plans, batches or fermion operators).
- * Synchronous.  Errors: as pdz_problem_create; PDZ_EINVAL (parity not +-1,
+ * Read at creation: PDZ_PARITY_UP_LANES = 16, 32 or 64 (default) lanes per
+ * row in the up pass of H.v (its column slab is that times 4 in FP32, 2 in
+ * FP64; any other value fails with PDZ_EINVAL); PDZ_PARITY_GATHER=1 serves
+ * the non-palindromic rows with the one-pass kernel.  Synchronous.  Errors: as pdz_problem_create; PDZ_EINVAL (parity not +-1,
  * bonds not mirror symmetric); PDZ_ERANGE (sectors too large for the hop
  * tables, empty subspace); PDZ_EDEVICE (a tree map failed its bijection
  * check: a library fault). */

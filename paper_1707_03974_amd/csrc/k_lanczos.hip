@@ -560,8 +560,10 @@ Layout make_layout(const pdz_problem_s* p, const pdz_lanczos_opts* o) {
     L.sc = off;
     off += align256(m * 8);
     L.partial = off;
-    off += align256(std::max<size_t>(std::max<size_t>((size_t)kRedGrid * (o->reorth ? m : 1), kMaxPartials),
-                                     hv_dot_count_max(p, (pdz_dtype)o->storage)) *
+    off += align256(std::max<size_t>(std::max<size_t>(std::max<size_t>((size_t)kRedGrid * (o->reorth ? m : 1),
+                                                                          kMaxPartials),
+                                                      hv_dot_count_max(p, (pdz_dtype)o->storage)),
+                                     (size_t)parity_dot_count(p, (pdz_dtype)o->storage)) *
                     8);
     L.partial2 = off;
     off += align256((size_t)kRedGrid * 8);
@@ -660,12 +662,14 @@ struct Run {
 
     // Split H.v layout of this run: partial-sum counts of its two passes
     // (ndn = 0: the on-the-fly path, which takes a separate dot kernel).
+    // nwhole: partial sums of q . H q that the whole (unsplit) H.v writes (parity).
     struct SplitCounts {
-        int ndn = 0, nup = 0;
+        int ndn = 0, nup = 0, nwhole = 0;
     };
     SplitCounts split_counts() const {
         SplitCounts c;
         if (!hv_dot_counts(p, (pdz_dtype)o->storage, &c.ndn, &c.nup)) c.ndn = c.nup = 0;
+        c.nwhole = parity_dot_count(p, (pdz_dtype)o->storage);
         return c;
     }
 
@@ -691,6 +695,17 @@ struct Run {
             hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn,
                                (uint64_t)c.nup, partial2(), done());
             hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), c.ndn, partial2(),
+                               (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
+        } else if (c.nwhole > 0) {   // the H.v writes partial sums of q . H q
+            HvSplit sw;
+            sw.dotp_up = partial();
+            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sw);
+            if (st != PDZ_OK) return st;
+            mark(1);
+            mark(2);
+            hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial(), (uint64_t)c.nwhole,
+                               partial2(), done());
+            hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), 0, partial2(),
                                (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
         } else {
             pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done());

@@ -167,15 +167,31 @@ struct PArgs {
     int pal_in;     // self-mapped states belong to this parity (sigma == P)
 };
 
+// *out = sum of v over a work group of kPBlock threads, in a fixed order
+// (every thread of the group calls it).
+__device__ __forceinline__ void block_sum_store(double v, double* out) {
+    __shared__ double red[kPBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kPBlock / 64; ++w) t += red[w];
+        *out = t;
+    }
+}
+
 // Rows of palindromic up strings (few): one work group per row, threads over
 // its columns (down representatives).
+// With dotp set, work group b writes dotp[b] = its elements' sum of x y.
 template <typename T>
 __global__ __launch_bounds__(kPBlock) void k_hvp(const PArgs a, const T* __restrict__ coef, const T* __restrict__ x,
-                                                  T* __restrict__ y, const int* skip) {
+                                                  T* __restrict__ y, const int* skip, double* dotp) {
     if (skip && *skip) return;
     const T r2 = (T)1.4142135623730950488, ir2 = (T)0.70710678118654752440, ps = (T)a.ps;
     // work group b: row b / chunks, columns (b % chunks) * kPBlock + thread
     const uint64_t chunks = (a.Lp + kPBlock - 1) / kPBlock;
+    double dsum = 0.0;
     for (uint64_t b = blockIdx.x; b < a.nlist * chunks; b += gridDim.x) {
         const uint64_t k = a.rows[b / chunks];
         const uint32_t ru = a.row_rank[k];
@@ -187,7 +203,8 @@ __global__ __launch_bounds__(kPBlock) void k_hvp(const PArgs a, const T* __restr
         if (c < len) {
             const uint32_t rd = a.dlist[c];
             const T wt = a.dcls[rd] == kClsPal ? (T)1 : r2;
-            T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[rd])) * x[off + c];
+            const T xc = x[off + c];
+            T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[rd])) * xc;
             const int ndh = a.dn_cnt[rd];
             for (int h = 0; h < ndh; ++h) {   // the up string stays: a column of this row
                 const uint32_t e = a.dn_ell[(uint64_t)h * a.Ddn + rd];
@@ -212,8 +229,10 @@ __global__ __launch_bounds__(kPBlock) void k_hvp(const PArgs a, const T* __restr
                     acc += wt * ir2 * ps * cf * x[off2 + a.dcolf[a.dinv[rd]]];
             }
             y[off + c] = acc;
+            dsum += (double)xc * (double)acc;
         }
     }
+    if (dotp) block_sum_store(dsum, dotp + blockIdx.x);
 }
 
 // Rows of non-palindromic up strings in one pass, for rows too long for the
@@ -345,12 +364,13 @@ template <typename T> constexpr int up_cols() { return sizeof(T) == 4 ? 4 : 2; }
 template <typename T, int LPR>
 __global__ __launch_bounds__(kPUpBlock) void k_hvp_up(const PArgs a, const T* __restrict__ coef,
                                                       const T* __restrict__ x, T* __restrict__ y, const int* skip,
-                                                      uint64_t nslab, int vec_ok) {
+                                                      uint64_t nslab, int vec_ok, double* dotp) {
     if (skip && *skip) return;
     using V2 = typename Vec2<T>::type;
     constexpr int CPT = up_cols<T>();
     constexpr int ROWS = kPUpBlock / LPR;
     static_assert(kPUpBlock % LPR == 0 && LPR <= 64, "lanes per row");
+    static_assert(kPUpBlock == kPBlock, "block_sum_store takes kPBlock threads");
     extern __shared__ __align__(16) unsigned char pup[];
     const int stride = a.fup_stride;
     uint64_t* s_e = reinterpret_cast<uint64_t*>(pup);   // ROWS x stride entries
@@ -361,7 +381,10 @@ __global__ __launch_bounds__(kPUpBlock) void k_hvp_up(const PArgs a, const T* __
     const uint64_t per_xcd = (nslab + 7) / 8;              // slabs per XCD
     const uint64_t xcd = blockIdx.x % 8, j = blockIdx.x / 8;
     const uint64_t slab = (j / groups) * 8 + xcd;          // slab-major within the XCD
-    if (j / groups >= per_xcd || slab >= nslab) return;    // whole work group
+    if (j / groups >= per_xcd || slab >= nslab) {          // whole work group
+        if (dotp && threadIdx.x == 0) dotp[blockIdx.x] = 0.0;
+        return;
+    }
     const uint64_t kk0 = (j % groups) * ROWS;
     if (threadIdx.x < ROWS) s_n[threadIdx.x] = s_nh[threadIdx.x] = 0;
     __syncthreads();
@@ -384,110 +407,132 @@ __global__ __launch_bounds__(kPUpBlock) void k_hvp_up(const PArgs a, const T* __
     const uint64_t kk = kk0 + r;
     const uint32_t Dd = (uint32_t)a.Ddn;
     const uint32_t c0 = (uint32_t)(slab * (CPT * LPR) + CPT * lane);
-    if (kk >= a.nlist || c0 >= Dd) return;   // no barrier follows
-    const int nv = c0 + CPT <= Dd ? CPT : (int)(Dd - c0);
-    const bool pair = c0 + CPT <= (uint32_t)a.npair2;   // all CPT columns are mirror pairs
-    const uint64_t off = a.row_off[a.rows[kk]];
-    const uint64_t* er = s_e + r * stride;
-    const T* fr = s_f + r * stride;
-    const int n_np = s_n[r], nh = s_nh[r];
-    T acc[CPT];
+    // returns this thread's share of x . y (its columns of the finished row)
+    auto row_part = [&]() -> double {
+        const int nv = c0 + CPT <= Dd ? CPT : (int)(Dd - c0);
+        const bool pair = c0 + CPT <= (uint32_t)a.npair2;   // all CPT columns are mirror pairs
+        const uint64_t off = a.row_off[a.rows[kk]];
+        const uint64_t* er = s_e + r * stride;
+        const T* fr = s_f + r * stride;
+        const int n_np = s_n[r], nh = s_nh[r];
+        T acc[CPT];
 #pragma unroll
-    for (int t = 0; t < CPT; ++t) acc[t] = (T)0;
-    if (pair) {
-        // an image source contributes the other member of each pair: its
-        // products go to accI, whose columns are swapped once at the end
-        T accI[CPT];
+        for (int t = 0; t < CPT; ++t) acc[t] = (T)0;
+        if (pair) {
+            // an image source contributes the other member of each pair: its
+            // products go to accI, whose columns are swapped once at the end
+            T accI[CPT];
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) accI[t] = (T)0;
-        for (int h = 0; h < n_np; h += kPUpNB) {
-            T v[kPUpNB][CPT], fa[kPUpNB], fi[kPUpNB];
-            uint64_t e[kPUpNB];
+            for (int t = 0; t < CPT; ++t) accI[t] = (T)0;
+            for (int h = 0; h < n_np; h += kPUpNB) {
+                T v[kPUpNB][CPT], fa[kPUpNB], fi[kPUpNB];
+                uint64_t e[kPUpNB];
 #pragma unroll
-            for (int q = 0; q < kPUpNB; ++q) {   // the batch's entries first, then its loads
-                const int hq = h + q < n_np ? h + q : h;   // slots past the count reload hop h, factor 0
-                e[q] = er[hq];
-                const T f = h + q < n_np ? fr[hq] : (T)0;
-                const bool img = ((e[q] >> 40) & 3u) == kClsImage;
-                fa[q] = img ? (T)0 : f;
-                fi[q] = img ? f : (T)0;
+                for (int q = 0; q < kPUpNB; ++q) {   // the batch's entries first, then its loads
+                    const int hq = h + q < n_np ? h + q : h;   // slots past the count reload hop h, factor 0
+                    e[q] = er[hq];
+                    const T f = h + q < n_np ? fr[hq] : (T)0;
+                    const bool img = ((e[q] >> 40) & 3u) == kClsImage;
+                    fa[q] = img ? (T)0 : f;
+                    fi[q] = img ? f : (T)0;
+                }
+#pragma unroll
+                for (int q = 0; q < kPUpNB; ++q) {
+                    const T* src = x + (e[q] & 0xFFFFFFFFFFull) + c0;   // one wide load (any alignment)
+#pragma unroll
+                    for (int t = 0; t < CPT; ++t) v[q][t] = src[t];
+                }
+#pragma unroll
+                for (int q = 0; q < kPUpNB; ++q)
+#pragma unroll
+                    for (int t = 0; t < CPT; ++t) {
+                        acc[t] += fa[q] * v[q][t];
+                        accI[t] += fi[q] * v[q][t];
+                    }
             }
 #pragma unroll
-            for (int q = 0; q < kPUpNB; ++q) {
-                const T* src = x + (e[q] & 0xFFFFFFFFFFull) + c0;   // one wide load (any alignment)
+            for (int t = 0; t < CPT; ++t) acc[t] += accI[t ^ 1];
+        } else {
+            for (int h = 0; h < n_np; ++h) {
+                const uint64_t e = er[h];
+                const T f = fr[h];
+                const uint64_t off2 = e & 0xFFFFFFFFFFull;
+                const bool img = ((e >> 40) & 3u) == kClsImage;
 #pragma unroll
-                for (int t = 0; t < CPT; ++t) v[q][t] = src[t];
+                for (int t = 0; t < CPT; ++t)
+                    if (t < nv) acc[t] += f * x[off2 + (img ? a.fmir[c0 + t] : c0 + t)];
             }
+        }
+        if (n_np < nh) {   // rare: a palindromic source row holds representatives only
+            uint32_t pcol[CPT];
+            T pfac[CPT];
 #pragma unroll
-            for (int q = 0; q < kPUpNB; ++q)
+            for (int t = 0; t < CPT; ++t) {
+                pcol[t] = 0u;
+                pfac[t] = (T)0;
+                if (t >= nv) continue;
+                const uint32_t rd = a.dlistf[c0 + t];
+                const uint8_t dc = a.dcls[rd];
+                if (dc == kClsA) {
+                    pcol[t] = a.dcol[rd];
+                    pfac[t] = r2 * ir2;
+                } else if (dc == kClsImage) {
+                    pcol[t] = a.dcol[a.dinv[rd]];
+                    pfac[t] = r2 * ir2 * ps;
+                } else if (a.pal_in) {
+                    pcol[t] = a.dcol[rd];
+                    pfac[t] = r2;
+                }
+            }
+            for (int h = n_np; h < nh; ++h) {
+                const uint64_t off2 = er[h] & 0xFFFFFFFFFFull;
+                const T cf = fr[h];
 #pragma unroll
-                for (int t = 0; t < CPT; ++t) {
-                    acc[t] += fa[q] * v[q][t];
-                    accI[t] += fi[q] * v[q][t];
+                for (int t = 0; t < CPT; ++t)
+                    if (pfac[t] != (T)0) acc[t] += (pfac[t] * cf) * x[off2 + pcol[t]];
+            }
+        }
+        T* yr = y + off + c0;
+        T yv[CPT];
+        if (vec_ok && nv == CPT && ((off + c0) % CPT) == 0u) {
+            if constexpr (CPT == 4) {
+                float4 q4 = *reinterpret_cast<const float4*>(yr);
+                q4.x += acc[0];
+                q4.y += acc[1];
+                q4.z += acc[2];
+                q4.w += acc[3];
+                *reinterpret_cast<float4*>(yr) = q4;
+                yv[0] = q4.x;
+                yv[1] = q4.y;
+                yv[2] = q4.z;
+                yv[3] = q4.w;
+            } else {
+                V2 q2 = *reinterpret_cast<const V2*>(yr);
+                q2.x += acc[0];
+                q2.y += acc[1];
+                *reinterpret_cast<V2*>(yr) = q2;
+                yv[0] = q2.x;
+                yv[1] = q2.y;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < CPT; ++t)
+                if (t < nv) {
+                    yv[t] = yr[t] + acc[t];
+                    yr[t] = yv[t];
                 }
         }
-#pragma unroll
-        for (int t = 0; t < CPT; ++t) acc[t] += accI[t ^ 1];
-    } else {
-        for (int h = 0; h < n_np; ++h) {
-            const uint64_t e = er[h];
-            const T f = fr[h];
-            const uint64_t off2 = e & 0xFFFFFFFFFFull;
-            const bool img = ((e >> 40) & 3u) == kClsImage;
+        double ds = 0.0;
+        if (dotp) {
+            const T* xr = x + off + c0;
 #pragma unroll
             for (int t = 0; t < CPT; ++t)
-                if (t < nv) acc[t] += f * x[off2 + (img ? a.fmir[c0 + t] : c0 + t)];
+                if (t < nv) ds += (double)xr[t] * (double)yv[t];
         }
-    }
-    if (n_np < nh) {   // rare: a palindromic source row holds representatives only
-        uint32_t pcol[CPT];
-        T pfac[CPT];
-#pragma unroll
-        for (int t = 0; t < CPT; ++t) {
-            pcol[t] = 0u;
-            pfac[t] = (T)0;
-            if (t >= nv) continue;
-            const uint32_t rd = a.dlistf[c0 + t];
-            const uint8_t dc = a.dcls[rd];
-            if (dc == kClsA) {
-                pcol[t] = a.dcol[rd];
-                pfac[t] = r2 * ir2;
-            } else if (dc == kClsImage) {
-                pcol[t] = a.dcol[a.dinv[rd]];
-                pfac[t] = r2 * ir2 * ps;
-            } else if (a.pal_in) {
-                pcol[t] = a.dcol[rd];
-                pfac[t] = r2;
-            }
-        }
-        for (int h = n_np; h < nh; ++h) {
-            const uint64_t off2 = er[h] & 0xFFFFFFFFFFull;
-            const T cf = fr[h];
-#pragma unroll
-            for (int t = 0; t < CPT; ++t)
-                if (pfac[t] != (T)0) acc[t] += (pfac[t] * cf) * x[off2 + pcol[t]];
-        }
-    }
-    T* yr = y + off + c0;
-    if (vec_ok && nv == CPT && ((off + c0) % CPT) == 0u) {
-        if constexpr (CPT == 4) {
-            float4 q4 = *reinterpret_cast<const float4*>(yr);
-            q4.x += acc[0];
-            q4.y += acc[1];
-            q4.z += acc[2];
-            q4.w += acc[3];
-            *reinterpret_cast<float4*>(yr) = q4;
-        } else {
-            V2 q2 = *reinterpret_cast<const V2*>(yr);
-            q2.x += acc[0];
-            q2.y += acc[1];
-            *reinterpret_cast<V2*>(yr) = q2;
-        }
-    } else {
-#pragma unroll
-        for (int t = 0; t < CPT; ++t)
-            if (t < nv) yr[t] += acc[t];
-    }
+        return ds;
+    };
+    const double ds = kk < a.nlist && c0 < Dd ? row_part() : 0.0;
+    if (dotp) block_sum_store(ds, dotp + blockIdx.x);
 }
 
 // Full-row down-hop table in column space.
@@ -634,46 +679,69 @@ void parity_free(ParSpace* q) {
 
 namespace {
 
+// Launch geometry of one H.v: whether the full rows take the two-pass form,
+// the up pass's slabs and grid, and the palindromic-row grid.
+struct PGeom {
+    bool two_pass = false;
+    uint64_t nslab = 0, g_up = 0, g_pal = 0;
+    size_t ulds = 0;
+};
+
+PGeom pgeom(const ParSpace* q, uint64_t Ddn, size_t es) {
+    PGeom m;
+    if (q->n_full > 0) {
+        m.two_pass = !q->force_gather && Ddn * es <= kPRowLds && q->d_fup && q->fup_stride <= kPFupMax;
+        if (m.two_pass) {
+            const uint64_t rows = kPUpBlock / q->up_lpr;
+            const uint64_t span = (uint64_t)(es == 4 ? 4 : 2) * q->up_lpr;   // up_cols: columns of a slab
+            m.nslab = (Ddn + span - 1) / span;
+            m.g_up = 8 * ((m.nslab + 7) / 8) * ((q->n_full + rows - 1) / rows);
+            m.ulds = (size_t)rows * q->fup_stride * (sizeof(uint64_t) + es);
+        }
+    }
+    if (q->n_pal > 0)
+        m.g_pal = std::min<uint64_t>(std::max<uint64_t>(q->n_pal * ((q->Lp + kPBlock - 1) / kPBlock), 1), 1ull << 20);
+    return m;
+}
+
+// dotp (optional, two-pass form only): one partial sum of x . y per work
+// group of the up pass, then per work group of the palindromic rows.
 template <typename T>
-pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipStream_t s, const int* skip) {
+pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipStream_t s, const int* skip,
+                   double* dotp) {
     const ParSpace* q = p->par;
     PArgs a = pargs(p);
+    const PGeom m = pgeom(q, a.Ddn, sizeof(T));
+    static_assert(up_cols<float>() == 4 && up_cols<double>() == 2, "slab width in pgeom");
+    if (dotp && q->n_full > 0 && !m.two_pass) return fail(PDZ_EINVAL, "x . y partials need the two-pass parity H.v");
     if (q->n_full > 0) {
         a.rows = q->d_rows_full;
         a.nlist = q->n_full;
         const unsigned grid = (unsigned)std::min<uint64_t>(q->n_full, 1ull << 20);
-        const size_t lds = (size_t)a.Ddn * sizeof(T);
-        if (!q->force_gather && lds <= kPRowLds && q->d_fup && q->fup_stride <= kPFupMax) {
-            hipLaunchKernelGGL(k_hvp_down<T>, dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y, skip);
-            const int lpr = q->up_lpr;
-            const uint64_t rows = kPUpBlock / lpr;
-            const uint64_t span = (uint64_t)up_cols<T>() * lpr;   // columns of a slab
-            const uint64_t nslab = (a.Ddn + span - 1) / span;
-            const uint64_t groups = (q->n_full + rows - 1) / rows;
-            const uint64_t per_xcd = (nslab + 7) / 8;
-            const uint64_t g = 8 * per_xcd * groups;
-            if (g >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
-            const size_t ulds = (size_t)rows * q->fup_stride * (sizeof(uint64_t) + sizeof(T));
+        if (m.two_pass) {
+            hipLaunchKernelGGL(k_hvp_down<T>, dim3(grid), dim3(kPLdsBlock), (size_t)a.Ddn * sizeof(T), s, a, coef, x, y,
+                               skip);
+            if (m.g_up >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
             const size_t al = up_cols<T>() * sizeof(T);
             const int vec_ok = reinterpret_cast<uintptr_t>(x) % al == 0 && reinterpret_cast<uintptr_t>(y) % al == 0;
-            if (lpr == 16)
-                hipLaunchKernelGGL((k_hvp_up<T, 16>), dim3((unsigned)g), dim3(kPUpBlock), ulds, s, a, coef, x, y, skip,
-                                   nslab, vec_ok);
-            else if (lpr == 32)
-                hipLaunchKernelGGL((k_hvp_up<T, 32>), dim3((unsigned)g), dim3(kPUpBlock), ulds, s, a, coef, x, y, skip,
-                                   nslab, vec_ok);
+            const dim3 ug((unsigned)m.g_up);
+            if (q->up_lpr == 16)
+                hipLaunchKernelGGL((k_hvp_up<T, 16>), ug, dim3(kPUpBlock), m.ulds, s, a, coef, x, y, skip, m.nslab,
+                                   vec_ok, dotp);
+            else if (q->up_lpr == 32)
+                hipLaunchKernelGGL((k_hvp_up<T, 32>), ug, dim3(kPUpBlock), m.ulds, s, a, coef, x, y, skip, m.nslab,
+                                   vec_ok, dotp);
             else
-                hipLaunchKernelGGL((k_hvp_up<T, 64>), dim3((unsigned)g), dim3(kPUpBlock), ulds, s, a, coef, x, y, skip,
-                                   nslab, vec_ok);
+                hipLaunchKernelGGL((k_hvp_up<T, 64>), ug, dim3(kPUpBlock), m.ulds, s, a, coef, x, y, skip, m.nslab,
+                                   vec_ok, dotp);
         } else
             hipLaunchKernelGGL(k_hvp_full<T>, dim3(grid), dim3(kPBlock), 0, s, a, coef, x, y, skip);
     }
     if (q->n_pal > 0) {
         a.rows = q->d_rows_pal;
         a.nlist = q->n_pal;
-        const uint64_t g = q->n_pal * ((q->Lp + kPBlock - 1) / kPBlock);
-        hipLaunchKernelGGL(k_hvp<T>, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(g, 1), 1ull << 20)),
-                           dim3(kPBlock), 0, s, a, coef, x, y, skip);
+        hipLaunchKernelGGL(k_hvp<T>, dim3((unsigned)m.g_pal), dim3(kPBlock), 0, s, a, coef, x, y, skip,
+                           dotp ? dotp + m.g_up : nullptr);
     }
     PDZ_HIP(hipGetLastError());
     return ok();
@@ -689,10 +757,19 @@ pdz_status parity_prepare() {
     return ok();
 }
 
-pdz_status launch_hvp(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s, const int* skip) {
+pdz_status launch_hvp(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s, const int* skip,
+                      double* dotp) {
     if (dt == PDZ_F64)
-        return run_hvp<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip);
-    return run_hvp<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip);
+        return run_hvp<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip, dotp);
+    return run_hvp<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip, dotp);
+}
+
+int parity_dot_count(const pdz_problem_s* p, pdz_dtype dt) {
+    if (!p->par) return 0;
+    const PGeom m = pgeom(p->par, p->dn.D, dt == PDZ_F64 ? 8 : 4);
+    if (p->par->n_full > 0 && !m.two_pass) return 0;
+    const uint64_t n = m.g_up + m.g_pal;
+    return n < (1ull << 30) ? (int)n : 0;
 }
 
 // Parity tables on top of a real-space problem with sector hop tables.

@@ -141,9 +141,12 @@ pdz_status kspace_prepare();  // the same for the momentum-space H.v kernels
 pdz_status parity_prepare();  // the same for the parity H.v kernels
 void kspace_free(KSpace* ks);
 void parity_free(ParSpace* q);
-// y = H x on an inversion-parity subspace
+// y = H x on an inversion-parity subspace; dotp (optional) receives
+// parity_dot_count partial sums of x . y, whose total is x . y
 pdz_status launch_hvp(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
-                      const int* skip);
+                      const int* skip, double* dotp = nullptr);
+// partial sums launch_hvp writes to dotp; 0 when it cannot write them
+int parity_dot_count(const pdz_problem_s* p, pdz_dtype dt);
 // y = H x on a momentum-space problem (every pass at once; no split form)
 pdz_status launch_hvk(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                       const int* skip);

@@ -223,6 +223,20 @@ def test_parity_lanczos_E0_matches_the_oracle(case):
         assert abs(r["E0"] - e0) <= 1e-9 * max(1.0, abs(e0)), (P, r["E0"], e0)
 
 
+def test_parity_lanczos_on_the_one_pass_kernel_matches_the_oracle(monkeypatch):
+    """Forced one-pass form: no x . y partials from the H.v, so alpha takes the separate dot kernel."""
+    N, bonds, U, nu, nd = SMALL[6]
+    monkeypatch.setenv("PDZ_PARITY_GATHER", "1")
+    po = _oracle(N, bonds, U, nu, nd)
+    for P in (1, -1):
+        HP = inv.build_csr_P(po, P)
+        v0 = np.random.default_rng(2).uniform(-1, 1, HP.shape[0])
+        e0 = sla.eigsh(HP, k=1, which="SA", v0=v0, tol=1e-13)[0][0]
+        g = _gpu(N, bonds, U, nu, nd, P)
+        r = g.lanczos(storage="f64", tol=1e-12, max_iter=min(400, g.D + 2))
+        assert abs(r["E0"] - e0) <= 1e-9 * max(1.0, abs(e0)), (P, r["E0"], e0)
+
+
 def test_lowest_parity_is_the_real_space_ground_state():
     """4x4 NN+NNN torus (point inversion through the centre), 8+8, U = 6."""
     torch_cuda()

@@ -61,6 +61,10 @@ struct ParSpace {
     uint32_t* d_fmir = nullptr;    // D_dn: column of the mirror of a full row's column
     uint8_t* d_fcnt = nullptr;     // D_dn: down hops of a full row's column
     uint32_t* d_fell = nullptr;    // max_hops x D_dn: those hops as target column | amplitude index << 24
+    uint32_t* d_fell2 = nullptr;   // ceil(max_hops / 2) x D_dn: the same hops as 16-bit pairs (column |
+                                   // amplitude << pshift), hop 2i in the low half; null when they do not fit
+    int pshift = 0;
+    bool wide_table = false;       // PDZ_PARITY_WIDE_TABLE=1: keep the 32-bit table (its test)
     uint64_t* d_fup = nullptr;     // n_full x max_hops: up hops of each full row, source row start |
                                    // class << 40 | amplitude index << 48, ~0 past the last
     int fup_stride = 0;
@@ -153,6 +157,8 @@ struct PArgs {
     const uint32_t* fmir;
     const uint8_t* fcnt;
     const uint32_t* fell;
+    const uint32_t* fell2;
+    int pshift;
     const uint64_t* fup;
     int fup_stride;
     uint64_t npair2;
@@ -302,7 +308,8 @@ constexpr int kPUpNB = 8;   // hop loads in flight per lane
 constexpr int kPFupMax = 64;   // up hops per row the two-pass form takes
 constexpr uint64_t kFupNone = ~0ull;
 
-template <typename T>
+// PACKED: the table as 16-bit pairs (half the bytes and loads per hop).
+template <typename T, bool PACKED>
 __global__ __launch_bounds__(kPLdsBlock) void k_hvp_down(const PArgs a, const T* __restrict__ coef,
                                                           const T* __restrict__ x, T* __restrict__ y,
                                                           const int* skip) {
@@ -333,13 +340,29 @@ __global__ __launch_bounds__(kPLdsBlock) void k_hvp_down(const PArgs a, const T*
             const uint32_t phd_n = cn < Dd ? a.dn_states[a.dlistf[cn]] : 0u;
             const int ndh_n = cn < Dd ? a.fcnt[cn] : 0;
             T acc = (T)(a.U * __builtin_popcount(phu & phd)) * R[c];
-            for (int h0 = 0; h0 < ndh; h0 += NB) {
-                uint32_t e[NB];
+            if constexpr (PACKED) {
+                const uint32_t tm = (1u << a.pshift) - 1u;
+                for (int h0 = 0; h0 < ndh; h0 += NB) {   // NB hops = NB / 2 words
+                    uint32_t w[NB / 2];
 #pragma unroll
-                for (int j = 0; j < NB; ++j) e[j] = h0 + j < ndh ? a.fell[(uint64_t)(h0 + j) * Dd + c] : 0u;
+                    for (int j = 0; j < NB / 2; ++j)
+                        w[j] = h0 + 2 * j < ndh ? a.fell2[(uint64_t)(h0 / 2 + j) * Dd + c] : 0u;
 #pragma unroll
-                for (int j = 0; j < NB; ++j)
-                    if (h0 + j < ndh) acc += s_coef[e[j] >> kTargetBits] * R[e[j] & kTargetMask];
+                    for (int j = 0; j < NB / 2; ++j) {
+                        const uint32_t e0 = w[j] & 0xFFFFu, e1 = w[j] >> 16;
+                        if (h0 + 2 * j < ndh) acc += s_coef[e0 >> a.pshift] * R[e0 & tm];
+                        if (h0 + 2 * j + 1 < ndh) acc += s_coef[e1 >> a.pshift] * R[e1 & tm];
+                    }
+                }
+            } else {
+                for (int h0 = 0; h0 < ndh; h0 += NB) {
+                    uint32_t e[NB];
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) e[j] = h0 + j < ndh ? a.fell[(uint64_t)(h0 + j) * Dd + c] : 0u;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j)
+                        if (h0 + j < ndh) acc += s_coef[e[j] >> kTargetBits] * R[e[j] & kTargetMask];
+                }
             }
             y[off + c] = acc;
             phd = phd_n;
@@ -641,6 +664,8 @@ PArgs pargs(const pdz_problem_s* p) {
     a.fmir = q->d_fmir;
     a.fcnt = q->d_fcnt;
     a.fell = q->d_fell;
+    a.fell2 = q->d_fell2;
+    a.pshift = q->pshift;
     a.fup = q->d_fup;
     a.fup_stride = q->fup_stride;
     a.npair2 = q->npair2;
@@ -671,7 +696,7 @@ void parity_free(ParSpace* q) {
     if (!q) return;
     void* ptrs[] = {q->d_ucls, q->d_uinv, q->d_utree, q->d_urow, q->d_dcls, q->d_dinv, q->d_dtree, q->d_dcol,
                     q->d_dlist, q->d_row_rank, q->d_row_off, q->d_row_pal, q->d_S, q->d_rows_full, q->d_rows_pal,
-                    q->d_dcolf, q->d_dlistf, q->d_fmir, q->d_fcnt, q->d_fell, q->d_fup};
+                    q->d_dcolf, q->d_dlistf, q->d_fmir, q->d_fcnt, q->d_fell, q->d_fell2, q->d_fup};
     for (void* v : ptrs)
         if (v) (void)hipFree(v);
     delete q;
@@ -719,8 +744,12 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
         a.nlist = q->n_full;
         const unsigned grid = (unsigned)std::min<uint64_t>(q->n_full, 1ull << 20);
         if (m.two_pass) {
-            hipLaunchKernelGGL(k_hvp_down<T>, dim3(grid), dim3(kPLdsBlock), (size_t)a.Ddn * sizeof(T), s, a, coef, x, y,
-                               skip);
+            if (q->d_fell2)
+                hipLaunchKernelGGL((k_hvp_down<T, true>), dim3(grid), dim3(kPLdsBlock), (size_t)a.Ddn * sizeof(T), s, a,
+                                   coef, x, y, skip);
+            else
+                hipLaunchKernelGGL((k_hvp_down<T, false>), dim3(grid), dim3(kPLdsBlock), (size_t)a.Ddn * sizeof(T), s, a,
+                                   coef, x, y, skip);
             if (m.g_up >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
             const size_t al = up_cols<T>() * sizeof(T);
             const int vec_ok = reinterpret_cast<uintptr_t>(x) % al == 0 && reinterpret_cast<uintptr_t>(y) % al == 0;
@@ -750,9 +779,13 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
 }  // namespace
 
 pdz_status parity_prepare() {
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<double>),
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<double, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<float>),
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<float, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<double, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<float, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
     return ok();
 }
@@ -781,6 +814,8 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
     {
         const char* env = std::getenv("PDZ_PARITY_GATHER");
         q->force_gather = env && env[0] == '1';
+        const char* wide = std::getenv("PDZ_PARITY_WIDE_TABLE");
+        q->wide_table = wide && wide[0] == '1';
         const char* lanes = std::getenv("PDZ_PARITY_UP_LANES");
         if (lanes) {
             const std::string v(lanes);
@@ -902,6 +937,30 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
         hipLaunchKernelGGL(k_pcolhops, dim3(pgrid(Dd, cu)), dim3(kPBlock), 0, nullptr, pa, mh, q->d_fcnt, q->d_fell);
         PDZ_HIP(hipGetLastError());
         PDZ_HIP(hipDeviceSynchronize());
+    }
+    if (!q->wide_table && p->dn.max_hops > 0) {   // 16-bit pairs when column and amplitude index fit
+        std::vector<uint8_t> fcnt(Dd);
+        std::vector<uint32_t> fell((size_t)mh * Dd);
+        PDZ_HIP(hipMemcpy(fcnt.data(), q->d_fcnt, Dd, hipMemcpyDeviceToHost));
+        PDZ_HIP(hipMemcpy(fell.data(), q->d_fell, fell.size() * 4, hipMemcpyDeviceToHost));
+        uint32_t cmax = 0;
+        for (uint64_t c = 0; c < Dd; ++c)
+            for (int h = 0; h < fcnt[c]; ++h) cmax = std::max(cmax, fell[(size_t)h * Dd + c] >> kTargetBits);
+        int cbits = 0;
+        while ((1u << cbits) <= cmax) ++cbits;
+        const int tbits = 16 - cbits;
+        if (tbits > 0 && Dd <= (1ull << tbits)) {
+            const int mh2 = (mh + 1) / 2;
+            std::vector<uint32_t> fell2((size_t)mh2 * Dd, 0u);
+            for (uint64_t c = 0; c < Dd; ++c)
+                for (int h = 0; h < fcnt[c]; ++h) {
+                    const uint32_t e = fell[(size_t)h * Dd + c];
+                    const uint32_t e16 = (e & kTargetMask) | ((e >> kTargetBits) << tbits);
+                    fell2[(size_t)(h / 2) * Dd + c] |= e16 << (16 * (h % 2));
+                }
+            q->pshift = tbits;
+            if ((st = dupload(&q->d_fell2, fell2)) != PDZ_OK) return st;
+        }
     }
     std::vector<uint32_t> rows_full, rows_pal;
     for (uint64_t k = 0; k < ureps; ++k) (row_pal[k] ? rows_pal : rows_full).push_back((uint32_t)k);

@@ -175,6 +175,25 @@ def test_parity_up_pass_lanes_must_be_16_32_or_64(monkeypatch):
         _gpu(8, _chain(8), 4.0, 4, 4, 1)
 
 
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+@pytest.mark.parametrize("case", [SMALL[0], SMALL[1], SMALL[6]], ids=["chain8", "chain7nnn", "open5x2"])
+def test_parity_down_pass_32bit_table_matches_the_oracle(case, dtype_name, monkeypatch):
+    """The down pass on its 32-bit hop table (the form for sectors whose columns do not fit 16-bit entries)."""
+    torch = torch_cuda()
+    N, bonds, U, nu, nd = case
+    monkeypatch.setenv("PDZ_PARITY_WIDE_TABLE", "1")
+    for P in (1, -1):
+        HP = inv.build_csr_P(_oracle(N, bonds, U, nu, nd), P)
+        g = _gpu(N, bonds, U, nu, nd, P)
+        dt, e = (torch.float64, EPS64) if dtype_name == "f64" else (torch.float32, EPS32)
+        x = np.random.default_rng(29).uniform(-1, 1, g.D)
+        if dtype_name == "f32":
+            x = x.astype(np.float32).astype(np.float64)
+        y = to_host(g.hv(to_dev(x, dt))).astype(np.float64)
+        err = np.abs(y - HP @ x)
+        assert np.all(err <= _bound(HP, x, e) + 1e-300), (np.max(err), dtype_name, P)
+
+
 def _sampled(w, P, nrows, seed, dtype_name):
     torch = torch_cuda()
     po = oracle.Problem.from_workload(w)

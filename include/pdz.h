@@ -382,7 +382,9 @@ pdz_status pdz_kspace_info(pdz_problem p, int32_t* L1, int32_t* L2, int32_t* K, 
  * Read at creation: PDZ_PARITY_UP_LANES = 16, 32 or 64 (default) lanes per
  * row in the up pass of H.v (its column slab is that times 4 in FP32, 2 in
  * FP64; any other value fails with PDZ_EINVAL); PDZ_PARITY_GATHER=1 serves
- * the non-palindromic rows with the one-pass kernel.  Synchronous.  Errors: as pdz_problem_create; PDZ_EINVAL (parity not +-1,
+ * the non-palindromic rows with the one-pass kernel; PDZ_PARITY_WIDE_TABLE=1
+ * keeps the down pass on 32-bit hop entries where 16-bit pairs would fit.
+ * Synchronous.  Errors: as pdz_problem_create; PDZ_EINVAL (parity not +-1,
  * bonds not mirror symmetric); PDZ_ERANGE (sectors too large for the hop
  * tables, empty subspace); PDZ_EDEVICE (a tree map failed its bijection
  * check: a library fault). */

@@ -380,10 +380,11 @@ template <typename T> constexpr int up_cols() { return sizeof(T) == 4 ? 4 : 2; }
 
 // Each lane takes up_cols consecutive columns starting at a multiple of
 // up_cols.  When they all lie in the head of the row (mirror pairs), the
-// source's columns are read as one block and an image source swaps each pair; lanes on the palindrome tail
-// (or straddling it) read single columns with the mirror column from the
-// table.  Hops from palindromic source rows (listed last) read the columns of
-// the representatives.
+// source's columns are read as one block and an image source swaps each
+// pair; lanes on the palindrome tail (or straddling it) read single columns
+// with the mirror column from the table.  Hops from palindromic source rows
+// (listed last) read the columns of the representatives.  With dotp set,
+// work group b writes dotp[b] = its share of x . y over the finished rows.
 template <typename T, int LPR>
 __global__ __launch_bounds__(kPUpBlock) void k_hvp_up(const PArgs a, const T* __restrict__ coef,
                                                       const T* __restrict__ x, T* __restrict__ y, const int* skip,

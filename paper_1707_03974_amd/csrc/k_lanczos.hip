@@ -732,6 +732,17 @@ struct Run {
 
     // The two passes of H q_k and alpha_k (the first half of step_scaled).
     pdz_status head_step(T* q, T* w, const SplitCounts& c) {
+        if (p->par) {   // the whole H q_0 into w, alpha_0 from its x . y partials
+            HvSplit sw;
+            sw.dotp_up = partial();
+            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sw);
+            if (st != PDZ_OK) return st;
+            hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial(), (uint64_t)c.nwhole,
+                               partial2(), done());
+            hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), 0, partial2(),
+                               (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
+            return launch_check();
+        }
         HvSplit sp;
         sp.z = zbuf();
         sp.dotp_dn = partial();
@@ -752,6 +763,7 @@ struct Run {
     // (receives that of H q_{k+1}).  Between the two passes: beta_{k+1}, the
     // tridiagonal solve of T_{k+1} and sc[k+1], as in step_scaled.
     pdz_status fused_step(T* q1, T* q2, T* w, const SplitCounts& c) {
+        if (p->par) return fused_step_parity(q1, q2, w, c);
         mark(0);
         HvSplit f;
         f.dotp_dn = partial();
@@ -785,6 +797,48 @@ struct Run {
                            partial2(), done());
         hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), c.ndn, partial2(),
                            (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
+        mark(4);
+        mark(5);
+        return launch_check();
+    }
+
+    // fused_step on a parity subspace, whose H.v keeps its parts in y: w holds
+    // the whole H q_k; the down pass forms q_{k+1} (over q2, the palindromic
+    // rows included) and overwrites w with the down part of H q_{k+1}, to which
+    // the up pass adds the rest (the palindromic rows whole), writing the x . y
+    // partials of alpha_{k+1}.
+    pdz_status fused_step_parity(T* q1, T* q2, T* w, const SplitCounts& c) {
+        const pdz_dtype dt = (pdz_dtype)o->storage;
+        mark(0);
+        HvSplit f;
+        f.fq1 = q1;
+        f.fq2 = q2;
+        f.fkeep = kept(0);
+        f.fkeep_ld = ld();
+        f.fkeep_cap = L.nkept;
+        f.falpha = alpha();
+        f.fbeta = beta();
+        f.fsc = sc();
+        f.fkidx = kptr();
+        f.fnorm = partial3();
+        pdz_status st = launch_hv_any(p, dt, q2, w, s, done(), kPassDown, &f);
+        if (st != PDZ_OK) return st;
+        mark(1);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial3(), parity_fused_norms(p, dt), beta(),
+                           kptr(), 1, (int)kStoreSqrt, done(), err);
+        hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kRedBlock), 0, s, alpha(), beta(), svec(), theta(), ctl(), o->tol,
+                           o->max_iter, err);
+        hipLaunchKernelGGL(k_next_scale, dim3(1), dim3(1), 0, s, beta(), sc(), ctl());
+        mark(2);
+        HvSplit u;
+        u.dotp_up = partial();
+        st = launch_hv_any(p, dt, q2, w, s, done(), kPassUp, &u);
+        if (st != PDZ_OK) return st;
+        mark(3);
+        hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial(), (uint64_t)c.nwhole,
+                           partial2(), done());
+        hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), 0, partial2(), (int)kRedGrid,
+                           alpha(), sc(), kptr(), done(), err);
         mark(4);
         mark(5);
         return launch_check();
@@ -881,6 +935,14 @@ struct Run {
     bool fused_path() const {
         if (o->reorth) return false;
         const SplitCounts c = split_counts();
+        if (p->par) {
+            // parity: the recurrence rides on its down pass (two-pass form) in
+            // FP64 storage, where a row fills the LDS budget and the fused pass
+            // costs less than the separate update; in FP32 two rows share a CU
+            // and the separate update is the faster of the two
+            const int nn = parity_fused_norms(p, (pdz_dtype)o->storage);
+            return o->storage == PDZ_F64 && nn > 0 && nn <= kMaxPartials && c.nwhole > 0;
+        }
         return c.ndn > 0 && c.ndn <= kMaxPartials && hv_fused_available(p, (pdz_dtype)o->storage);
     }
 

@@ -308,23 +308,98 @@ constexpr int kPUpNB = 8;   // hop loads in flight per lane
 constexpr int kPFupMax = 64;   // up hops per row the two-pass form takes
 constexpr uint64_t kFupNone = ~0ull;
 
+// Lanczos recurrence carried by a pass (the whole H q_k is in y):
+// q_{k+1} = sc_k y - alpha_k sc_k q_k - beta_k sc_{k-1} q_{k-1}, written over
+// q2 = q_{k-1} (and to slot k + 1 of keep when set), with one |q_{k+1}|^2
+// partial per work group in norm.
+template <typename T>
+struct PFuse {
+    const T* q1 = nullptr;
+    T* q2 = nullptr;
+    T* keep = nullptr;
+    uint64_t keep_ld = 0;
+    int keep_cap = 0;
+    const double* alpha = nullptr;
+    const double* beta = nullptr;
+    const double* sc = nullptr;
+    const int* kidx = nullptr;
+    double* norm = nullptr;
+};
+
+// The recurrence's coefficients at step *kidx and the keep slot it fills.
+template <typename T>
+__device__ __forceinline__ void pfuse_coefs(const PFuse<T>& f, double* fa, double* fb, double* fc, T** keep) {
+    const int k = *f.kidx;
+    *fa = f.sc[k];
+    *fb = f.alpha[k] * f.sc[k];
+    *fc = k > 0 ? f.beta[k] * f.sc[k - 1] : 0.0;
+    *keep = f.keep && k + 1 < f.keep_cap ? f.keep + (uint64_t)(k + 1) * f.keep_ld : nullptr;
+}
+
+// *out = sum of v over a work group of kPLdsBlock threads, in a fixed order.
+__device__ __forceinline__ void block_sum_store_wide(double v, double* out) {
+    __shared__ double red[kPLdsBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kPLdsBlock / 64; ++w) t += red[w];
+        *out = t;
+    }
+}
+
 // PACKED: the table as 16-bit pairs (half the bytes and loads per hop).
-template <typename T, bool PACKED>
+// FUSE: the rows staged are q_{k+1}, formed here from y (the whole H q_k,
+// then overwritten by the down part of H q_{k+1}) and f; x is unused.
+template <typename T, bool PACKED, bool FUSE>
 __global__ __launch_bounds__(kPLdsBlock) void k_hvp_down(const PArgs a, const T* __restrict__ coef,
                                                           const T* __restrict__ x, T* __restrict__ y,
-                                                          const int* skip) {
+                                                          const int* skip, const PFuse<T> f) {
     if (skip && *skip) return;
     extern __shared__ __align__(16) unsigned char pdyn[];
     T* R = reinterpret_cast<T*>(pdyn);
     __shared__ T s_coef[kMaxCoef];
     for (int i = threadIdx.x; i < kMaxCoef; i += kPLdsBlock) s_coef[i] = coef[i];
     const uint32_t Dd = (uint32_t)a.Ddn;
+    double fa = 0.0, fb = 0.0, fc = 0.0, nsum = 0.0;
+    T* fkeep = nullptr;
+    if constexpr (FUSE) pfuse_coefs(f, &fa, &fb, &fc, &fkeep);
     for (uint64_t kk = blockIdx.x; kk < a.nlist; kk += gridDim.x) {
         const uint64_t k = a.rows[kk];
         const uint64_t off = a.row_off[k];
         const uint32_t phu = a.up_states[a.row_rank[k]];
         __syncthreads();
-        for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) R[c] = x[off + c];
+        if constexpr (FUSE) {
+            // four elements per thread at a time: every operand load of the
+            // batch is issued before its stores (q2 is both read and written)
+            for (uint32_t c0 = threadIdx.x; c0 < Dd; c0 += 4 * kPLdsBlock) {
+                T vy[4], v1[4], v2[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t c = c0 + j * kPLdsBlock;
+                    if (c < Dd) {   // streamed past L2, which keeps the hop table
+                        vy[j] = __builtin_nontemporal_load(y + off + c);
+                        v1[j] = __builtin_nontemporal_load(f.q1 + off + c);
+                        v2[j] = __builtin_nontemporal_load(f.q2 + off + c);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t c = c0 + j * kPLdsBlock;
+                    if (c < Dd) {
+                        const T v = lanczos_recurrence<T>(vy[j], (T)0, v1[j], v2[j], fa, fb, fc);
+                        __builtin_nontemporal_store(v, f.q2 + off + c);
+                        if (fkeep) __builtin_nontemporal_store(v, fkeep + off + c);
+                        nsum += (double)v * (double)v;
+                        R[c] = v;
+                    }
+                }
+            }
+        } else {
+            for (uint32_t c = threadIdx.x; c < Dd; c += kPLdsBlock) R[c] = __builtin_nontemporal_load(x + off + c);
+        }
         __syncthreads();
         // each column: its down string and hop count (prefetched one column
         // ahead), then its table entries NB at a time, then their LDS reads.
@@ -364,11 +439,35 @@ __global__ __launch_bounds__(kPLdsBlock) void k_hvp_down(const PArgs a, const T*
                         if (h0 + j < ndh) acc += s_coef[e[j] >> kTargetBits] * R[e[j] & kTargetMask];
                 }
             }
-            y[off + c] = acc;
+            __builtin_nontemporal_store(acc, y + off + c);
             phd = phd_n;
             ndh = ndh_n;
         }
     }
+    if constexpr (FUSE) block_sum_store_wide(nsum, f.norm + blockIdx.x);
+}
+
+// The recurrence on the palindromic rows (FUSE companion of k_hvp_down, which
+// covers the full rows): norm partials at f.norm[norm_off + work group].
+template <typename T>
+__global__ __launch_bounds__(kPBlock) void k_pform(const PArgs a, T* __restrict__ y, const int* skip,
+                                                    const PFuse<T> f, int norm_off) {
+    if (skip && *skip) return;
+    double fa, fb, fc, nsum = 0.0;
+    T* fkeep;
+    pfuse_coefs(f, &fa, &fb, &fc, &fkeep);
+    const uint64_t n = a.nlist * a.Lp;   // row kk of the list, column c < Lp (past the row's length: none)
+    for (uint64_t i = (uint64_t)blockIdx.x * kPBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kPBlock) {
+        const uint64_t k = a.rows[i / a.Lp], c = i % a.Lp;
+        const uint64_t off = a.row_off[k];
+        if (c >= a.row_off[k + 1] - off) continue;
+        const uint64_t e = off + c;
+        const T v = lanczos_recurrence<T>(y[e], (T)0, f.q1[e], f.q2[e], fa, fb, fc);
+        f.q2[e] = v;
+        if (fkeep) fkeep[e] = v;
+        nsum += (double)v * (double)v;
+    }
+    block_sum_store(nsum, f.norm + norm_off + blockIdx.x);
 }
 
 template <typename T> struct Vec2;
@@ -730,48 +829,77 @@ PGeom pgeom(const ParSpace* q, uint64_t Ddn, size_t es) {
     return m;
 }
 
-// dotp (optional, two-pass form only): one partial sum of x . y per work
-// group of the up pass, then per work group of the palindromic rows.
+// Work groups of the fused down pass (|q_{k+1}|^2 partials: these plus
+// kPFormGrid for the palindromic rows).
+constexpr uint64_t kPFuseGrid = 2048;
+constexpr uint64_t kPFormGrid = 256;
+
+// passes: kPassDown launches the down pass (with the recurrence when f is
+// set: then x is unused and the palindromic rows' q_{k+1} is formed too),
+// kPassUp the up pass and the palindromic rows; both: the whole H.v.
+// dotp (optional, two-pass form only, with the up part): one partial sum of
+// x . y per work group of the up pass, then per work group of the
+// palindromic rows.
 template <typename T>
 pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipStream_t s, const int* skip,
-                   double* dotp) {
+                   double* dotp, unsigned passes, const PFuse<T>* f) {
     const ParSpace* q = p->par;
     PArgs a = pargs(p);
     const PGeom m = pgeom(q, a.Ddn, sizeof(T));
     static_assert(up_cols<float>() == 4 && up_cols<double>() == 2, "slab width in pgeom");
-    if (dotp && q->n_full > 0 && !m.two_pass) return fail(PDZ_EINVAL, "x . y partials need the two-pass parity H.v");
+    const bool down = passes & kPassDown, up = passes & kPassUp;
+    if ((dotp || f || passes != (kPassDown | kPassUp)) && q->n_full > 0 && !m.two_pass)
+        return fail(PDZ_EINVAL, "separate passes, x . y partials and the fused recurrence need the two-pass parity H.v");
+    if (f && (!down || up)) return fail(PDZ_EINVAL, "the fused recurrence rides on the down pass alone");
     if (q->n_full > 0) {
         a.rows = q->d_rows_full;
         a.nlist = q->n_full;
-        const unsigned grid = (unsigned)std::min<uint64_t>(q->n_full, 1ull << 20);
+        const unsigned grid = (unsigned)std::min<uint64_t>(q->n_full, f ? kPFuseGrid : (1ull << 20));
         if (m.two_pass) {
-            if (q->d_fell2)
-                hipLaunchKernelGGL((k_hvp_down<T, true>), dim3(grid), dim3(kPLdsBlock), (size_t)a.Ddn * sizeof(T), s, a,
-                                   coef, x, y, skip);
-            else
-                hipLaunchKernelGGL((k_hvp_down<T, false>), dim3(grid), dim3(kPLdsBlock), (size_t)a.Ddn * sizeof(T), s, a,
-                                   coef, x, y, skip);
-            if (m.g_up >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
-            const size_t al = up_cols<T>() * sizeof(T);
-            const int vec_ok = reinterpret_cast<uintptr_t>(x) % al == 0 && reinterpret_cast<uintptr_t>(y) % al == 0;
-            const dim3 ug((unsigned)m.g_up);
-            if (q->up_lpr == 16)
-                hipLaunchKernelGGL((k_hvp_up<T, 16>), ug, dim3(kPUpBlock), m.ulds, s, a, coef, x, y, skip, m.nslab,
-                                   vec_ok, dotp);
-            else if (q->up_lpr == 32)
-                hipLaunchKernelGGL((k_hvp_up<T, 32>), ug, dim3(kPUpBlock), m.ulds, s, a, coef, x, y, skip, m.nslab,
-                                   vec_ok, dotp);
-            else
-                hipLaunchKernelGGL((k_hvp_up<T, 64>), ug, dim3(kPUpBlock), m.ulds, s, a, coef, x, y, skip, m.nslab,
-                                   vec_ok, dotp);
+            const size_t lds = (size_t)a.Ddn * sizeof(T);
+            const PFuse<T> f0 = f ? *f : PFuse<T>();
+            if (down) {
+                if (f && q->d_fell2)
+                    hipLaunchKernelGGL((k_hvp_down<T, true, true>), dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y,
+                                       skip, f0);
+                else if (f)
+                    hipLaunchKernelGGL((k_hvp_down<T, false, true>), dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x,
+                                       y, skip, f0);
+                else if (q->d_fell2)
+                    hipLaunchKernelGGL((k_hvp_down<T, true, false>), dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x,
+                                       y, skip, f0);
+                else
+                    hipLaunchKernelGGL((k_hvp_down<T, false, false>), dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x,
+                                       y, skip, f0);
+            }
+            if (up) {
+                if (m.g_up >= (1ull << 31)) return fail(PDZ_ERANGE, "parity up pass grid too large");
+                const size_t al = up_cols<T>() * sizeof(T);
+                const int vec_ok =
+                    reinterpret_cast<uintptr_t>(x) % al == 0 && reinterpret_cast<uintptr_t>(y) % al == 0;
+                const dim3 ug((unsigned)m.g_up);
+                if (q->up_lpr == 16)
+                    hipLaunchKernelGGL((k_hvp_up<T, 16>), ug, dim3(kPUpBlock), m.ulds, s, a, coef, x, y, skip, m.nslab,
+                                       vec_ok, dotp);
+                else if (q->up_lpr == 32)
+                    hipLaunchKernelGGL((k_hvp_up<T, 32>), ug, dim3(kPUpBlock), m.ulds, s, a, coef, x, y, skip, m.nslab,
+                                       vec_ok, dotp);
+                else
+                    hipLaunchKernelGGL((k_hvp_up<T, 64>), ug, dim3(kPUpBlock), m.ulds, s, a, coef, x, y, skip, m.nslab,
+                                       vec_ok, dotp);
+            }
         } else
             hipLaunchKernelGGL(k_hvp_full<T>, dim3(grid), dim3(kPBlock), 0, s, a, coef, x, y, skip);
     }
     if (q->n_pal > 0) {
         a.rows = q->d_rows_pal;
         a.nlist = q->n_pal;
-        hipLaunchKernelGGL(k_hvp<T>, dim3((unsigned)m.g_pal), dim3(kPBlock), 0, s, a, coef, x, y, skip,
-                           dotp ? dotp + m.g_up : nullptr);
+        if (f)
+            hipLaunchKernelGGL(k_pform<T>, dim3((unsigned)kPFormGrid), dim3(kPBlock), 0, s, a, y, skip, *f,
+                               q->n_full > 0 ? (int)std::min<uint64_t>(q->n_full, kPFuseGrid) : 0);
+        if (up)
+            hipLaunchKernelGGL(k_hvp<T>, dim3((unsigned)m.g_pal), dim3(kPBlock), 0, s, a, coef, x, y, skip,
+                               dotp ? dotp + m.g_up : nullptr);
     }
     PDZ_HIP(hipGetLastError());
     return ok();
@@ -780,22 +908,72 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
 }  // namespace
 
 pdz_status parity_prepare() {
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<double, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<float, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<double, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hvp_down<float, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
+    const void* downs[] = {
+        reinterpret_cast<const void*>(&k_hvp_down<double, false, false>),
+        reinterpret_cast<const void*>(&k_hvp_down<float, false, false>),
+        reinterpret_cast<const void*>(&k_hvp_down<double, true, false>),
+        reinterpret_cast<const void*>(&k_hvp_down<float, true, false>),
+        reinterpret_cast<const void*>(&k_hvp_down<double, false, true>),
+        reinterpret_cast<const void*>(&k_hvp_down<float, false, true>),
+        reinterpret_cast<const void*>(&k_hvp_down<double, true, true>),
+        reinterpret_cast<const void*>(&k_hvp_down<float, true, true>)};
+    for (const void* k : downs)
+        PDZ_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRowLds));
     return ok();
 }
 
 pdz_status launch_hvp(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s, const int* skip,
                       double* dotp) {
+    const unsigned both = kPassDown | kPassUp;
     if (dt == PDZ_F64)
-        return run_hvp<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip, dotp);
-    return run_hvp<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip, dotp);
+        return run_hvp<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip, dotp,
+                               both, nullptr);
+    return run_hvp<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip, dotp, both,
+                          nullptr);
+}
+
+namespace {
+template <typename T>
+PFuse<T> pfuse_of(const HvSplit* sp) {
+    PFuse<T> f;
+    f.q1 = static_cast<const T*>(sp->fq1);
+    f.q2 = static_cast<T*>(sp->fq2);
+    f.keep = static_cast<T*>(sp->fkeep);
+    f.keep_ld = sp->fkeep_ld;
+    f.keep_cap = sp->fkeep_cap;
+    f.alpha = sp->falpha;
+    f.beta = sp->fbeta;
+    f.sc = sp->fsc;
+    f.kidx = sp->fkidx;
+    f.norm = sp->fnorm;
+    return f;
+}
+}  // namespace
+
+pdz_status launch_hvp_split(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
+                            const int* skip, unsigned passes, const HvSplit* sp) {
+    if (sp && (sp->z || sp->dotp_dn || sp->fz))
+        return fail(PDZ_EINVAL, "a parity H.v keeps its parts in y: no z, down-pass dots or fz");
+    if (sp && sp->dotp_up && !(passes & kPassUp)) return fail(PDZ_EINVAL, "x . y partials come with the up part");
+    if (sp && sp->fq2 && !sp->fnorm) return fail(PDZ_EINVAL, "the fused recurrence needs fnorm");
+    double* dotp = sp ? sp->dotp_up : nullptr;
+    const bool fuse = sp && sp->fq2;
+    if (dt == PDZ_F64) {
+        const PFuse<double> f = fuse ? pfuse_of<double>(sp) : PFuse<double>();
+        return run_hvp<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip, dotp,
+                               passes, fuse ? &f : nullptr);
+    }
+    const PFuse<float> f = fuse ? pfuse_of<float>(sp) : PFuse<float>();
+    return run_hvp<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip, dotp, passes,
+                          fuse ? &f : nullptr);
+}
+
+int parity_fused_norms(const pdz_problem_s* p, pdz_dtype dt) {
+    if (!p->par) return 0;
+    const ParSpace* q = p->par;
+    const PGeom m = pgeom(q, p->dn.D, dt == PDZ_F64 ? 8 : 4);
+    if (q->n_full > 0 && !m.two_pass) return 0;
+    return (int)((q->n_full > 0 ? std::min<uint64_t>(q->n_full, kPFuseGrid) : 0) + (q->n_pal > 0 ? kPFormGrid : 0));
 }
 
 int parity_dot_count(const pdz_problem_s* p, pdz_dtype dt) {

@@ -76,14 +76,12 @@ uint64_t binom(int n, int k) {
 
 pdz_status launch_hv_any(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                          const int* skip, unsigned passes, const HvSplit* split) {
-    if (p->ks || p->par) {
-        // a parity H.v may write its x . y partial sums (split carrying dotp_up only)
-        const bool dot_only = p->par && split && !split->z && !split->dotp_dn && !split->fq2 && split->dotp_up;
-        if ((split && !dot_only) || passes != (kPassDown | kPassUp))
-            return fail(PDZ_EINVAL, "a symmetry-sector H.v has no separate passes");
-        return p->ks ? launch_hvk(p, dt, x, y, s, skip)
-                     : launch_hvp(p, dt, x, y, s, skip, dot_only ? split->dotp_up : nullptr);
+    if (p->ks) {
+        if (split || passes != (kPassDown | kPassUp))
+            return fail(PDZ_EINVAL, "a momentum-space H.v has no separate passes");
+        return launch_hvk(p, dt, x, y, s, skip);
     }
+    if (p->par) return launch_hvp_split(p, dt, x, y, s, skip, passes, split);
     return launch_hv(p, dt, x, y, s, skip, passes, split);
 }
 

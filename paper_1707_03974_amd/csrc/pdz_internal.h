@@ -183,6 +183,15 @@ struct HvSplit {
     double* fnorm = nullptr;
 };
 bool hv_fused_available(const pdz_problem_s* p, pdz_dtype dt);
+// Parity H.v by passes (kPassDown: the down pass, with the recurrence when
+// sp->fq2 is set; kPassUp: the up pass and the palindromic rows, with x . y
+// partials in sp->dotp_up).  Its parts stay in y: sp->z, dotp_dn and fz must
+// be null.
+pdz_status launch_hvp_split(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
+                            const int* skip, unsigned passes, const HvSplit* sp);
+// |q_{k+1}|^2 partials the fused parity down pass writes to fnorm; 0 when
+// the problem has no fused form
+int parity_fused_norms(const pdz_problem_s* p, pdz_dtype dt);
 // H.v of a real-space problem (k_hv.hip)
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                      const int* skip = nullptr, unsigned passes = kPassDown | kPassUp,

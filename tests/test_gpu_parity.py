@@ -242,6 +242,26 @@ def test_parity_lanczos_E0_matches_the_oracle(case):
         assert abs(r["E0"] - e0) <= 1e-9 * max(1.0, abs(e0)), (P, r["E0"], e0)
 
 
+@pytest.mark.parametrize("mode", ["f32_keep", "f32_regen", "f64_graph_off", "f64_reorth"])
+def test_parity_lanczos_modes_match_the_oracle(mode):
+    """The recurrence fused into the parity down pass (FP32 storage with kept or regenerated vectors for the
+    FP64 refinement, FP64 without graphs) and the unfused step of full re-orthogonalisation, against the oracle."""
+    N, bonds, U, nu, nd = SMALL[6]
+    po = _oracle(N, bonds, U, nu, nd)
+    kw = {"f32_keep": dict(storage="f32", tol=1e-7, refine=1, keep_basis=1),
+          "f32_regen": dict(storage="f32", tol=1e-7, refine=1, keep_basis=0),
+          "f64_graph_off": dict(storage="f64", tol=1e-12, use_graph=0),
+          "f64_reorth": dict(storage="f64", tol=1e-12, reorth=1)}[mode]
+    for P in (1, -1):
+        HP = inv.build_csr_P(po, P)
+        v0 = np.random.default_rng(2).uniform(-1, 1, HP.shape[0])
+        e0 = sla.eigsh(HP, k=1, which="SA", v0=v0, tol=1e-13)[0][0]
+        g = _gpu(N, bonds, U, nu, nd, P)
+        r = g.lanczos(max_iter=300, **kw)
+        e = r["E0_refined"] if mode.startswith("f32") else r["E0"]
+        assert abs(e - e0) <= 1e-8 * max(1.0, abs(e0)), (mode, P, e, e0)
+
+
 def test_parity_lanczos_on_the_one_pass_kernel_matches_the_oracle(monkeypatch):
     """Forced one-pass form: no x . y partials from the H.v, so alpha takes the separate dot kernel."""
     N, bonds, U, nu, nd = SMALL[6]

@@ -577,6 +577,8 @@ def main():
                     help="run only the momentum-space section and print its JSON object")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 32-cluster batched section and print its JSON object")
+    ap.add_argument("--dynamics-only", action="store_true",
+                    help="run only the single-particle spectral function section and print its JSON object")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of D floats (known bytes) to scale counter readings")
     args = ap.parse_args()
@@ -592,6 +594,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batched_only:
         print(json.dumps({"batched": batched_bench(torch, pdz, synth, args.hv_reps)}), flush=True)
+        return
+    if args.dynamics_only:
+        print(json.dumps({"dynamics": dynamics_bench(torch, pdz, synth)}), flush=True)
         return
     if args.parity_only:
         print(json.dumps({"parity": parity_bench(torch, pdz, synth, args.hv_reps, calibrate=args.calibrate_copy)}),

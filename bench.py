@@ -579,6 +579,8 @@ def main():
                     help="run only the 32-cluster batched section and print its JSON object")
     ap.add_argument("--dynamics-only", action="store_true",
                     help="run only the single-particle spectral function section and print its JSON object")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="run only the learned-start section and print its JSON object")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of D floats (known bytes) to scale counter readings")
     args = ap.parse_args()
@@ -597,6 +599,9 @@ def main():
         return
     if args.dynamics_only:
         print(json.dumps({"dynamics": dynamics_bench(torch, pdz, synth)}), flush=True)
+        return
+    if args.learned_only:
+        print(json.dumps({"learned_start": learned_bench(torch, pdz, synth)}), flush=True)
         return
     if args.parity_only:
         print(json.dumps({"parity": parity_bench(torch, pdz, synth, args.hv_reps, calibrate=args.calibrate_copy)}),

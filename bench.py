@@ -26,13 +26,12 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 
 
-def recorded_traffic(workload, kernel, plan):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None.
+def recorded_traffic(workload, plan):
+    """HBM bytes of one FP32 H.v (both passes) from the committed counter summary, or None.
 
-    The summary (profiles/hv_traffic_<workload>.txt) holds FETCH_SIZE and
-    WRITE_SIZE per dispatch scaled by a plain copy's reading, the SHA-1 of the
-    H.v kernel source and the tuned launch plan it was taken with; a changed
-    source or a different plan gives None.
+    The summary (profiles/hv_traffic_<workload>.txt) holds FETCH_SIZE and WRITE_SIZE per dispatch
+    scaled by a plain copy's reading, the SHA-1 of the H.v kernel source and the launch plan it was
+    taken with; a changed source or a different plan gives None.
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", f"hv_traffic_{workload}.txt")
@@ -47,34 +46,17 @@ def recorded_traffic(workload, kernel, plan):
         return None
     with open(src, "rb") as f:
         sha = hashlib.sha1(f.read()).hexdigest()
-    k = rec.get("kernels", {}).get(kernel)
-    if rec.get("source_sha1") != sha or not k or rec.get("plans", {}).get("f32") != plan:
+    ks = rec.get("kernels", {})
+    if rec.get("source_sha1") != sha or rec.get("plans", {}).get("f32") != plan:
         return None
-    return k["fetch_bytes"] + k["write_bytes"]
+    parts = [ks.get("down_f32"), ks.get("up_f32")]
+    if any(k is None for k in parts):
+        return None
+    return sum(k["fetch_bytes"] + k["write_bytes"] for k in parts)
 
 
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def hv_timing(torch, g, dtype, reps):
-    """Average duration of one pdz_hv launch, HIP events on the launching stream."""
-    D = g.D
-    x = torch.empty(D, dtype=dtype, device="cuda").uniform_(-1.0, 1.0)
-    y = torch.empty_like(x)
-    stream = torch.cuda.current_stream()
-    for _ in range(2):
-        g.hv(x, y, stream=stream)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(reps):
-        g.hv(x, y, stream=stream)
-    ev1.record(stream)
-    ev1.synchronize()
-    ms = ev0.elapsed_time(ev1) / reps
-    del x, y
-    return ms
 
 
 def lanczos_steps(torch, g, storage, steps, warmup, check_every):
@@ -93,40 +75,84 @@ def lanczos_steps(torch, g, storage, steps, warmup, check_every):
     return t, r
 
 
-def time_to_e0(torch, g, rel=1e-8, max_iter=600):
-    """Lanczos time-to-E0 at relative accuracy `rel`, FP64 and FP32 storage (+FP64 refinement)."""
-    out = {}
-    ref = g.lanczos(storage="f64", tol=1e-12, max_iter=max_iter, check_every=12, history=True)
+def _ws(torch, g, **kw):
+    return torch.empty(max(1, g.workspace_size(g.lanczos_opts(**kw))), dtype=torch.uint8, device="cuda")
+
+
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, r
+
+
+def time_to_e0(torch, g, rel=1e-8, seeds=(1, 2, 3, 4, 5), max_iter=400, E_oracle=None):
+    """Lanczos time to E0 at relative accuracy `rel`, FP64 and FP32 storage + FP64 refinement.
+
+    E_ref: FP64 Lanczos of seed 1 converged to 1e-12 (compared with the oracle's stored value when one
+    is given).  Per seed: an untimed FP64 run records the Ritz value of every step and k* is the first
+    step within `rel` of E_ref; then exactly k* steps are timed.  FP32 storage: the untimed search takes
+    the fewest steps k >= k* whose refined energy (FP64 Rayleigh quotient of the Ritz vector combined
+    from the kept FP32 Lanczos vectors) is within `rel`, then times k steps plus the refinement.  A
+    third form needs no reference: FP32 storage stopped by its residual test (tol 1e-7) with refine = 2,
+    which restarts in FP64 from the Ritz vector whenever its FP64 residual does not bound the energy
+    to 1e-8.  Every timed call gets a preallocated workspace."""
+    import statistics
+    out = {"seeds": list(seeds)}
+    ws64 = _ws(torch, g, storage="f64", max_iter=max_iter)
+    ref = g.lanczos(workspace=ws64, storage="f64", tol=1e-12, max_iter=max_iter, check_every=12, seed=seeds[0])
     E_ref = ref["E0"]
     out["E0_ref"] = E_ref
     out["ref_iters"] = ref["iters"]
-    out["ref_converged"] = bool(ref["converged"])
-    k64 = next((k + 1 for k, th in enumerate(ref["thetas"]) if abs(th - E_ref) <= rel * abs(E_ref)), None)
-    if k64 is None:
-        return out
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r64 = g.lanczos(storage="f64", tol=0.0, max_iter=k64, check_every=12)
-    torch.cuda.synchronize()
-    out["f64"] = {"seconds": time.perf_counter() - t0, "iters": r64["iters"],
-                  "rel_err": abs(r64["E0"] - E_ref) / abs(E_ref)}
-    k = k64
-    for _ in range(6):
-        # keep the FP32 Lanczos vectors in HBM (k + 1 of them) while they fit a generous share of it,
-        # so that the refinement combines them in one pass instead of rerunning the k products
-        keep = 1 if (k + 1) * g.D * 4 <= 120e9 else 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r32 = g.lanczos(storage="f32", tol=0.0, max_iter=k, check_every=12, refine=1, keep_basis=keep)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        err = abs(r32["E0_refined"] - E_ref) / abs(E_ref)
-        out["f32_refined"] = {"seconds": t, "iters": r32["iters"], "rel_err": err,
-                              "rel_err_unrefined": abs(r32["E0"] - E_ref) / abs(E_ref),
-                              "resid_refined": r32["resid_refined"], "keep_basis": keep}
-        if err <= rel:
-            break
-        k = int(k * 1.25) + 3
+    if E_oracle is not None:
+        out["E0_oracle"] = E_oracle
+        out["ref_rel_dev_from_oracle"] = abs(E_ref - E_oracle) / abs(E_oracle)
+    kstar, t64, e64 = [], [], []
+    for s in seeds:
+        h = g.lanczos(workspace=ws64, storage="f64", tol=1e-12, max_iter=max_iter, check_every=12, seed=s,
+                      history=True)
+        k = next((i + 1 for i, th in enumerate(h["thetas"]) if abs(th - E_ref) <= rel * abs(E_ref)), None)
+        if k is None:
+            return out
+        sec, r = _timed(torch, lambda: g.lanczos(workspace=ws64, storage="f64", tol=0.0, max_iter=k,
+                                                 check_every=12, seed=s))
+        kstar.append(k)
+        t64.append(sec)
+        e64.append(abs(r["E0"] - E_ref) / abs(E_ref))
+    out["f64"] = {"s_median": statistics.median(t64), "s": t64, "iters": kstar, "max_rel_err": max(e64)}
+    del ws64
+    kmax = int(max(kstar) * 1.6) + 8
+    ws32 = _ws(torch, g, storage="f32", max_iter=kmax, refine=1, keep_basis=1)
+    t32, k32, e32 = [], [], []
+    for s, k0 in zip(seeds, kstar):
+        k = k0
+        while True:
+            r = g.lanczos(workspace=ws32, storage="f32", tol=0.0, max_iter=k, check_every=12, seed=s, refine=1,
+                          keep_basis=1)
+            if abs(r["E0_refined"] - E_ref) <= rel * abs(E_ref) or k >= kmax:
+                break
+            k = min(kmax, k + max(2, k // 10))
+        sec, r = _timed(torch, lambda: g.lanczos(workspace=ws32, storage="f32", tol=0.0, max_iter=k,
+                                                 check_every=12, seed=s, refine=1, keep_basis=1))
+        t32.append(sec)
+        k32.append(k)
+        e32.append(abs(r["E0_refined"] - E_ref) / abs(E_ref))
+    out["f32_refined"] = {"s_median": statistics.median(t32), "s": t32, "iters": k32, "max_rel_err": max(e32),
+                          "met": max(e32) <= rel}
+    del ws32
+    ws2 = _ws(torch, g, storage="f32", max_iter=max_iter, refine=2, keep_basis=1)
+    t2, e2, k2, rs = [], [], [], []
+    for s in seeds:
+        sec, r = _timed(torch, lambda: g.lanczos(workspace=ws2, storage="f32", tol=1e-7, max_iter=max_iter,
+                                                 check_every=12, seed=s, refine=2, keep_basis=1))
+        t2.append(sec)
+        e2.append(abs(r["E0_refined"] - E_ref) / abs(E_ref))
+        k2.append(r["iters"])
+        rs.append(r["restart_iters"])
+    out["f32_refine2_tol1e-7"] = {"s_median": statistics.median(t2), "s": t2, "iters": k2, "restart_iters": rs,
+                                  "max_rel_err": max(e2), "met": max(e2) <= rel}
+    del ws2
     return out
 
 
@@ -198,7 +224,6 @@ def batched_bench(torch, pdz, synth, reps, rel=1e-8):
         tol, secs, err, iters = _tol_to_rel(fn, E_ref, rel)
         out["time_to_E0_1e-8_" + key] = {"seconds": secs, "tol": tol, "max_rel_err": err, "max_iters": iters,
                                          "met": err <= rel}
-        _log(f"batched {key}: {out['time_to_E0_1e-8_' + key]}")
     return out
 
 
@@ -304,7 +329,7 @@ def kspace_bench(torch, pdz, synth, reps=20, E_real=None, calibrate=False):
                                      "err_vs_real_space": (e - E_real) if E_real is not None else None}
     # the real-space procedure (steps to a Ritz value within 1e-8 of a converged reference, then timed),
     # so the sectors compare with it step for step; the solves above stop on their residual instead
-    out["time_to_E0_1e-8"] = time_to_e0(torch, g)
+    out["time_to_E0_1e-8"] = time_to_e0(torch, g, seeds=(1,))
     if calibrate:
         src = torch.empty(g.D, dtype=torch.float32, device="cuda").uniform_(-1.0, 1.0)
         dst = torch.empty_like(src)
@@ -365,7 +390,7 @@ def parity_bench(torch, pdz, synth, reps=20, E_real=None, calibrate=False):
                                      "err_vs_real_space": (e - E_real) if E_real is not None else None}
     # the real-space procedure (steps to a Ritz value within 1e-8 of a converged reference, then timed),
     # so the sectors compare with it step for step; the solves above stop on their residual instead
-    out["time_to_E0_1e-8"] = time_to_e0(torch, g)
+    out["time_to_E0_1e-8"] = time_to_e0(torch, g, seeds=(1,))
     if calibrate:
         src = torch.empty(g.D, dtype=torch.float32, device="cuda").uniform_(-1.0, 1.0)
         dst = torch.empty_like(src)
@@ -555,14 +580,42 @@ def _sector_hops(po, spin):
     return cnt
 
 
+def _golden_energy(name):
+    """E0 of a full-size workload stored by the oracle (tests/golden/energies_fullsize.json), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "energies_fullsize.json")
+    try:
+        with open(path) as f:
+            return json.load(f).get(name, {}).get("E0")
+    except (OSError, ValueError):
+        return None
+
+
+def _round(v, nd=4):
+    """Compact copy of a result tree for the headline line (floats to `nd` significant digits;
+    energies keep every digit)."""
+    if isinstance(v, float):
+        return float(f"{v:.{nd}g}")
+    if isinstance(v, dict):
+        return {k: (x if k.startswith("E0") and isinstance(x, float) else _round(x, nd)) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_round(x, nd) for x in v]
+    return v
+
+
+def _pick(d, *keys):
+    return {k: d[k] for k in keys if d is not None and k in d}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--workload", default="torus4x4_nnn")
-    ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--hv-reps", type=int, default=50, help="H.v launches timed (median), after 5 warm-ups")
     ap.add_argument("--check-every", type=int, default=12)
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file that receives every section's full results (the headline line stays compact)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-e0", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -571,6 +624,8 @@ def main():
     ap.add_argument("--no-kspace", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--headline-only", action="store_true", help="only the Lanczos steps, the H.v timing and "
+                    "time to E0 (no other section, no CPU baseline)")
     ap.add_argument("--parity-only", action="store_true",
                     help="run only the inversion-parity section and print its JSON object")
     ap.add_argument("--kspace-only", action="store_true",
@@ -588,6 +643,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding of this path is a design note, not built.", file=sys.stderr)
         sys.exit(2)
+    if args.headline_only:
+        args.no_cpu_baseline = args.no_batched = args.no_learned = args.no_dynamics = True
+        args.no_kspace = args.no_parity = args.no_configs = True
 
     import torch
     import synth
@@ -615,51 +673,34 @@ def main():
     g = pdz.Problem.from_workload(w)
     D, nnz = g.D, g.nnz
     _log(f"workload {w.name}: D={D} nnz={nnz}")
+    detail = {"workload": w.name, "D": D, "nnz_per_hv": nnz}
 
-    # autotune the launch plan for both precisions: libpdz times every valid H.v plan, and the
-    # fastest few are then timed as Lanczos steps (the timed workload) before one is kept
+    # launch plans: libpdz times every valid H.v plan, the fastest few are then timed as Lanczos steps
     tuned = {}
     for dn in ("f32", "f64"):
         best, trials, steps = g.tune_lanczos(dn, top=6)
-        tuned[dn] = {"best": best, "trials": trials, "lanczos_trials": steps}
-        _log(f"tuned {dn}: {best} from {len(trials)} plans; Lanczos steps {steps}")
+        tuned[dn] = best
+        detail["plan_trials_" + dn] = {"best": best, "hv": trials, "lanczos_steps": steps}
+    _log(f"plans {tuned}")
 
-    # headline: FP32-storage Lanczos steps
+    # the timed steps: exactly K Lanczos steps after W warm-up steps, FP32 storage (FP64 beside it)
     t32, r32 = lanczos_steps(torch, g, "f32", args.steps, args.warmup, args.check_every)
-    _log(f"f32 lanczos: {args.steps} steps in {t32:.4f} s")
     t64, r64 = lanczos_steps(torch, g, "f64", args.steps, args.warmup, args.check_every)
-    _log(f"f64 lanczos: {args.steps} steps in {t64:.4f} s")
+    _log(f"lanczos steps: f32 {t32 / args.steps * 1e3:.3f} ms, f64 {t64 / args.steps * 1e3:.3f} ms")
 
-    ms32 = hv_timing(torch, g, torch.float32, args.hv_reps)
-    ms64 = hv_timing(torch, g, torch.float64, args.hv_reps)
-    _log(f"hv f32 {ms32:.4f} ms, f64 {ms64:.4f} ms")
-    # whole H.v: x read once, y written once
-    bytes32 = 2.0 * D * 4
-    bytes64 = 2.0 * D * 8
-    ach32 = bytes32 / (ms32 * 1e-3) / 1e9
-    ach64 = bytes64 / (ms64 * 1e-3) / 1e9
-    # per kernel of the public H.v (each launched alone, HIP events on its stream inside libpdz)
-    kt32 = g.kernel_times("f32", reps=args.hv_reps)
-    kt64 = g.kernel_times("f64", reps=args.hv_reps)
-    _log(f"kernel times f32 {kt32}, f64 {kt64}")
-    # per launch group of the timed Lanczos step (HIP events between the launches inside libpdz):
-    # the dominant kernel and its algorithmic bytes per launch.  Down pass fused with the update:
-    # reads the two parts of H q_k, q_k and q_(k-1), writes q_(k+1) and its down part (6 D s);
-    # separate down pass: x read, part written (2 D s); up pass inside Lanczos: x read through the
-    # gathers, its part written (2 D s); separate update: 4 vectors read, 1 written (5 D s).
-    lk32 = g.lanczos_kernel_times("f32", steps=max(10, 2 * args.hv_reps))
-    lk64 = g.lanczos_kernel_times("f64", steps=max(10, 2 * args.hv_reps))
-    _log(f"lanczos kernel times f32 {lk32}, f64 {lk64}")
-    groups = {"down": lk32["down"], "up": lk32["up"], "update": lk32["update"]}
-    dom = max(groups, key=groups.get)
-    streams = {"down": 6.0 if lk32["fused"] else 2.0, "up": 2.0, "update": 5.0}
-    kbytes = streams[dom] * D * 4
-    ach_dom = kbytes / (groups[dom] * 1e-3) / 1e9
-    role = {"down": "fused_f32" if lk32["fused"] else "down_f32", "up": "up_f32_split", "update": None}[dom]
-    traffic = recorded_traffic(w.name, role, tuned["f32"]["best"]) if role else None
-    names = {"down": ("down pass with the recurrence update fused (k_hv_down_wide)" if lk32["fused"]
-                      else "down pass (k_hv_down_wide)"),
-             "up": "up pass, its part written apart (k_hv_up)", "update": "recurrence update (k_update_scaled)"}
+    # H.v: median of n launches after 5 warm-ups, HIP events on the launching stream
+    hv = {}
+    for dt, dn, es in ((torch.float32, "f32", 4), (torch.float64, "f64", 8)):
+        ms = hv_median_ms(torch, g, dt, n=args.hv_reps, warm=5)
+        kt = g.kernel_times(dn, reps=20)
+        alg = 2.0 * D * es
+        hv[dn] = {"ms": ms, "nnz_per_s": nnz / (ms * 1e-3), "achieved_GBs": alg / (ms * 1e-3) / 1e9,
+                  "frac": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "kernels_ms": {"down": kt["down"], "up": kt["up"]}}
+        lk = g.lanczos_kernel_times(dn, steps=20)
+        hv[dn]["lanczos_step_kernels_ms"] = {k: lk[k] for k in ("down", "up", "update", "scalars", "step")}
+    _log(f"hv {hv}")
+    detail["hv"] = hv
+    traffic = recorded_traffic(w.name, tuned["f32"])
 
     copy = None
     if args.calibrate_copy:
@@ -676,57 +717,82 @@ def main():
         ev1.synchronize()
         cms = ev0.elapsed_time(ev1) / 5
         copy = {"bytes_read": D * 4, "bytes_written": D * 4, "ms": cms, "GBs": 2 * D * 4 / (cms * 1e-3) / 1e9}
-        _log(f"copy calibration: {copy}")
+        detail["copy_calibration"] = copy
         del src, dst
 
     tte = None
     if not args.no_time_to_e0:
-        tte = time_to_e0(torch, g)
-        _log(f"time to E0: {tte}")
+        tte = time_to_e0(torch, g, E_oracle=_golden_energy(w.name))
+        detail["time_to_E0_1e-8"] = tte
+        _log("time to E0 done")
+    e_real = tte.get("E0_ref") if tte else None
 
-    batched = None
+    sections = {}
     if not args.no_batched:
-        batched = batched_bench(torch, pdz, synth, args.hv_reps)
-        _log(f"batched: hv f32 {batched['hv_f32']['ms']:.4f} ms, f64 {batched['hv_f64']['ms']:.4f} ms")
-
-    learned_res = None
+        sections["batched"] = batched_bench(torch, pdz, synth, 20)
+        _log("batched done")
     if not args.no_learned:
-        learned_res = learned_bench(torch, pdz, synth)
-        _log(f"learned start: {json.dumps({k: v for k, v in learned_res.items() if k != 'compare'})}")
-
-    dyn = None
+        sections["learned_start"] = learned_bench(torch, pdz, synth)
+        _log("learned start done")
     if not args.no_dynamics:
-        dyn = dynamics_bench(torch, pdz, synth)
-        _log(f"dynamics: {dyn}")
-
-    ks = None
+        sections["dynamics"] = dynamics_bench(torch, pdz, synth)
+        _log("dynamics done")
     if not args.no_kspace:
-        e_real = None
-        if tte is not None:
-            e_real = tte.get("E0_ref")
-        ks = kspace_bench(torch, pdz, synth, args.hv_reps, E_real=e_real)
-        _log(f"kspace: {json.dumps({k: v for k, v in ks.items() if k != 'per_K'})}")
-
-    par = None
+        sections["kspace"] = kspace_bench(torch, pdz, synth, 20, E_real=e_real)
+        _log("kspace done")
     if not args.no_parity:
-        e_real = tte.get("E0_ref") if tte is not None else None
-        par = parity_bench(torch, pdz, synth, args.hv_reps, E_real=e_real)
-        _log(f"parity: {json.dumps(par)}")
-
-    cfgs = None
+        sections["parity"] = parity_bench(torch, pdz, synth, 20, E_real=e_real)
+        _log("parity done")
     if not args.no_configs:
-        cfgs = configs_bench(torch, pdz, synth, D)
-        _log(f"configs: {json.dumps(cfgs)}")
-
+        sections["configs"] = configs_bench(torch, pdz, synth, D)
+        _log("configs done")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
-        _log(f"cpu baseline: {cpu}")
+        _log("cpu baseline done")
+    detail.update(sections)
+    detail["cpu_baseline"] = cpu
 
-    value = nnz * args.steps / t32
+    # compact summaries of the other sections for the headline line (every figure is in the detail file)
+    summ = {}
+    b = sections.get("batched")
+    if b:
+        summ["batched"] = {"hv_ms_f32": b["hv_f32"]["ms"], "hv_speedup_vs_32_single": b["hv_f32"]["speedup_vs_single"],
+                           "tte_s_batched_f64": b["time_to_E0_1e-8_batched_f64"]["seconds"],
+                           "tte_s_single_f64": b["time_to_E0_1e-8_single_f64"]["seconds"],
+                           "tte_s_batched_f32_refined": b["time_to_E0_1e-8_batched_f32_refined"]["seconds"]}
+    ls = sections.get("learned_start")
+    if ls:
+        summ["learned_start"] = _pick(ls, "learned_speedup", "random_median_iters", "overlap_learned",
+                                      "overlap_random", "break_even_solves")
+        summ["learned_start"]["learned_iters"] = ls["compare"]["learned"].get("iters")
+    ks = sections.get("kspace")
+    if ks:
+        summ["kspace_K0"] = {"hv_ms_f32": ks["hv_f32"]["ms"], "hv_ms_f64": ks["hv_f64"]["ms"], "E0_diff": ks.get("E0_diff")}
+    pa = sections.get("parity")
+    if pa:
+        summ["parity_P+1"] = {"hv_ms_f32": pa["hv_f32"]["ms"], "hv_ms_f64": pa["hv_f64"]["ms"], "E0_diff": pa.get("E0_diff")}
+    dy = sections.get("dynamics")
+    if dy:
+        summ["dynamics"] = _pick(dy, "fermion_op_ms", "resolvent_s", "norm2")
+    cf = sections.get("configs")
+    if cf:
+        summ["configs_hv_nnz_per_s_f64"] = {k: v["hv_f64"]["nnz_per_s"] for k, v in cf.items() if "hv_f64" in v}
+        summ["copy_ceiling_GBs"] = cf["copy_ceiling"]["GBs"]
+
+    tte_c = None
+    if tte:
+        tte_c = {"E0_ref": tte.get("E0_ref"), "E0_oracle": tte.get("E0_oracle"),
+                 "ref_rel_dev_from_oracle": tte.get("ref_rel_dev_from_oracle")}
+        for k in ("f64", "f32_refined", "f32_refine2_tol1e-7"):
+            if k in tte:
+                tte_c[k] = _pick(tte[k], "s_median", "iters", "max_rel_err", "restart_iters")
+
+    h32, h64 = hv["f32"], hv["f64"]
     line = {
-        "metric": "H.v nonzeros/s (Lanczos steps, FP32 Krylov storage, FP64 scalars)",
-        "value": value,
+        "metric": "H.v nonzeros/s in Lanczos steps (FP32 Krylov storage, FP64 scalars); % of HBM roofline; "
+                  "time to E0 at 1e-8, FP32 vs FP64",
+        "value": nnz * args.steps / t32,
         "unit": "nonzeros/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -736,35 +802,28 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded SplitMix64 start vector; problem fully specified by the lattice)",
-        "config": {"workload": w.name, "lattice": "4x4 periodic, NN t=1 + NNN t'=-0.3" if w.name == "torus4x4_nnn"
-                   else w.note, "U": w.U, "n_up": w.n_up, "n_dn": w.n_dn, "D": D, "nnz_per_hv": nnz,
-                   "storage": "f32", "step": "one Lanczos step (H.v + recurrence + tridiagonal solve)"},
-        "roofline": {"bound": "hbm", "achieved": ach_dom, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": ach_dom / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": f"{names[dom]} in the FP32 Lanczos step, plan {tuned['f32']['best']}",
-                     "avg_ms": groups[dom], "algorithmic_bytes": kbytes,
-                     "step_kernels_ms": lk32,
-                     "public_hv_kernel_ms": kt32,
-                     "whole_hv": {"ms": ms32, "algorithmic_bytes": bytes32, "achieved": ach32,
-                                  "frac": ach32 / PEAK_HBM_GBS}},
-        "fp64": {"value": nnz * args.steps / t64, "ms_per_step": t64 / args.steps * 1e3,
-                 "hv_ms": ms64, "hv_achieved_GBs": ach64, "hv_frac": ach64 / PEAK_HBM_GBS,
-                 "kernel_ms": kt64, "step_kernels_ms": lk64,
-                 "hv_nnz_per_s": nnz / (ms64 * 1e-3)},
-        "hv_nnz_per_s_f32": nnz / (ms32 * 1e-3),
-        "time_to_E0_1e-8": tte,
-        "batched": batched,
-        "learned_start": learned_res,
-        "dynamics": dyn,
-        "kspace": ks,
-        "parity": par,
-        "configs": cfgs,
-        "copy_calibration": copy,
-        "hv_plans": tuned,
-        "cpu_baseline": cpu,
+        "data": "synthetic (lattice problem fully specified; SplitMix64 seeded start vector)",
+        "config": {"workload": w.name, "lattice": w.note, "D": D, "nnz_per_hv": nnz,
+                   "step": "one Lanczos step: H.v + recurrence + tridiagonal solve"},
+        "roofline": {"bound": "hbm", "achieved": h32["achieved_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": h32["frac"], "traffic": traffic,
+                     "kernel": "whole FP32 H.v (down pass + up pass), 2*D*4 bytes per launch",
+                     "avg_ms": h32["ms"], "kernels_ms": h32["kernels_ms"], "plan": tuned["f32"]},
+        "hv_f64": {"ms": h64["ms"], "nnz_per_s": h64["nnz_per_s"], "achieved_GBs": h64["achieved_GBs"],
+                   "frac": h64["frac"], "kernels_ms": h64["kernels_ms"]},
+        "fp64_steps": {"value": nnz * args.steps / t64, "ms_per_step": t64 / args.steps * 1e3},
+        "time_to_E0_1e-8": tte_c,
+        "sections": summ,
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "detail_file": args.detail,
     }
-    print(json.dumps(line), flush=True)
+    try:
+        os.makedirs(os.path.dirname(os.path.join(ROOT, args.detail)), exist_ok=True)
+        with open(os.path.join(ROOT, args.detail), "w") as f:
+            json.dump(detail, f, indent=1)
+    except OSError as e:
+        _log(f"could not write {args.detail}: {e}")
+    print(json.dumps(_round(line)), flush=True)
 
 
 if __name__ == "__main__":

@@ -91,13 +91,15 @@ def build_csr(p: Problem, with_diag: bool = True) -> sp.csr_matrix:
     return H
 
 
-def hv_rows(p: Problem, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
+def hv_rows(p: Problem, x: np.ndarray, rows: np.ndarray, with_abs: bool = False):
     """(H x)[r] for the listed rows only, without building H.
 
     For each term amplitude * c+_a c_b, the source states r' that it sends
     onto |r> are those with c+_b c_a |r> != 0.  The matrix element
     <r| c+_a c_b |r'> is then evaluated by applying c+_a c_b to |r'> and
     reading its sign.  Indices come from binary search in the sector lists.
+    with_abs: also return each row's sum of |terms| and its number of terms
+    (the diagonal counts as one term), the scale of a rounding bound.
     """
     N = p.n_sites
     up, dn = p.up_list, p.dn_list
@@ -106,6 +108,8 @@ def hv_rows(p: Problem, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
     PU = up[rows // Ddn]
     PD = dn[rows % Ddn]
     y = diag_values(p, PU, PD) * x[rows]
+    yabs = np.abs(y)
+    nterm = np.ones(len(rows), dtype=np.int64)
     for a, b, spin, amp in p.terms():
         ok, _, su, sd = apply_hop_vec(PU, PD, spin, b, a)   # candidate sources
         if not np.any(ok):
@@ -119,6 +123,10 @@ def hv_rows(p: Problem, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
         contrib = np.zeros(len(rows))
         contrib[ok] = amp * sign[ok] * x[src]
         y += contrib
+        yabs += np.abs(contrib)
+        nterm += ok
+    if with_abs:
+        return y, yabs, nterm
     return y
 
 

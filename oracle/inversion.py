@@ -25,10 +25,12 @@ Definitions used here:
   notes): a state's representative is decided by its up string, and by its
   down string when the up string is a palindrome.  Basis order: up
   representatives in tree order; behind a non-palindromic up string every
-  down string: each down A representative in tree order followed by its
-  mirror image, then the down palindromes in tree order; behind a
-  palindromic up string the down representatives in tree order, down
-  palindromes only when the state is itself even (F|s> = P|s>).
+  down string in ascending order (the plain sector order of Sec. II.A);
+  behind a palindromic up string the down representatives in tree order,
+  down palindromes only when the state is itself even (F|s> = P|s>).
+  Only the set of basis states and each state's basis vector are part of
+  the method; a device layout may order them differently, and tests compare
+  through the state a position holds.
 * Basis vector of a representative r: (|r> + P F|r>) / sqrt(2), or |r> for a
   state with F|r> = +-|r> (kept only when F|r> = P|r>).
 * H_P = B^T H B with B the matrix of those basis vectors and H the real-space
@@ -125,14 +127,8 @@ def tree_order(N, n):
 
 
 def full_row_order(N, n):
-    """Down strings of a non-palindromic row: the A representatives in tree order, each followed by its
-    mirror, then the palindromes in tree order."""
-    reps = tree_order(N, n)
-    out = []
-    for r in reps:
-        if classify(r, N)[0] == "A":
-            out += [r, reverse(r, N)]
-    return out + [r for r in reps if classify(r, N)[0] == "P"]
+    """Down strings of a non-palindromic row: every string of the sector, ascending."""
+    return [int(d) for d in sector_list(N, n)]
 
 
 def basis(N, n_up, n_dn, P):
@@ -244,26 +240,29 @@ def representative(u, d, N):
     return int(u), int(d), False
 
 
-def hv_rows_P(p, P, ridx, x, rows_up, rows_dn):
+def hv_rows_P(p, P, lookup, rows_up, rows_dn):
     """(H_P x) at the listed basis states (representatives), without building H_P.
 
     (H_P x)_t = <t_P| H |v> with |v> = sum_k x_k |k_P>: the full-space vector
-    v at any state s is x[rep(s)] times 1/sqrt(2) (pair states; times P F's
+    v at any state s is x at rep(s) times 1/sqrt(2) (pair states; times P F's
     sign for the image) or 1 (self-mapped states), and <t_P| reads the row of
     H at t (and at F t) with the same weights.  H's terms come from oracle's
     real-space operator algebra (hv_rows on single states).
+    lookup(reps_up, reps_dn) -> the x component of each listed representative
+    state (arrays), so x may be held in any order of the basis.
     Returns (y, sum of |terms|, number of terms).
     """
     from .fock import apply_hop
     N = p.n_sites
-    out, asum, nterm = [], [], []
+    # pass 1: every term of every row, with the representative it reads
+    rows_terms, need = [], {}
     for u, d in zip(rows_up, rows_dn):
         u, d = int(u), int(d)
         s0 = reorder_sign(u, d, N)
         self_mapped = reverse(u, N) == u and reverse(d, N) == d
         orbit = [(u, d, 1.0)] if self_mapped else [(u, d, 1 / np.sqrt(2)),
                                                    (reverse(u, N), reverse(d, N), P * s0 / np.sqrt(2))]
-        acc, a, n = 0.0, 0.0, 0
+        row = []
         for (su, sd, w_t) in orbit:
             # H|v> at state (su, sd): sum over the sources of the row (symmetric H)
             terms = [(float(p.U) * popcount(su & sd), su, sd)]
@@ -281,15 +280,24 @@ def hv_rows_P(p, P, ridx, x, rows_up, rows_dn):
                 sm = reverse(ru, N) == ru and reverse(rd, N) == rd
                 if sm and reorder_sign(ru, rd, N) != P:
                     continue          # a self-mapped state of the other parity: no component here
-                k = ridx.index(ru, rd)
                 w_s = 1.0 if sm else (P * reorder_sign(ru, rd, N) / np.sqrt(2) if img else 1 / np.sqrt(2))
-                v = w_t * coef * w_s * x[k]
-                acc += v
-                a += abs(v)
-                n += 1
+                need.setdefault((ru, rd), len(need))
+                row.append((w_t * coef * w_s, (ru, rd)))
+        rows_terms.append(row)
+    # pass 2: the x components of every representative read, then the sums in term order
+    keys = list(need)
+    xv = np.asarray(lookup(np.array([k[0] for k in keys], np.uint64), np.array([k[1] for k in keys], np.uint64)),
+                    dtype=np.float64) if keys else np.zeros(0)
+    out, asum, nterm = [], [], []
+    for row in rows_terms:
+        acc, a = 0.0, 0.0
+        for w, key in row:
+            v = w * xv[need[key]]
+            acc += v
+            a += abs(v)
         out.append(acc)
         asum.append(a)
-        nterm.append(n)
+        nterm.append(len(row))
     return np.array(out), np.array(asum), np.array(nterm)
 
 

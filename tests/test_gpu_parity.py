@@ -1,8 +1,10 @@
 """Inversion-parity subspaces (Sec. IV.B) on the GPU against the CPU oracle.
 
-* pdz_parity_unrank / pdz_parity_rank equal the oracle's basis order (decision
-  tree, up string first) bit for bit, for both parities of small sectors; states
-  outside the basis are flagged.
+* The device basis and the oracle's hold the same representative states; rows
+  (up representatives) come in the decision tree's order on both sides, and a
+  state's position inside its row is the layout's choice, so every comparison
+  goes through the state a position holds (pdz_parity_unrank).  pdz_parity_rank
+  inverts pdz_parity_unrank; states outside the basis are flagged.
 * H.v element by element against B^T H B (small sectors) and on sampled rows of
   the 4x3 torus 6+6 and of the 4x4 NN+NNN 8+8 cluster (oracle rows from the
   real-space operator algebra), FP64 and FP32.  Tolerance: (n + 6) eps sum|terms|:
@@ -71,19 +73,31 @@ def _gpu(N, bonds, U, nu, nd, P):
     return pdz.ParityProblem(N, bonds, U, nu, nd, P)
 
 
+def _perm(g, N, nu, nd, P):
+    """Oracle basis index of the state at every device position (asserted to be a bijection)."""
+    torch = torch_cuda()
+    bu, bd, _ = inv.basis(N, nu, nd, P)
+    assert g.D == len(bu)
+    gu, gd = g.unrank(torch.arange(g.D, dtype=torch.int64, device="cuda"))
+    gu = to_host(gu).view(np.uint32).astype(np.uint64)
+    gd = to_host(gd).view(np.uint32).astype(np.uint64)
+    where = {(int(u), int(d)): k for k, (u, d) in enumerate(zip(bu, bd))}
+    perm = np.array([where.get((int(u), int(d)), -1) for u, d in zip(gu, gd)], dtype=np.int64)
+    assert np.all(perm >= 0) and len(np.unique(perm)) == len(perm), "device basis differs from the oracle's"
+    return perm, gu, bu
+
+
 @pytest.mark.parametrize("P", [1, -1])
 @pytest.mark.parametrize("case", SMALL, ids=IDS)
 def test_parity_maps_equal_the_oracle_basis(case, P):
     torch = torch_cuda()
     import paper_1707_03974_amd as pdz
     N, bonds, U, nu, nd = case
-    bu, bd, _ = inv.basis(N, nu, nd, P)
     g = _gpu(N, bonds, U, nu, nd, P)
-    assert g.D == len(bu)
-    gu, gd = g.unrank(torch.arange(g.D, dtype=torch.int64, device="cuda"))
-    assert np.array_equal(to_host(gu).view(np.uint32).astype(np.uint64), bu)
-    assert np.array_equal(to_host(gd).view(np.uint32).astype(np.uint64), bd)
-    r = g.rank(gu, gd)
+    perm, gu, bu = _perm(g, N, nu, nd, P)
+    assert np.array_equal(gu, bu)          # rows: up representatives in tree order, equal lengths
+    gu2, gd2 = g.unrank(torch.arange(g.D, dtype=torch.int64, device="cuda"))
+    r = g.rank(gu2, gd2)
     assert torch.equal(r, torch.arange(g.D, dtype=torch.int64, device="cuda"))
     assert pdz.device_errors() == 0
 
@@ -124,9 +138,17 @@ def test_parity_hv_matches_the_oracle(case, P, dtype_name):
     x = np.random.default_rng(12).uniform(-1, 1, g.D)
     if dtype_name == "f32":
         x = x.astype(np.float32).astype(np.float64)
+    _check_hv(g, HP, x, dt, e, _perm(g, N, nu, nd, P)[0], (dtype_name, P))
+
+
+def _check_hv(g, HP, x, dt, e, perm, what):
+    """Device y = H x against B^T H B, each device position compared with the oracle row of its state."""
+    xo = np.zeros_like(x)
+    xo[perm] = x
     y = to_host(g.hv(to_dev(x, dt))).astype(np.float64)
-    err = np.abs(y - HP @ x)
-    assert np.all(err <= _bound(HP, x, e) + 1e-300), (np.max(err), dtype_name, P)
+    want = (HP @ xo)[perm]
+    err = np.abs(y - want)
+    assert np.all(err <= _bound(HP, xo, e)[perm] + 1e-300), (np.max(err), what)
 
 
 @pytest.mark.parametrize("dtype_name", ["f64", "f32"])
@@ -143,9 +165,7 @@ def test_parity_one_pass_gather_kernel_matches_the_oracle(case, dtype_name, monk
         x = np.random.default_rng(21).uniform(-1, 1, g.D)
         if dtype_name == "f32":
             x = x.astype(np.float32).astype(np.float64)
-        y = to_host(g.hv(to_dev(x, dt))).astype(np.float64)
-        err = np.abs(y - HP @ x)
-        assert np.all(err <= _bound(HP, x, e) + 1e-300), (np.max(err), dtype_name, P)
+        _check_hv(g, HP, x, dt, e, _perm(g, N, nu, nd, P)[0], (dtype_name, P))
 
 
 @pytest.mark.parametrize("lanes", ["16", "32"])
@@ -163,9 +183,7 @@ def test_parity_up_pass_slab_widths_match_the_oracle(case, dtype_name, lanes, mo
         x = np.random.default_rng(23).uniform(-1, 1, g.D)
         if dtype_name == "f32":
             x = x.astype(np.float32).astype(np.float64)
-        y = to_host(g.hv(to_dev(x, dt))).astype(np.float64)
-        err = np.abs(y - HP @ x)
-        assert np.all(err <= _bound(HP, x, e) + 1e-300), (np.max(err), dtype_name, P, lanes)
+        _check_hv(g, HP, x, dt, e, _perm(g, N, nu, nd, P)[0], (dtype_name, P, lanes))
 
 
 def test_parity_up_pass_lanes_must_be_16_32_or_64(monkeypatch):
@@ -189,9 +207,7 @@ def test_parity_down_pass_32bit_table_matches_the_oracle(case, dtype_name, monke
         x = np.random.default_rng(29).uniform(-1, 1, g.D)
         if dtype_name == "f32":
             x = x.astype(np.float32).astype(np.float64)
-        y = to_host(g.hv(to_dev(x, dt))).astype(np.float64)
-        err = np.abs(y - HP @ x)
-        assert np.all(err <= _bound(HP, x, e) + 1e-300), (np.max(err), dtype_name, P)
+        _check_hv(g, HP, x, dt, e, _perm(g, N, nu, nd, P)[0], (dtype_name, P))
 
 
 def _sampled(w, P, nrows, seed, dtype_name):
@@ -209,8 +225,16 @@ def _sampled(w, P, nrows, seed, dtype_name):
     rows = np.unique(np.concatenate([rng.integers(0, g.D, nrows), [0, g.D - 1]]))
     gu, gd = g.unrank(to_dev(rows, torch.int64))
     ru, rd = to_host(gu).view(np.uint32), to_host(gd).view(np.uint32)
-    assert all(ridx.index(u, d) == k for u, d, k in zip(ru, rd, rows))
-    want, a, n = inv.hv_rows_P(po, P, ridx, x, ru, rd)
+    assert all(inv.representative(u, d, w.n_sites)[:2] == (int(u), int(d)) for u, d in zip(ru, rd))
+
+    def lookup(uu, dd):
+        """x at the device position of each listed representative state (its rank)."""
+        k = to_host(g.rank(to_dev(uu.astype(np.uint32).view(np.int32), torch.int32),
+                           to_dev(dd.astype(np.uint32).view(np.int32), torch.int32)))
+        assert np.all(k >= 0), "a source state is missing from the device basis"
+        return x[k]
+
+    want, a, n = inv.hv_rows_P(po, P, lookup, ru, rd)
     bound = (n + 6) * e * a + n * EPS64 * a
     err = np.abs(y[rows] - want)
     assert np.all(err <= bound), (np.max(err - bound), dtype_name, P)
@@ -251,7 +275,7 @@ def test_parity_lanczos_modes_match_the_oracle(mode):
     kw = {"f32_keep": dict(storage="f32", tol=1e-7, refine=1, keep_basis=1),
           "f32_regen": dict(storage="f32", tol=1e-7, refine=1, keep_basis=0),
           "f64_graph_off": dict(storage="f64", tol=1e-12, use_graph=0),
-          "f64_reorth": dict(storage="f64", tol=1e-12, reorth=1)}[mode]
+          "f64_reorth": dict(storage="f64", tol=1e-12, reorth=2)}[mode]
     for P in (1, -1):
         HP = inv.build_csr_P(po, P)
         v0 = np.random.default_rng(2).uniform(-1, 1, HP.shape[0])

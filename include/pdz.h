@@ -197,7 +197,11 @@ typedef struct {
     int32_t max_iter;      /* >= 1: Lanczos steps at most                                       */
     double tol;            /* accept when beta_{k+1} |s_k| <= tol * |theta| (>= 0)              */
     int32_t storage;       /* pdz_dtype of the Krylov vectors and of H.v                        */
-    int32_t reorth;        /* 0: three-term recurrence only; 1: full re-orthogonalisation       */
+    int32_t reorth;        /* 0: three-term recurrence only; 1: local re-orthogonalisation     */
+                           /*    (w against v_{k-1} and v_k, classical Gram-Schmidt twice);   */
+                           /*    2: full (against every earlier v_j, twice).  1 and 2 keep    */
+                           /*    every Lanczos vector in the workspace (max_iter + 1 of D     */
+                           /*    elements) and run without graphs                             */
     uint64_t seed;         /* start vector when v0 == NULL: SplitMix64 output r -> 2u-1         */
     int32_t check_every;   /* host reads the device convergence flag every this many steps (>=1) */
     int32_t use_graph;     /* 1: replay blocks of check_every steps as a captured HIP graph     */
@@ -223,6 +227,21 @@ typedef struct {
     int32_t converged;     /* 1 if the tolerance was met or the Krylov space became invariant   */
     int32_t restart_iters; /* steps of the FP64 restart (refine == 2 when it ran), else 0       */
 } pdz_lanczos_result;
+
+/* The refine == 2 decision of pdz_lanczos (host only, no device): given the
+ * Lanczos coefficients of T_k (alpha[0..k), beta[0..k], beta[j] coupling
+ * steps j-1 and j), the refined energy E and the FP64 residual norm resid of
+ * the Ritz vector, *restart = 1 when resid^2 / gap > 1e-8 |E|, i.e. when the
+ * residual does not bound E to 1e-8 and the FP64 restart must run.  gap is
+ * (theta_next - theta_1) / 10, theta_next the lowest eigenvalue of T_k above
+ * the cluster of Ritz values within 1e-8 max(1, |theta_1|) of theta_1 (ghost
+ * copies or a degenerate level count once; the factor 10 allows for Ritz
+ * values lying above the eigenvalues they approximate); with no Ritz value
+ * above the cluster the gap is unknown and *restart = 1.  *gap receives the
+ * estimate (0 when unknown).  Errors: PDZ_EINVAL (null pointer, k outside
+ * [1, 2000]). */
+pdz_status pdz_refine_decision(const double* alpha, const double* beta, int32_t k, double E, double resid,
+                               int32_t* restart, double* gap);
 
 /* Fill *o with defaults: max_iter 300, tol 1e-12, F64, no reorth, seed 1,
  * check_every 10, use_graph 1, refine 0, keep_basis 0. */

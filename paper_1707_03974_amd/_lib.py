@@ -90,6 +90,9 @@ _SIGNATURES = {
     "pdz_hv_kernel_times": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_double), _P]),
     "pdz_lanczos_default_opts": (ctypes.c_int32, [ctypes.POINTER(LanczosOpts)]),
+    "pdz_refine_decision": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "pdz_lanczos_workspace_size": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), ctypes.POINTER(ctypes.c_size_t)]),
     "pdz_lanczos": (ctypes.c_int32, [_P, ctypes.POINTER(LanczosOpts), _P, _P, ctypes.c_size_t, _P,
                                      ctypes.POINTER(LanczosResult), _P]),

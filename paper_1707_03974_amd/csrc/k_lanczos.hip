@@ -478,31 +478,57 @@ struct Layout {
     size_t restart = 0;   // workspace of the FP64 restart (refine == 2)
 };
 
-// Second-lowest eigenvalue of the k x k tridiagonal matrix (diagonal a[0..k),
-// off-diagonal b[1..k)) by bisection on the Sturm count (host, FP64).
-double tridiag_second_min_host(const std::vector<double>& a, const std::vector<double>& b, int k) {
+// Eigenvalues of the k x k tridiagonal matrix (diagonal a[0..k), off-diagonal
+// b[1..k)) below x, by the Sturm count (host, FP64).
+int tridiag_count_below(const std::vector<double>& a, const std::vector<double>& b, int k, double x) {
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < k; ++i) {
+        const double d = q != 0.0 ? q : 1e-300;
+        q = a[i] - x - b[i] * b[i] / d;
+        if (q < 0) ++c;
+    }
+    return c;
+}
+
+// The j-th smallest eigenvalue (j = 1, 2, ...) of the same matrix by bisection.
+double tridiag_kth_host(const std::vector<double>& a, const std::vector<double>& b, int k, int j) {
     double lo = a[0], hi = a[0];
     for (int i = 0; i < k; ++i) {
         const double r = (i > 0 ? std::fabs(b[i]) : 0.0) + (i + 1 < k ? std::fabs(b[i + 1]) : 0.0);
         lo = std::min(lo, a[i] - r);
         hi = std::max(hi, a[i] + r);
     }
-    auto count_below = [&](double x) {   // eigenvalues < x
-        int c = 0;
-        double q = a[0] - x;
-        if (q < 0) ++c;
-        for (int i = 1; i < k; ++i) {
-            const double d = q != 0.0 ? q : 1e-300;
-            q = a[i] - x - b[i] * b[i] / d;
-            if (q < 0) ++c;
-        }
-        return c;
-    };
     for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(lo) + std::fabs(hi)); ++it) {
         const double mid = 0.5 * (lo + hi);
-        if (count_below(mid) >= 2) hi = mid; else lo = mid;
+        if (tridiag_count_below(a, b, k, mid) >= j) hi = mid; else lo = mid;
     }
     return 0.5 * (lo + hi);
+}
+
+// refine == 2 decision.  The Rayleigh quotient E of the Ritz vector with FP64
+// residual r is within r^2 / gap of the eigenvalue, gap the distance to the
+// next distinct eigenvalue.  Estimate: the first eigenvalue of T_k above the
+// cluster of Ritz values within 1e-8 max(1, |theta_1|) of theta_1 (copies
+// of theta_1 are ghosts of the same eigenvalue, or a degenerate level),
+// divided by 10 since a Ritz value lies above the eigenvalue it approximates
+// (Cauchy interlacing), so theta_next - theta_1 can exceed the true gap.
+// No Ritz value above the cluster: the gap is unknown and the restart runs.
+// Returns 1 when the FP64 restart must run; *gap_out receives the estimate
+// (0 when unknown).
+int refine_restart_needed(const std::vector<double>& a, const std::vector<double>& b, int k, double E, double r,
+                          double* gap_out) {
+    *gap_out = 0.0;
+    if (k < 1) return 1;
+    const double th1 = tridiag_kth_host(a, b, k, 1);
+    const double delta = 1e-8 * std::max(1.0, std::fabs(th1));
+    const int m = tridiag_count_below(a, b, k, th1 + delta);
+    if (m >= k) return 1;
+    const double gap = (tridiag_kth_host(a, b, k, m + 1) - th1) / 10.0;
+    if (!(gap > 0.0) || !std::isfinite(gap)) return 1;
+    *gap_out = gap;
+    return r * r > 1e-8 * std::fabs(E) * gap ? 1 : 0;
 }
 
 // Options of the FP64 Lanczos restart from the Ritz vector (refine == 2).
@@ -901,8 +927,10 @@ struct Run {
     }
 
     // One Lanczos step with v = v_k, vp = v_{k-1}, w the output slot.
-    // `reorth_nvec` > 0: re-orthogonalise against basis(0..reorth_nvec-1).
-    pdz_status step(T* v, T* vp, T* w, int reorth_nvec) {
+    // rn > 0: re-orthogonalise w (classical Gram-Schmidt, twice) against the
+    // rn consecutive basis slots from basis(rfirst): every earlier vector for
+    // full re-orthogonalisation, v_{k-1} and v_k for local.
+    pdz_status step(T* v, T* vp, T* w, int rfirst, int rn) {
         const unsigned g = grid_elems(D);
         pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, v, w, s, done());
         if (st != PDZ_OK) return st;
@@ -911,14 +939,14 @@ struct Run {
                            (int)kStoreSum, done(), err);
         hipLaunchKernelGGL(k_update<T>, dim3(kRedGrid), dim3(kRedBlock), 0, s, w, v, vp, D, alpha(), beta(), kptr(),
                            partial(), done());
-        if (reorth_nvec > 0) {
+        if (rn > 0) {
             for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(k_dots_basis<T>, dim3(kRedGrid, reorth_nvec), dim3(kRedBlock), 0, s, basis(0), ld(), D,
-                                   reorth_nvec, w, partial(), done());
-                hipLaunchKernelGGL(k_finalize_basis, dim3(reorth_nvec), dim3(kRedBlock), 0, s, partial(), kRedGrid,
-                                   coefs(), done());
-                hipLaunchKernelGGL(k_sub_basis<T>, dim3(g), dim3(kRedBlock), 0, s, basis(0), ld(), D, reorth_nvec, coefs(), w,
+                hipLaunchKernelGGL(k_dots_basis<T>, dim3(kRedGrid, rn), dim3(kRedBlock), 0, s, basis(rfirst), ld(), D,
+                                   rn, w, partial(), done());
+                hipLaunchKernelGGL(k_finalize_basis, dim3(rn), dim3(kRedBlock), 0, s, partial(), kRedGrid, coefs(),
                                    done());
+                hipLaunchKernelGGL(k_sub_basis<T>, dim3(g), dim3(kRedBlock), 0, s, basis(rfirst), ld(), D, rn, coefs(),
+                                   w, done());
             }
             hipLaunchKernelGGL((k_dot_partial<T, T>), dim3(kRedGrid), dim3(kRedBlock), 0, s, w, w, D, partial(), done());
         }
@@ -958,7 +986,10 @@ struct Run {
             for (int k = 1; k <= o->max_iter; ++k) {
                 // v_k = basis(k-1), v_{k-1} = basis(k-2) or the zero vector, w -> basis(k)
                 T* vp = (k >= 2) ? basis(k - 2) : buf(0);
-                st = step(basis(k - 1), vp, basis(k), k);
+                // full (2): against v_0 .. v_{k-1}; local (1): against v_{k-2}, v_{k-1}
+                const int rfirst = o->reorth == 2 ? 0 : (k >= 2 ? k - 2 : 0);
+                const int rn = o->reorth == 2 ? k : (k >= 2 ? 2 : 1);
+                st = step(basis(k - 1), vp, basis(k), rfirst, rn);
                 if (st != PDZ_OK) return st;
                 if (k % o->check_every == 0 || k == o->max_iter) {
                     st = read_ctl(h);
@@ -1145,20 +1176,18 @@ struct Run {
     }
 
     // refine == 2: when the FP64 residual r of the Ritz vector y is too large
-    // for its Rayleigh quotient theta to be within 1e-8 of the eigenvalue,
-    // |r|^2 / gap > 1e-8 |theta| with gap = theta_2(T_k) - theta_1(T_k), run
-    // FP64 Lanczos from y (three-term recurrence, tol at least 1e-12, at
-    // least 300 steps) and report its refined energy.
+    // for its Rayleigh quotient to be within 1e-8 of the eigenvalue
+    // (refine_restart_needed), run FP64 Lanczos from y (three-term
+    // recurrence, tol at least 1e-12, at least 300 steps) and report its
+    // refined energy.
     pdz_status maybe_restart(int k, double* ritz_out, pdz_lanczos_result* res, bool* restarted) {
         *restarted = false;
-        if (k < 2) return ok();
         std::vector<double> a(k), b(k + 1);
         PDZ_HIP(hipMemcpyAsync(a.data(), alpha(), (size_t)k * 8, hipMemcpyDeviceToHost, s));
         PDZ_HIP(hipMemcpyAsync(b.data(), beta(), (size_t)(k + 1) * 8, hipMemcpyDeviceToHost, s));
         PDZ_HIP(hipStreamSynchronize(s));
-        const double gap = tridiag_second_min_host(a, b, k) - res->E0;
-        const double r = res->resid_refined;
-        if (!(gap > 0.0) || !(r * r > 1e-8 * std::fabs(res->E0_refined) * gap)) return ok();
+        double gap = 0.0;
+        if (!refine_restart_needed(a, b, k, res->E0_refined, res->resid_refined, &gap)) return ok();
         const pdz_lanczos_opts ro = restart_opts(o);
         const Layout L2 = make_layout(p, &ro);
         Run<double> r2{p, &ro, L2, ws + L.restart, s, err, D};
@@ -1179,7 +1208,7 @@ pdz_status check_opts(const pdz_lanczos_opts* o) {
     if (o->max_iter < 1 || o->max_iter > kMaxIter) return fail(PDZ_EINVAL, "max_iter must be in [1, 2000]");
     if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(PDZ_EINVAL, "tol must be finite and >= 0");
     if (o->storage != PDZ_F64 && o->storage != PDZ_F32) return fail(PDZ_EINVAL, "storage must be F64 or F32");
-    if (o->reorth != 0 && o->reorth != 1) return fail(PDZ_EINVAL, "reorth must be 0 or 1");
+    if (o->reorth < 0 || o->reorth > 2) return fail(PDZ_EINVAL, "reorth must be 0 (none), 1 (local) or 2 (full)");
     if (o->check_every < 1) return fail(PDZ_EINVAL, "check_every must be >= 1");
     if (o->refine < 0 || o->refine > 2) return fail(PDZ_EINVAL, "refine must be 0, 1 or 2");
     if (o->refine == 2 && o->reorth) return fail(PDZ_EINVAL, "refine = 2 restarts the three-term recurrence (reorth 0)");
@@ -1193,6 +1222,15 @@ pdz_status check_opts(const pdz_lanczos_opts* o) {
 using namespace pdz;
 
 extern "C" {
+
+pdz_status pdz_refine_decision(const double* alpha, const double* beta, int32_t k, double E, double resid,
+                               int32_t* restart, double* gap) {
+    if (!alpha || !beta || !restart || !gap || k < 1 || k > kMaxIter)
+        return fail(PDZ_EINVAL, "pdz_refine_decision: null pointer or k outside [1, 2000]");
+    std::vector<double> a(alpha, alpha + k), b(beta, beta + k + 1);
+    *restart = refine_restart_needed(a, b, k, E, resid, gap);
+    return ok();
+}
 
 pdz_status pdz_lanczos_default_opts(pdz_lanczos_opts* o) {
     if (!o) return fail(PDZ_EINVAL, "opts is NULL");

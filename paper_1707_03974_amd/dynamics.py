@@ -21,7 +21,7 @@ def neighbour_problem(problem, spin, op):
 
 def resolvent(problem, psi0, site, spin, op, w, steps=200, storage="f64", target=None, reorth=0):
     """R(w) = <phi|(w - H)^{-1}|phi> with phi = c or c+ (op) on psi0, from `steps` Lanczos steps in the
-    target sector (fewer when the Krylov space closes; reorth=1 re-orthogonalises every step).
+    target sector (fewer when the Krylov space closes; reorth=1 re-orthogonalises each step locally, reorth=2 fully).
     Returns (R at the points w, Lanczos result)."""
     import torch
     tgt = target if target is not None else neighbour_problem(problem, spin, op)

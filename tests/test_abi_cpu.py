@@ -109,3 +109,45 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError, match="no fallback"):
         _lib.load(os.path.join(ROOT, "does_not_exist", "libpdz.so"))
+
+
+def _decide(alpha, beta, E, resid):
+    lib = _lib.load()
+    k = len(alpha)
+    a = (ctypes.c_double * k)(*alpha)
+    b = (ctypes.c_double * (k + 1))(*beta)
+    rs = ctypes.c_int32()
+    gap = ctypes.c_double()
+    assert lib.pdz_refine_decision(a, b, k, E, resid, ctypes.byref(rs), ctypes.byref(gap)) == _lib.PDZ_OK
+    return rs.value, gap.value
+
+
+def test_refine_decision_skips_copies_of_the_lowest_ritz_value():
+    """A duplicated lowest Ritz value (a ghost or a degenerate level) must not read as a zero gap."""
+    # T_k = diag(-2, -2, 1, 3) with tiny couplings: theta_1 = -2 twice, next distinct value 1
+    alpha = [-2.0, -2.0, 1.0, 3.0]
+    beta = [0.0, 1e-13, 1e-13, 1e-13, 0.5]
+    restart, gap = _decide(alpha, beta, -2.0, 1e-6)
+    assert abs(gap - 0.3) < 1e-9          # (1 - (-2)) / 10
+    assert restart == 0                    # 1e-12 / 0.3 < 1e-8 * 2
+    restart, _ = _decide(alpha, beta, -2.0, 1e-3)
+    assert restart == 1                    # 1e-6 / 0.3 > 2e-8
+
+
+def test_refine_decision_restarts_when_the_gap_is_unknown():
+    # every Ritz value in one cluster: no distinct second value
+    restart, gap = _decide([-1.0, -1.0], [0.0, 0.0, 0.0], -1.0, 1e-12)
+    assert restart == 1 and gap == 0.0
+    # a single step
+    restart, gap = _decide([-1.0], [0.0, 0.1], -1.0, 1e-12)
+    assert restart == 1
+
+
+def test_refine_decision_matches_the_bound_on_a_clear_gap():
+    # T = [[0, 1], [1, 0]]: Ritz values -1, 1; gap estimate 0.2
+    restart, gap = _decide([0.0, 0.0], [0.0, 1.0, 0.0], -1.0, 1e-5)
+    assert abs(gap - 0.2) < 1e-9 and restart == 0          # 1e-10 / 0.2 <= 1e-8
+    restart, _ = _decide([0.0, 0.0], [0.0, 1.0, 0.0], -1.0, 1e-4)
+    assert restart == 1                                      # 1e-8 / 0.2 > 1e-8
+    with pytest.raises(AssertionError):
+        _decide([], [0.0], -1.0, 0.0)

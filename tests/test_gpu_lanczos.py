@@ -229,8 +229,32 @@ def test_kept_basis_option_is_validated_and_sized():
 
 def test_full_reorthogonalisation():
     E = _energies()["ring8"]["E0"]
-    r = _gpu("ring8").lanczos(reorth=1, tol=1e-12)
+    r = _gpu("ring8").lanczos(reorth=2, tol=1e-12)
     assert r["converged"] and abs(r["E0"] - E) <= 1e-10 * abs(E)
+
+
+@pytest.mark.parametrize("name", ["ring8", "torus4x3"])
+@pytest.mark.parametrize("reorth", [0, 1, 2])
+def test_reorthogonalisation_modes_match_oracle(name, reorth):
+    """0 none, 1 local (against v_(k-1), v_k), 2 full: FP64 E0 within 1e-9 of the oracle's."""
+    E = _energies()[name]["E0"]
+    r = _gpu(name).lanczos(reorth=reorth, tol=1e-12, max_iter=300)
+    assert r["converged"] == 1
+    assert abs(r["E0"] - E) <= 1e-9 * abs(E), (reorth, r, E)
+
+
+def test_local_reorthogonalisation_fp32_storage_refined():
+    """FP32 vectors with local re-orthogonalisation: the FP64 Rayleigh quotient of the Ritz vector
+    (combined from the kept basis) is within 1e-8 of the oracle's E0."""
+    E = _energies()["torus4x3"]["E0"]
+    r = _gpu("torus4x3").lanczos(reorth=1, storage="f32", tol=1e-7, max_iter=300, refine=1)
+    assert abs(r["E0_refined"] - E) <= 1e-8 * abs(E), (r, E)
+
+
+def test_reorth_out_of_range_is_rejected():
+    import paper_1707_03974_amd as pdz
+    with pytest.raises(pdz.PdzError, match="reorth"):
+        _gpu("ring8").lanczos(reorth=3)
 
 
 def test_ritz_vector_is_an_eigenvector():

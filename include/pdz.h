@@ -590,6 +590,21 @@ pdz_status pdz_start_vector(pdz_problem p, const uint16_t* params_bf16, pdz_dtyp
  * sums in FP64.  Synchronous.  Errors: PDZ_EINVAL. */
 pdz_status pdz_dot(pdz_dtype dt, const void* a, const void* b, uint64_t n, double* result, void* stream);
 
+/* pdz_dot for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and summation order as pdz_dot, with the 1024 partial sums held in
+ * a fixed device array of the library (8 KiB per device, kept until the
+ * process ends) instead of memory allocated per call, and the result written
+ * to device memory.  result: one double in device memory, written
+ * asynchronously on `stream` (bitwise equal to pdz_dot's result for the same
+ * inputs).  n is not limited: the partial sums are 1024 whatever n is.
+ * Calls that overlap on one device (different streams, no ordering between
+ * them) race on the shared array; calls ordered on one stream do not.  Calls
+ * no allocating routine.  Asynchronous.  Errors: PDZ_EINVAL (NULL argument,
+ * dtype), PDZ_EDEVICE / PDZ_EHIP when the array's device address cannot be
+ * obtained. */
+pdz_status pdz_dot_noalloc(pdz_dtype dt, const void* a, const void* b, uint64_t n, double* result, void* stream);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Message of the last failing call on this thread ("" if none).  Valid until

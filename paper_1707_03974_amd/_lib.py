@@ -152,6 +152,7 @@ _SIGNATURES = {
                                     ctypes.c_double, _P, _P, _P, _P]),
     "pdz_start_vector": (ctypes.c_int32, [_P, _P, ctypes.c_int32, _P, _P]),
     "pdz_dot": (ctypes.c_int32, [ctypes.c_int32, _P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), _P]),
+    "pdz_dot_noalloc": (ctypes.c_int32, [ctypes.c_int32, _P, _P, ctypes.c_uint64, _P, _P]),
     "pdz_last_error": (ctypes.c_char_p, []),
     "pdz_version": (ctypes.c_int32, []),
 }

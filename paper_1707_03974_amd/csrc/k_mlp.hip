@@ -13,6 +13,7 @@
 // and a SplitMix64 draw per sample, so the draws do not depend on summation
 // order.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "pdz_internal.h"
@@ -591,6 +592,36 @@ Act act_views(void* act, uint64_t n) {
 
 using namespace pdz;
 
+namespace {
+
+// Partial sums of pdz_dot_noalloc: one array per device, held until the
+// process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns on each device (dot_scratch_ptr).
+constexpr int kDotPartials = 1024;
+static __device__ __align__(256) double scratch[kDotPartials];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's array (the current device), looked up once per device.
+pdz_status dot_scratch_ptr(double** out) {
+    int dev = -1;
+    PDZ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PDZ_EDEVICE, "device index outside the supported range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        PDZ_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(PDZ_EDEVICE, "no device address for the dot-product scratch array");
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return ok();
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t pdz_mlp_param_count(void) { return kParams; }
@@ -775,6 +806,26 @@ pdz_status pdz_dot(pdz_dtype dt, const void* a, const void* b, uint64_t n, doubl
     (void)hipFreeAsync(d, s);
     (void)hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "pdz_dot");
+    return ok();
+}
+
+pdz_status pdz_dot_noalloc(pdz_dtype dt, const void* a, const void* b, uint64_t n, double* result, void* stream) {
+    if (!a || !b || !result) return fail(PDZ_EINVAL, "NULL argument");
+    if (dt != PDZ_F64 && dt != PDZ_F32) return fail(PDZ_EINVAL, "dtype must be PDZ_F64 or PDZ_F32");
+    double* part = nullptr;
+    pdz_status st = dot_scratch_ptr(&part);
+    if (st != PDZ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // every one of the kDotPartials work groups writes its partial sum, so
+    // nothing of the previous call's contents is read
+    if (dt == PDZ_F64)
+        hipLaunchKernelGGL(k_vdot<double>, dim3(kDotPartials), dim3(256), 0, s, static_cast<const double*>(a),
+                           static_cast<const double*>(b), n, part);
+    else
+        hipLaunchKernelGGL(k_vdot<float>, dim3(kDotPartials), dim3(256), 0, s, static_cast<const float*>(a),
+                           static_cast<const float*>(b), n, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, kDotPartials, 1.0, result);
+    PDZ_HIP(hipGetLastError());
     return ok();
 }
 

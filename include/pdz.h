@@ -136,10 +136,16 @@ pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* str
 /* ------------------------------------------------------ H.v launch plans */
 
 /* Launch geometry of pdz_hv for one precision.  0 in a field = automatic.
- * down: 1 one row per work group with the column's hop table loaded up front,
+ * down: looped family (summands of each element in hop-table order):
+ *       1 one row per work group with the column's hop table loaded up front,
  *       2 one row with the table read in a loop, 3 two rows per work group,
  *       4 three rows per work group (1: 16-bit tables and at most 48 hops
  *       per state; 3, 4: the rows must fit in LDS);
+ *       scheduled family (summands in the order of a gather schedule built
+ *       at creation, in which the 32 lanes of a half-wave read 32 different
+ *       LDS banks at every step): 5, 6, 7 one, two, three rows per work
+ *       group (needs rows of 1024 to 13280 down states, at most two hop
+ *       magnitudes; 6 and 7 F32 only);
  * up_cw: column-chunk width of the up-hop pass (F32: 32, 64, 128, 256;
  *       F64: 16, 32, 64, 128);
  * up: 1 the hops of a row are loaded in batches of 8, 2 all hops of a row are
@@ -149,7 +155,10 @@ pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* str
  * map: order of the up-pass tiles: 1 each XCD walks a pair of neighbouring
  *       column chunks at a time (blocks are dealt to XCDs round robin),
  *       2 chunk-major over all blocks, 3 each XCD walks one chunk at a time.
- * Every plan computes the same y bit for bit. */
+ * Plans of one down family compute the same y bit for bit.  Where the
+ * scheduled family exists, the automatic plan and pdz_hv_tune use it alone,
+ * so every plan they pick gives the same y; a looped variant set explicitly
+ * differs from it by rounding only. */
 typedef struct {
     int32_t down;
     int32_t up_cw;

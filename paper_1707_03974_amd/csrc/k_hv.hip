@@ -445,6 +445,222 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
         block_dot_store<kWideBlock>(dsum, a.dotp + blockIdx.x);
 }
 
+// Scheduled down pass (plans down 5, 6, 7: 1, 2 or 3 rows per group).  The
+// group's rows are staged as planes of 32-bit words kSchedPlane words apart,
+// element d' of a row in bank d' mod 32 (FP64: a plane of low words and one
+// of high words), and each wave's 64 columns gather in the steps of the
+// sector's gather schedule (pdz_sched.cpp): at every step the 32 lanes of a
+// half-wave read 32 different banks, so no read waits on a bank conflict,
+// and the hop magnitude of a step is the same in every lane (its sign comes
+// with the lane's entry).  An element's sum: diagonal, then its hops in
+// schedule order.  The next group's rows are loaded into registers while a
+// group computes.  FUSE: the staged rows are q_{k+1}, formed from the
+// previous step's parts as in k_hv_down_wide.
+constexpr int kSchedMaxWords = kSchedMaxSteps / 2;   // schedule words a wave holds in registers
+
+template <typename T>
+struct SchedArgs {
+    const uint32_t* words;
+    const uint32_t* off;
+    const uint16_t* steps;
+    T mag0, mag1;          // hop magnitudes of the two step groups
+};
+
+// Sums of one double per thread over the work group (fixed order) into *out1
+// and *out2 by thread 0, through `red` (LDS the work group no longer reads).
+__device__ __forceinline__ void sched_block_sums(double v1, double* out1, double v2, double* out2, double* red) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        v1 += __shfl_xor(v1, m);
+        v2 += __shfl_xor(v2, m);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = v1;
+        red[kWideBlock / 64 + (threadIdx.x >> 6)] = v2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t1 = 0.0, t2 = 0.0;
+        for (int i = 0; i < kWideBlock / 64; ++i) {
+            t1 += red[i];
+            t2 += red[kWideBlock / 64 + i];
+        }
+        if (out1) *out1 = t1;
+        if (out2) *out2 = t2;
+    }
+}
+
+template <typename T, typename E, int R, bool FUSE>
+__global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, E> a, const SchedArgs<T> sc,
+                                                              const T* __restrict__ x, T* __restrict__ y) {
+    if (a.skip && *a.skip) return;
+    constexpr int W = sizeof(T) / 4;      // 32-bit planes per row
+    static_assert(R >= 1 && R <= 3 && (W == 1 || R == 1), "rows per group");
+    // elements per thread loaded ahead for the next group (the rest when it is staged)
+    constexpr int PER = FUSE ? (W == 1 ? 4 : 3) : 8;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* planes = reinterpret_cast<uint32_t*>(smem);   // plane (r, word) at (r * W + word) * kSchedPlane
+    constexpr uint32_t P = kSchedPlane;
+    const uint64_t D_up = a.D_up, D_dn = a.D_dn;
+    const uint32_t Dn = (uint32_t)D_dn;
+    const uint64_t ngroups = (D_up + R - 1) / R;
+    const uint32_t nwaves = (Dn + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // zero pads: read by lanes without a hop at a step
+    for (uint32_t k = threadIdx.x; k < (uint32_t)(R * W) * 32u; k += kWideBlock)
+        planes[(k / 32u) * P + P - 32u + (k % 32u)] = 0u;
+    double dsum = 0.0, nsum = 0.0;
+    double fa = 0.0, fb = 0.0, fc = 0.0;
+    T* fkeep = nullptr;
+    if constexpr (FUSE) {
+        const int k = *a.fkidx;
+        fa = a.fsc[k];
+        fb = a.falpha[k] * a.fsc[k];
+        fc = k > 0 ? a.fbeta[k] * a.fsc[k - 1] : 0.0;
+        if (a.fkeep && k + 1 < a.fkeep_cap) fkeep = a.fkeep + (uint64_t)(k + 1) * a.fkeep_ld;
+    }
+    // element k of a group lives in row k / Dn at column k mod Dn
+    auto put = [&](uint32_t k, T v) {
+        const uint32_t r = R == 1 ? 0u : (k >= 2 * Dn ? 2u : (k >= Dn ? 1u : 0u));
+        const uint32_t d = k - r * Dn;
+        if constexpr (W == 1) {
+            planes[r * P + d] = __float_as_uint((float)v);
+        } else {
+            const unsigned long long b = (unsigned long long)__double_as_longlong((double)v);
+            planes[d] = (uint32_t)b;
+            planes[P + d] = (uint32_t)(b >> 32);
+        }
+    };
+    // element of row r at byte address ba of plane r (ba = 4 d')
+    auto get = [&](int r, uint32_t ba) -> T {
+        const uint32_t* pr = reinterpret_cast<const uint32_t*>(smem + ba);
+        if constexpr (W == 1) {
+            return (T)__uint_as_float(pr[(uint32_t)r * P]);
+        } else {
+            return (T)__longlong_as_double((long long)(((unsigned long long)pr[P] << 32) | pr[0]));
+        }
+    };
+    T pre[PER];
+    T pz[FUSE ? PER : 1], p1[FUSE ? PER : 1], p2[FUSE ? PER : 1];
+    auto fetch = [&](uint64_t g) {
+        const uint64_t u0 = g * R;
+        const uint64_t nelem = ((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * D_dn;
+        const uint64_t off = u0 * D_dn;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint64_t k = threadIdx.x + (uint64_t)i * kWideBlock;
+            if constexpr (FUSE) {
+                if (k < nelem) {
+                    pre[i] = y[off + k];
+                    pz[i] = a.fz[off + k];
+                    p1[i] = a.fq1[off + k];
+                    p2[i] = a.fq2[off + k];
+                }
+            } else {
+                pre[i] = (k < nelem) ? __builtin_nontemporal_load(x + off + k) : (T)0;
+            }
+        }
+    };
+    // q_{k+1} at element e (FUSE), stored back and counted in |q_{k+1}|^2
+    auto form = [&](uint64_t e, T hd, T hu, T q1, T q2) -> T {
+        const T v = lanczos_recurrence<T>(hd, hu, q1, q2, fa, fb, fc);
+        a.fq2[e] = v;
+        if (fkeep) fkeep[e] = v;
+        nsum += (double)v * (double)v;
+        return v;
+    };
+    if (blockIdx.x < ngroups) fetch(blockIdx.x);
+    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const uint64_t u0 = g * R;
+        const int nr = (int)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
+        const uint32_t nelem = (uint32_t)nr * Dn;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t k = threadIdx.x + (uint32_t)i * kWideBlock;
+            if (k < (uint32_t)R * Dn) {
+                T v = (T)0;
+                if (k < nelem) v = FUSE ? form(u0 * D_dn + k, pre[i], pz[i], p1[i], p2[i]) : pre[i];
+                put(k, v);
+            }
+        }
+        for (uint32_t k = threadIdx.x + (uint32_t)PER * kWideBlock; k < (uint32_t)R * Dn; k += kWideBlock) {
+            T v = (T)0;
+            if (k < nelem) {
+                const uint64_t e = u0 * D_dn + k;
+                if constexpr (FUSE)
+                    v = form(e, y[e], a.fz[e], a.fq1[e], a.fq2[e]);
+                else
+                    v = x[e];
+            }
+            put(k, v);
+        }
+        __syncthreads();
+        if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
+        uint32_t pu[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) pu[r] = a.up_states[u0 + (r < nr ? r : 0)];
+        const T m0 = sc.mag0, m1 = sc.mag1;
+        for (uint32_t d0 = 0; d0 < Dn; d0 += kWideBlock) {
+            const uint32_t wv = (d0 >> 6) + wave;
+            if (wv >= nwaves) break;   // no barrier follows inside this loop
+            // this wave's schedule words, all loaded before its steps start
+            const int n = sc.steps[2 * wv] / 2;     // words: a multiple of 4
+            const int nb = sc.steps[2 * wv + 1] / 2;
+            const uint32_t* wp = sc.words + sc.off[wv] + lane;
+            uint32_t wbuf[kSchedMaxWords];
+#pragma unroll
+            for (int i = 0; i < kSchedMaxWords; ++i) wbuf[i] = i < n ? wp[(uint32_t)i * 64u] : 0u;
+            const uint32_t d = d0 + threadIdx.x;
+            const bool live = d < Dn;
+            const uint32_t pd = live ? a.dn_states[d] : 0u;
+            T acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                acc[r] = live ? a.U * (T)__builtin_popcount(pu[r] & pd) * get(r, d * 4u) : (T)0;
+            auto step = [&](uint32_t e, T m) {
+                T c;
+                if constexpr (W == 1) {
+                    c = __uint_as_float(__float_as_uint(m) ^ (e << 31));
+                } else {
+                    const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+                    c = __longlong_as_double((long long)(mb ^ ((unsigned long long)(e & 1u) << 63)));
+                }
+                const uint32_t ba = e & 0xFFFCu;
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += c * get(r, ba);
+            };
+            // four words (eight steps) per chunk; the words sit in registers, indexed statically,
+            // and only the chunk test branches (wave-uniform)
+#pragma unroll
+            for (int c = 0; c < kSchedMaxWords / 4; ++c) {
+                if (4 * c < n) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int i = 4 * c + j;
+                        const T m = i < nb ? m0 : m1;
+                        step(wbuf[i] & 0xFFFFu, m);
+                        step(wbuf[i] >> 16, m);
+                    }
+                }
+            }
+            if (live) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (r < nr) {
+                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                        dsum += (double)get(r, d * 4u) * (double)acc[r];
+                    }
+            }
+        }
+    }
+    // the planes are free now: the work group's sums go through them
+    sched_block_sums(dsum, a.dotp ? a.dotp + blockIdx.x : nullptr, nsum, FUSE ? a.fnorm + blockIdx.x : nullptr,
+                     reinterpret_cast<double*>(smem));
+}
+
 // Short rows: `rows` consecutive rows staged row-major; threads walk the
 // flattened (row, column) index of the group.  STAGE = false gathers from
 // global memory instead (rows too long for LDS).
@@ -845,6 +1061,48 @@ void launch_wide_fused(int variant, uint64_t grid, size_t lds, hipStream_t s, co
         hipLaunchKernelGGL((k_hv_down_wide<T, E, 1, 0, true>), g, b, lds, s, da, x, y);
 }
 
+// Scheduled down pass (plans down 5, 6, 7: 1, 2, 3 rows per group).
+bool sched_plan(int variant) { return variant >= 5 && variant <= 7; }
+int sched_rows(int variant) { return variant - 4; }
+size_t sched_lds(const pdz_problem_s* p, size_t es, int rows) {
+    (void)p;
+    return (size_t)rows * (es / 4) * kSchedPlane * 4;
+}
+bool sched_fits(const pdz_problem_s* p, size_t es, int rows) {
+    return sched_lds(p, es, rows) <= kDynLds && p->up.D >= (uint64_t)rows;
+}
+
+template <typename T>
+SchedArgs<T> sched_args(const pdz_problem_s* p) {
+    SchedArgs<T> sa;
+    sa.words = p->dn.sched.words;
+    sa.off = p->dn.sched.off;
+    sa.steps = p->dn.sched.steps;
+    sa.mag0 = (T)p->dn.sched.mag0;
+    sa.mag1 = (T)p->dn.sched.mag1;
+    return sa;
+}
+
+template <typename T, typename E, bool FUSE>
+void launch_sched(const pdz_problem_s* p, int variant, uint64_t grid, size_t lds, hipStream_t s,
+                  const DownArgs<T, E>& da, const T* x, T* y) {
+    const dim3 g((unsigned)grid), b(kWideBlock);
+    const SchedArgs<T> sa = sched_args<T>(p);
+    if (variant == 7 && sizeof(T) == 4)
+        hipLaunchKernelGGL((k_hv_down_sched<T, E, sizeof(T) == 4 ? 3 : 1, FUSE>), g, b, lds, s, da, sa, x, y);
+    else if (variant == 6 && sizeof(T) == 4)
+        hipLaunchKernelGGL((k_hv_down_sched<T, E, sizeof(T) == 4 ? 2 : 1, FUSE>), g, b, lds, s, da, sa, x, y);
+    else
+        hipLaunchKernelGGL((k_hv_down_sched<T, E, 1, FUSE>), g, b, lds, s, da, sa, x, y);
+}
+
+template <typename T, typename E, int R, bool FUSE>
+pdz_status set_sched_lds() {
+    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_sched<T, E, R, FUSE>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
+    return ok();
+}
+
 // Up-pass geometry: the x[:, chunk] slab one XCD streams over is
 // D_up * CW * sizeof(T) bytes; narrower chunks stay in L2, wider ones issue
 // fewer, longer requests.  The plan (autotuned or default) picks CW.
@@ -906,7 +1164,11 @@ HvPlan default_plan(const pdz_problem_s* p, pdz_dtype dt) {
     const size_t es = dt == PDZ_F64 ? 8 : 4;
     HvPlan d;
     const bool compact = p->up.tbits16 > 0 && p->dn.tbits16 > 0;
-    if (dt == PDZ_F32 && row_fits(p, es, 2) && p->up.D >= 2)
+    if (wide_down(p, es) && p->dn.sched.words) {
+        int r = es == 4 ? 3 : 1;
+        while (r > 1 && !sched_fits(p, es, r)) --r;
+        d.down = 4 + r;
+    } else if (dt == PDZ_F32 && row_fits(p, es, 2) && p->up.D >= 2)
         d.down = 3;
     else if (compact && p->dn.max_hops <= 48)
         d.down = 1;
@@ -928,7 +1190,7 @@ HvPlan hv_resolve(const pdz_problem_s* p, pdz_dtype dt) {
     return pl;
 }
 
-int down_rows(int variant) { return variant == 4 ? 3 : variant == 3 ? 2 : 1; }
+int down_rows(int variant) { return sched_plan(variant) ? sched_rows(variant) : variant == 4 ? 3 : variant == 3 ? 2 : 1; }
 
 // Down-pass launch geometry (also the number of x . y partial sums it writes).
 struct DownGeom {
@@ -947,7 +1209,7 @@ DownGeom down_geom(const pdz_problem_s* p, size_t es, const HvPlan& plan, unsign
     if (D_dn >= (uint64_t)kWideBlock && row_bytes <= lds_cap) {
         g.wide = g.stage = true;
         g.rows = down_rows(plan.down);
-        g.lds = kMaxCoef * es + (size_t)g.rows * row_bytes;
+        g.lds = sched_plan(plan.down) ? sched_lds(p, es, g.rows) : kMaxCoef * es + (size_t)g.rows * row_bytes;
         const uint64_t ngroups = (D_up + g.rows - 1) / g.rows;
         const unsigned per_cu = (unsigned)(kLdsBytes / (g.lds + 256));
         g.grid = (uint64_t)cu * (per_cu < 1 ? 1 : per_cu);
@@ -1029,14 +1291,20 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     da.rows = gm.rows;
     if (fused) {
         if (!(passes & kPassDown) || (passes & kPassUp) || !gm.wide ||
-            !(plan.down == 2 || plan.down == 3 || plan.down == 4) || !split->dotp_dn || !split->fnorm)
+            !(plan.down == 2 || plan.down == 3 || plan.down == 4 || sched_plan(plan.down)) || !split->dotp_dn ||
+            !split->fnorm)
             return fail(PDZ_EINVAL, "fused recurrence needs the looped wide down pass, alone");
-        launch_wide_fused<T, E>(plan.down, gm.grid, gm.lds, s, da, y);
+        if (sched_plan(plan.down))
+            launch_sched<T, E, true>(p, plan.down, gm.grid, gm.lds, s, da, static_cast<const T*>(split->fq2), y);
+        else
+            launch_wide_fused<T, E>(plan.down, gm.grid, gm.lds, s, da, y);
         PDZ_HIP(hipGetLastError());
         return ok();
     }
     if (!(passes & kPassDown)) {
         // up pass only
+    } else if (gm.wide && sched_plan(plan.down)) {
+        launch_sched<T, E, false>(p, plan.down, gm.grid, gm.lds, s, da, x, y);
     } else if (gm.wide) {
         launch_wide<T, E>(plan.down, p->dn.max_hops, gm.grid, gm.lds, s, da, x, y);
     } else if (gm.stage) {
@@ -1199,6 +1467,14 @@ pdz_status prepare_one() {
     if (st == PDZ_OK) st = set_wide_lds<T, E, 1, 0, true>();
     if (st == PDZ_OK) st = set_wide_lds<T, E, 2, 0, true>();
     if (st == PDZ_OK) st = set_wide_lds<T, E, 3, 0, true>();
+    if (st == PDZ_OK) st = set_sched_lds<T, E, 1, false>();
+    if (st == PDZ_OK) st = set_sched_lds<T, E, 1, true>();
+    if (sizeof(T) == 4) {
+        if (st == PDZ_OK) st = set_sched_lds<T, E, sizeof(T) == 4 ? 2 : 1, false>();
+        if (st == PDZ_OK) st = set_sched_lds<T, E, sizeof(T) == 4 ? 2 : 1, true>();
+        if (st == PDZ_OK) st = set_sched_lds<T, E, sizeof(T) == 4 ? 3 : 1, false>();
+        if (st == PDZ_OK) st = set_sched_lds<T, E, sizeof(T) == 4 ? 3 : 1, true>();
+    }
     if (st != PDZ_OK) return st;
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_narrow<T, E, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
@@ -1225,7 +1501,7 @@ pdz_status hv_prepare() {
     return st;
 }
 
-std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
+std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt, bool every) {
     std::vector<HvPlan> out;
     const HvPlan d = default_plan(p, dt);
     out.push_back(d);
@@ -1233,12 +1509,18 @@ std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
     const size_t es = dt == PDZ_F64 ? 8 : 4;
     const bool compact = p->up.tbits16 > 0 && p->dn.tbits16 > 0;
     std::vector<int> downs;
-    if (wide_down(p, es)) {
+    const bool sched = wide_down(p, es) && p->dn.sched.words;
+    if (sched) {
+        // the scheduled family: one summation order for every plan the tuner tries
+        for (int r = 1; r <= (es == 4 ? 3 : 1); ++r)
+            if (sched_fits(p, es, r)) downs.push_back(4 + r);
+    }
+    if (wide_down(p, es) && (!sched || every)) {
         if (compact && p->dn.max_hops <= 48) downs.push_back(1);
         downs.push_back(2);
         if (row_fits(p, es, 2) && p->up.D >= 2) downs.push_back(3);
         if (row_fits(p, es, 3) && p->up.D >= 3) downs.push_back(4);
-    } else {
+    } else if (!sched) {
         downs.push_back(d.down);
     }
     const int* cws = dt == PDZ_F64 ? kUpCw64 : kUpCw32;
@@ -1263,7 +1545,7 @@ std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt) {
 
 bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan) {
     if (plan.down == 0 && plan.up_cw == 0 && plan.up == 0 && plan.map == 0) return true;
-    for (const HvPlan& c : hv_candidates(p, dt))
+    for (const HvPlan& c : hv_candidates(p, dt, true))
         if ((plan.down == 0 || plan.down == c.down) && (plan.up_cw == 0 || plan.up_cw == c.up_cw) &&
             (plan.up == 0 || plan.up == c.up) && (plan.map == 0 || plan.map == c.map))
             return true;
@@ -1287,7 +1569,7 @@ bool hv_fused_available(const pdz_problem_s* p, pdz_dtype dt) {
     const size_t es = dt == PDZ_F64 ? 8 : 4;
     const HvPlan plan = hv_resolve(p, dt);
     const DownGeom gm = down_geom(p, es, plan, (unsigned)ctx->cu_count);
-    return gm.wide && (plan.down == 2 || plan.down == 3 || plan.down == 4);
+    return gm.wide && (plan.down == 2 || plan.down == 3 || plan.down == 4 || sched_plan(plan.down));
 }
 
 size_t hv_dot_count_max(const pdz_problem_s* p, pdz_dtype dt) {
@@ -1296,7 +1578,7 @@ size_t hv_dot_count_max(const pdz_problem_s* p, pdz_dtype dt) {
     if (device_ctx(&ctx) != PDZ_OK) return 0;
     const size_t es = dt == PDZ_F64 ? 8 : 4;
     size_t best = 0;
-    for (const HvPlan& c : hv_candidates(p, dt)) {
+    for (const HvPlan& c : hv_candidates(p, dt, true)) {
         const size_t n = (size_t)down_grid(p, es, c, (unsigned)ctx->cu_count) +
                          (p->up.max_hops == 0 ? 1 : (size_t)up_blocks(p, es, c));
         if (n > best) best = n;

@@ -94,6 +94,7 @@ static void free_tables(SectorTables& t) {
     if (t.count) (void)hipFree(t.count);
     if (t.ell) (void)hipFree(t.ell);
     if (t.ell16) (void)hipFree(t.ell16);
+    free_down_schedule(&t.sched);
     t.ell16 = nullptr;
     t.states = nullptr;
     t.count = nullptr;
@@ -256,6 +257,10 @@ pdz_status pdz_problem_create(int32_t n_sites, const pdz_bond* bonds, int32_t n_
         }
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return cleanup(hip_fail(e, "table build"));
+        // down-pass gather schedule (shared with the up tables when both sectors are one)
+        st = build_down_schedule(p->dn, p->coef_host, &p->dn.sched, s);
+        if (st != PDZ_OK) return cleanup(st);
+        if (p->same_sector) p->up.sched = p->dn.sched;
         uint32_t word = 0;
         e = hipMemcpy(&word, ctx->err, sizeof(word), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return cleanup(hip_fail(e, "table build error word"));

@@ -32,6 +32,24 @@ struct BondDev {
     int32_t coef_neg;   // index of +t (odd number)
 };
 
+// Bank-conflict-free gather schedule of the down pass over one sector
+// (pdz_sched.cpp): per wave of 64 columns an even number of steps S, the
+// first B of them with the smaller hop magnitude mag0, the rest with mag1;
+// a step is a 16-bit entry per lane, (target word in a row plane of
+// kSchedPlane words, whose last 32 are zeros) << 2 | sign.
+// words[off[w] + (t / 2) * 64 + lane] holds steps t and t + 1 of wave w;
+// steps[2 w] = S, steps[2 w + 1] = B.  words == NULL: no schedule.
+constexpr uint32_t kSchedPlane = 13312;   // words per plane: sectors of at most 13280 states
+constexpr int kSchedMaxSteps = 64;        // a longer schedule is not built
+struct DownSchedule {
+    uint32_t* words = nullptr;
+    uint32_t* off = nullptr;     // per wave, and the total behind the last
+    uint16_t* steps = nullptr;   // per wave: S, B
+    uint32_t plane = 0;
+    double mag0 = 0.0, mag1 = 0.0;
+    size_t nwords = 0;
+};
+
 // Per-spin sector tables on the device (ELL layout, hop slot major).
 struct SectorTables {
     uint64_t D = 0;             // sector size C(N, n)
@@ -44,6 +62,7 @@ struct SectorTables {
     uint16_t* ell16 = nullptr;  // target | coef << tbits16 when that fits 16 bits, slot-pair layout:
                                 // slot h of state s at ((h / 2) * D + s) * 2 + h % 2
     int tbits16 = 0;            // target bits of a 16-bit entry (0: no 16-bit table)
+    DownSchedule sched;         // gather schedule for a down pass over this sector
 };
 
 }  // namespace pdz
@@ -135,6 +154,11 @@ pdz_status launch_unrank(const uint32_t* d_binom, int N, int n, const uint32_t* 
 pdz_status build_sector_tables(const uint32_t* d_binom, int N, int n, const BondDev* d_bonds, int nb,
                                SectorTables* st, uint32_t* err, hipStream_t s);
 pdz_status build_compact_table(SectorTables* st, int ncoef, hipStream_t s);
+// Down-pass gather schedule of a sector (host colouring; no schedule when the
+// sector has more than kSchedPlane - 32 states or more than two hop magnitudes).
+pdz_status build_down_schedule(const SectorTables& t, const std::vector<double>& coef, DownSchedule* out,
+                               hipStream_t s);
+void free_down_schedule(DownSchedule* sc);
 pdz_status hv_prepare();   // per-device kernel attributes, called once outside any capture
 pdz_status batch_prepare();   // the same for the batched H.v kernels
 pdz_status kspace_prepare();  // the same for the momentum-space H.v kernels
@@ -150,8 +174,11 @@ int parity_dot_count(const pdz_problem_s* p, pdz_dtype dt);
 // y = H x on a momentum-space problem (every pass at once; no split form)
 pdz_status launch_hvk(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                       const int* skip);
-// Candidate plans valid for this problem and precision; the first is the default.
-std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt);
+// Candidate plans for this problem and precision; the first is the default.
+// Where the down sector has a gather schedule the tuner's set holds only the
+// scheduled down family (one summation order); every = true adds the looped
+// family, which a caller may still select.
+std::vector<HvPlan> hv_candidates(const pdz_problem_s* p, pdz_dtype dt, bool every = false);
 bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan);
 // passes: kPassDown | kPassUp for y = H x; one bit alone launches only that
 // pass of the table path (the down pass writes y, the up pass adds onto it).

@@ -46,6 +46,7 @@ struct DownArgs {
     const T* coef;
     int ncoef;
     int rows;         // rows staged per group
+    int add_y;        // scheduled pass: 1 adds its part to y (written by the up pass), 0 writes y
     double* dotp;     // NULL, or one partial sum of x . y (this pass's output) per work group
     const int* skip;
     // Fused Lanczos recurrence (FUSE kernels only): the staged rows are
@@ -446,16 +447,17 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
 }
 
 // Scheduled down pass (plans down 5, 6, 7: 1, 2 or 3 rows per group).  The
-// group's rows are staged as planes of 32-bit words kSchedPlane words apart,
-// element d' of a row in bank d' mod 32 (FP64: a plane of low words and one
-// of high words), and each wave's 64 columns gather in the steps of the
-// sector's gather schedule (pdz_sched.cpp): at every step the 32 lanes of a
-// half-wave read 32 different banks, so no read waits on a bank conflict,
-// and the hop magnitude of a step is the same in every lane (its sign comes
-// with the lane's entry).  An element's sum: diagonal, then its hops in
-// schedule order.  The next group's rows are loaded into registers while a
-// group computes.  FUSE: the staged rows are q_{k+1}, formed from the
-// previous step's parts as in k_hv_down_wide.
+// group's rows are staged as planes of 32-bit words kSchedPlane words apart in
+// a static LDS array, element d' of a row in bank d' mod 32 (FP64: a plane of
+// low words and one of high words), and each wave's 64 columns gather in the
+// steps of the sector's gather schedule (pdz_sched.cpp): at every step the 32
+// lanes of a half-wave read 32 different banks, so no read waits on a bank
+// conflict.  The hop magnitude of a step is the same in every lane; its sign
+// comes with the lane's entry.  An element's sum: diagonal, then its hops in
+// schedule order.  The next group's
+// rows are partly loaded into registers while a group computes; the rest are
+// loaded in unrolled batches once the group is done.  FUSE: the staged rows
+// are q_{k+1}, formed from the previous step's parts as in k_hv_down_wide.
 constexpr int kSchedMaxWords = kSchedMaxSteps / 2;   // schedule words a wave holds in registers
 
 template <typename T>
@@ -491,17 +493,28 @@ __device__ __forceinline__ void sched_block_sums(double v1, double* out1, double
     }
 }
 
+// Read-only data the kernels read at wave-uniform addresses, seen through the
+// constant address space so that the reads are scalar loads.
+template <typename U>
+using CPtr = const U __attribute__((address_space(4)))*;
+template <typename U>
+__device__ __forceinline__ CPtr<U> const_ptr(const U* p) {
+    return (CPtr<U>)p;
+}
+
+
 template <typename T, typename E, int R, bool FUSE>
 __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, E> a, const SchedArgs<T> sc,
                                                               const T* __restrict__ x, T* __restrict__ y) {
     if (a.skip && *a.skip) return;
     constexpr int W = sizeof(T) / 4;      // 32-bit planes per row
     static_assert(R >= 1 && R <= 3 && (W == 1 || R == 1), "rows per group");
-    // elements per thread loaded ahead for the next group (the rest when it is staged)
-    constexpr int PER = FUSE ? (W == 1 ? 4 : 3) : 8;
-    extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t* planes = reinterpret_cast<uint32_t*>(smem);   // plane (r, word) at (r * W + word) * kSchedPlane
     constexpr uint32_t P = kSchedPlane;
+    // elements per thread loaded ahead for the next group
+    constexpr int PER = FUSE ? (W == 1 ? 4 : 3) : 8;
+    constexpr int NB = FUSE ? (W == 1 ? 8 : 4) : 16;   // batch of the remaining loads
+    __shared__ __align__(16) uint32_t planes[R * W * P];   // plane (r, word) at (r * W + word) * P
+    const unsigned char* lbase = reinterpret_cast<const unsigned char*>(planes);
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
     const uint32_t Dn = (uint32_t)D_dn;
     const uint64_t ngroups = (D_up + R - 1) / R;
@@ -535,7 +548,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     };
     // element of row r at byte address ba of plane r (ba = 4 d')
     auto get = [&](int r, uint32_t ba) -> T {
-        const uint32_t* pr = reinterpret_cast<const uint32_t*>(smem + ba);
+        const uint32_t* pr = reinterpret_cast<const uint32_t*>(lbase + ba);
         if constexpr (W == 1) {
             return (T)__uint_as_float(pr[(uint32_t)r * P]);
         } else {
@@ -571,45 +584,80 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
         nsum += (double)v * (double)v;
         return v;
     };
+    // +-magnitude bits: FP32 the whole word, FP64 the high word (the low word is the same for both signs)
+    auto hi_bits = [](T m) -> uint32_t {
+        if constexpr (W == 1) return __float_as_uint((float)m);
+        else return (uint32_t)((unsigned long long)__double_as_longlong((double)m) >> 32);
+    };
+    auto lo_bits = [](T m) -> uint32_t {
+        if constexpr (W == 1) return 0u;
+        else return (uint32_t)(unsigned long long)__double_as_longlong((double)m);
+    };
+    const uint32_t mp0 = hi_bits(sc.mag0), ml0 = lo_bits(sc.mag0);
+    const uint32_t mp1 = hi_bits(sc.mag1), ml1 = lo_bits(sc.mag1);
     if (blockIdx.x < ngroups) fetch(blockIdx.x);
     for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const uint64_t u0 = g * R;
         const int nr = (int)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
         const uint32_t nelem = (uint32_t)nr * Dn;
+        const uint32_t nput = (uint32_t)R * Dn;   // rows past the last are staged as zeros
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const uint32_t k = threadIdx.x + (uint32_t)i * kWideBlock;
-            if (k < (uint32_t)R * Dn) {
+            if (k < nput) {
                 T v = (T)0;
                 if (k < nelem) v = FUSE ? form(u0 * D_dn + k, pre[i], pz[i], p1[i], p2[i]) : pre[i];
                 put(k, v);
             }
         }
-        for (uint32_t k = threadIdx.x + (uint32_t)PER * kWideBlock; k < (uint32_t)R * Dn; k += kWideBlock) {
-            T v = (T)0;
-            if (k < nelem) {
-                const uint64_t e = u0 * D_dn + k;
-                if constexpr (FUSE)
-                    v = form(e, y[e], a.fz[e], a.fq1[e], a.fq2[e]);
-                else
-                    v = x[e];
+#pragma nounroll
+        for (uint32_t kb = threadIdx.x + (uint32_t)PER * kWideBlock; kb < nput; kb += (uint32_t)NB * kWideBlock) {
+            // every load of the batch issued before the first store to LDS
+            T v0[NB], v1[FUSE ? NB : 1], v2[FUSE ? NB : 1], v3[FUSE ? NB : 1];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const uint32_t k = kb + (uint32_t)j * kWideBlock;
+                if (k < nelem) {
+                    const uint64_t e = u0 * D_dn + k;
+                    if constexpr (FUSE) {
+                        v0[j] = y[e];
+                        v1[j] = a.fz[e];
+                        v2[j] = a.fq1[e];
+                        v3[j] = a.fq2[e];
+                    } else {
+                        v0[j] = __builtin_nontemporal_load(x + e);
+                    }
+                }
             }
-            put(k, v);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const uint32_t k = kb + (uint32_t)j * kWideBlock;
+                if (k < nput) {
+                    T v = (T)0;
+                    if (k < nelem) {
+                        if constexpr (FUSE)
+                            v = form(u0 * D_dn + k, v0[j], v1[j], v2[j], v3[j]);
+                        else
+                            v = v0[j];
+                    }
+                    put(k, v);
+                }
+            }
         }
         __syncthreads();
         if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
         uint32_t pu[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) pu[r] = a.up_states[u0 + (r < nr ? r : 0)];
-        const T m0 = sc.mag0, m1 = sc.mag1;
         for (uint32_t d0 = 0; d0 < Dn; d0 += kWideBlock) {
             const uint32_t wv = (d0 >> 6) + wave;
             if (wv >= nwaves) break;   // no barrier follows inside this loop
             // this wave's schedule words, all loaded before its steps start
-            const int n = sc.steps[2 * wv] / 2;     // words: a multiple of 4
-            const int nb = sc.steps[2 * wv + 1] / 2;
-            const uint32_t* wp = sc.words + sc.off[wv] + lane;
+            const uint32_t so = const_ptr(sc.off)[wv];
+            const int n = const_ptr(sc.steps)[2 * wv] / 2;       // words: a multiple of 2
+            const int nb = const_ptr(sc.steps)[2 * wv + 1] / 2;  // words of the smaller magnitude: a multiple of 2
+            const uint32_t* wp = sc.words + so + lane;
             uint32_t wbuf[kSchedMaxWords];
 #pragma unroll
             for (int i = 0; i < kSchedMaxWords; ++i) wbuf[i] = i < n ? wp[(uint32_t)i * 64u] : 0u;
@@ -617,33 +665,57 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
             const bool live = d < Dn;
             const uint32_t pd = live ? a.dn_states[d] : 0u;
             T acc[R];
+            if (a.add_y) {   // the up part of these elements, loaded with the schedule words
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                acc[r] = live ? a.U * (T)__builtin_popcount(pu[r] & pd) * get(r, d * 4u) : (T)0;
-            auto step = [&](uint32_t e, T m) {
-                T c;
-                if constexpr (W == 1) {
-                    c = __uint_as_float(__float_as_uint(m) ^ (e << 31));
-                } else {
-                    const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
-                    c = __longlong_as_double((long long)(mb ^ ((unsigned long long)(e & 1u) << 63)));
+                for (int r = 0; r < R; ++r)
+                    acc[r] = (live && r < nr) ? __builtin_nontemporal_load(y + (u0 + r) * D_dn + d) : (T)0;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T dg = live ? a.U * (T)__builtin_popcount(pu[r] & pd) * get(r, d * 4u) : (T)0;
+                acc[r] = a.add_y ? acc[r] + dg : dg;
+            }
+            // two words (four steps) per chunk, all of one magnitude: the chunk's reads are issued
+            // before its multiply-adds; the words sit in registers, indexed statically, and only
+            // the chunk tests branch (wave-uniform)
+            auto chunk = [&](int cc, uint32_t mp, uint32_t ml) {
+                uint32_t ba[4];
+                T xv[4][R];
+                uint32_t sh[4];   // signed magnitude bits of each step (mp has a clear sign bit,
+                                  // so adding 2^31 sets it)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint32_t wj = wbuf[2 * cc + j];
+                    ba[2 * j] = wj & 0xFFFCu;
+                    ba[2 * j + 1] = (wj >> 16) & 0xFFFCu;
+                    sh[2 * j] = (wj << 31) + mp;
+                    sh[2 * j + 1] = mp ^ ((wj >> 16) << 31);
                 }
-                const uint32_t ba = e & 0xFFFCu;
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[r] += c * get(r, ba);
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) xv[q][r] = get(r, ba[q]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t h = sh[q];
+                    T c;
+                    if constexpr (W == 1)
+                        c = __uint_as_float(h);
+                    else
+                        c = __longlong_as_double((long long)(((unsigned long long)h << 32) | ml));
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] += c * xv[q][r];
+                }
             };
-            // four words (eight steps) per chunk; the words sit in registers, indexed statically,
-            // and only the chunk test branches (wave-uniform)
+            uint32_t vp = mp0, vl = ml0;   // magnitude of the current chunk
 #pragma unroll
-            for (int c = 0; c < kSchedMaxWords / 4; ++c) {
-                if (4 * c < n) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int i = 4 * c + j;
-                        const T m = i < nb ? m0 : m1;
-                        step(wbuf[i] & 0xFFFFu, m);
-                        step(wbuf[i] >> 16, m);
+            for (int cc = 0; cc < kSchedMaxWords / 2; ++cc) {
+                if (2 * cc < n) {
+                    if (2 * cc == nb) {
+                        vp = mp1;
+                        vl = ml1;
                     }
+                    chunk(cc, vp, vl);
                 }
             }
             if (live) {
@@ -658,7 +730,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     }
     // the planes are free now: the work group's sums go through them
     sched_block_sums(dsum, a.dotp ? a.dotp + blockIdx.x : nullptr, nsum, FUSE ? a.fnorm + blockIdx.x : nullptr,
-                     reinterpret_cast<double*>(smem));
+                     reinterpret_cast<double*>(planes));
 }
 
 // Short rows: `rows` consecutive rows staged row-major; threads walk the
@@ -1064,6 +1136,7 @@ void launch_wide_fused(int variant, uint64_t grid, size_t lds, hipStream_t s, co
 // Scheduled down pass (plans down 5, 6, 7: 1, 2, 3 rows per group).
 bool sched_plan(int variant) { return variant >= 5 && variant <= 7; }
 int sched_rows(int variant) { return variant - 4; }
+// LDS bytes of the row planes (a static array of the kernel)
 size_t sched_lds(const pdz_problem_s* p, size_t es, int rows) {
     (void)p;
     return (size_t)rows * (es / 4) * kSchedPlane * 4;
@@ -1088,19 +1161,14 @@ void launch_sched(const pdz_problem_s* p, int variant, uint64_t grid, size_t lds
                   const DownArgs<T, E>& da, const T* x, T* y) {
     const dim3 g((unsigned)grid), b(kWideBlock);
     const SchedArgs<T> sa = sched_args<T>(p);
+    (void)lds;   // the planes are a static LDS array
+    lds = 0;
     if (variant == 7 && sizeof(T) == 4)
         hipLaunchKernelGGL((k_hv_down_sched<T, E, sizeof(T) == 4 ? 3 : 1, FUSE>), g, b, lds, s, da, sa, x, y);
     else if (variant == 6 && sizeof(T) == 4)
         hipLaunchKernelGGL((k_hv_down_sched<T, E, sizeof(T) == 4 ? 2 : 1, FUSE>), g, b, lds, s, da, sa, x, y);
     else
         hipLaunchKernelGGL((k_hv_down_sched<T, E, 1, FUSE>), g, b, lds, s, da, sa, x, y);
-}
-
-template <typename T, typename E, int R, bool FUSE>
-pdz_status set_sched_lds() {
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_sched<T, E, R, FUSE>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
-    return ok();
 }
 
 // Up-pass geometry: the x[:, chunk] slab one XCD streams over is
@@ -1255,76 +1323,12 @@ uint64_t up_blocks(const pdz_problem_s* p, size_t es, const HvPlan& plan) {
     return nch * rt;
 }
 
+// Up pass of the table path: yout = (add_y ? yout : 0) + the up hops of x.
 template <typename T, typename E>
-pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coef, const T* x, T* y, hipStream_t s,
-                      const int* skip, bool compact, unsigned passes, const HvSplit* split) {
+pdz_status up_pass(const pdz_problem_s* p, const T* coef, const T* x, T* yout, hipStream_t s, const int* skip,
+                   bool compact, const HvPlan& plan, int add_y, double* dotp) {
     const uint64_t D_up = p->up.D, D_dn = p->dn.D;
     const int ncoef = (int)p->coef_host.size();
-    // ---- down pass
-    DownArgs<T, E> da;
-    da.D_up = D_up;
-    da.D_dn = D_dn;
-    da.U = (T)p->U;
-    da.up_states = p->up.states;
-    da.dn_states = p->dn.states;
-    da.dn_count = p->dn.count;
-    fill_table_view<T, E>(p->dn, compact, &da.dn_ell, &da.tmask, &da.cshift);
-    da.ell_bytes = compact ? (uint32_t)(((uint64_t)(p->dn.max_hops + 1) & ~1ull) * D_dn * sizeof(uint16_t)) : 0u;
-    da.coef = coef;
-    da.ncoef = ncoef;
-    da.skip = skip;
-    da.dotp = split ? split->dotp_dn : nullptr;
-    const bool fused = split && split->fq2;
-    da.fz = fused ? static_cast<const T*>(split->fz) : nullptr;
-    da.fq1 = fused ? static_cast<const T*>(split->fq1) : nullptr;
-    da.fq2 = fused ? static_cast<T*>(split->fq2) : nullptr;
-    da.fkeep = fused ? static_cast<T*>(split->fkeep) : nullptr;
-    da.fkeep_ld = fused ? split->fkeep_ld : 0;
-    da.fkeep_cap = fused ? split->fkeep_cap : 0;
-    da.falpha = fused ? split->falpha : nullptr;
-    da.fbeta = fused ? split->fbeta : nullptr;
-    da.fsc = fused ? split->fsc : nullptr;
-    da.fkidx = fused ? split->fkidx : nullptr;
-    da.fnorm = fused ? split->fnorm : nullptr;
-    const HvPlan plan = hv_resolve(p, sizeof(T) == 8 ? PDZ_F64 : PDZ_F32);
-    const DownGeom gm = down_geom(p, sizeof(T), plan, (unsigned)ctx->cu_count);
-    da.rows = gm.rows;
-    if (fused) {
-        if (!(passes & kPassDown) || (passes & kPassUp) || !gm.wide ||
-            !(plan.down == 2 || plan.down == 3 || plan.down == 4 || sched_plan(plan.down)) || !split->dotp_dn ||
-            !split->fnorm)
-            return fail(PDZ_EINVAL, "fused recurrence needs the looped wide down pass, alone");
-        if (sched_plan(plan.down))
-            launch_sched<T, E, true>(p, plan.down, gm.grid, gm.lds, s, da, static_cast<const T*>(split->fq2), y);
-        else
-            launch_wide_fused<T, E>(plan.down, gm.grid, gm.lds, s, da, y);
-        PDZ_HIP(hipGetLastError());
-        return ok();
-    }
-    if (!(passes & kPassDown)) {
-        // up pass only
-    } else if (gm.wide && sched_plan(plan.down)) {
-        launch_sched<T, E, false>(p, plan.down, gm.grid, gm.lds, s, da, x, y);
-    } else if (gm.wide) {
-        launch_wide<T, E>(plan.down, p->dn.max_hops, gm.grid, gm.lds, s, da, x, y);
-    } else if (gm.stage) {
-        hipLaunchKernelGGL((k_hv_down_narrow<T, E, true>), dim3((unsigned)gm.grid), dim3(kNarrowBlock), gm.lds, s, da,
-                           x, y);
-    } else {
-        hipLaunchKernelGGL((k_hv_down_narrow<T, E, false>), dim3((unsigned)gm.grid), dim3(kNarrowBlock), gm.lds, s,
-                           da, x, y);
-    }
-    PDZ_HIP(hipGetLastError());
-    if (p->up.max_hops == 0 || !(passes & kPassUp)) {
-        if (split && split->z) {   // no up hops: the up term is zero
-            hipLaunchKernelGGL(k_zero_fill<T>, dim3(1024), dim3(256), 0, s, static_cast<T*>(split->z), p->D);
-            if (split->dotp_up) hipLaunchKernelGGL(k_zero_fill<double>, dim3(1), dim3(64), 0, s, split->dotp_up,
-                                                   (uint64_t)1);
-            PDZ_HIP(hipGetLastError());
-        }
-        return ok();
-    }
-    // ---- up pass
     UpArgs<T, E> ua;
     ua.D_up = D_up;
     ua.D_dn = D_dn;
@@ -1333,10 +1337,8 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     ua.coef = coef;
     ua.ncoef = ncoef;
     ua.skip = skip;
-    // split: the up term goes to its own buffer (no re-read of y); else it is added into y
-    ua.add_y = (split && split->z) ? 0 : 1;
-    ua.dotp = split ? split->dotp_up : nullptr;
-    T* yout = (split && split->z) ? static_cast<T*>(split->z) : y;
+    ua.add_y = add_y;
+    ua.dotp = dotp;
     const int CW = plan.up_cw;
     const int ROWS = up_tile_rows(sizeof(T), plan);
     const bool idx64 = p->D > 0xFFFFFFFFull;
@@ -1392,6 +1394,98 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     }
     PDZ_HIP(hipGetLastError());
     return ok();
+}
+
+
+template <typename T, typename E>
+pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coef, const T* x, T* y, hipStream_t s,
+                      const int* skip, bool compact, unsigned passes, const HvSplit* split) {
+    const uint64_t D_up = p->up.D, D_dn = p->dn.D;
+    const int ncoef = (int)p->coef_host.size();
+    // ---- down pass
+    DownArgs<T, E> da;
+    da.D_up = D_up;
+    da.D_dn = D_dn;
+    da.U = (T)p->U;
+    da.up_states = p->up.states;
+    da.dn_states = p->dn.states;
+    da.dn_count = p->dn.count;
+    fill_table_view<T, E>(p->dn, compact, &da.dn_ell, &da.tmask, &da.cshift);
+    da.ell_bytes = compact ? (uint32_t)(((uint64_t)(p->dn.max_hops + 1) & ~1ull) * D_dn * sizeof(uint16_t)) : 0u;
+    da.coef = coef;
+    da.ncoef = ncoef;
+    da.skip = skip;
+    da.add_y = 0;
+    da.dotp = split ? split->dotp_dn : nullptr;
+    const bool fused = split && split->fq2;
+    da.fz = fused ? static_cast<const T*>(split->fz) : nullptr;
+    da.fq1 = fused ? static_cast<const T*>(split->fq1) : nullptr;
+    da.fq2 = fused ? static_cast<T*>(split->fq2) : nullptr;
+    da.fkeep = fused ? static_cast<T*>(split->fkeep) : nullptr;
+    da.fkeep_ld = fused ? split->fkeep_ld : 0;
+    da.fkeep_cap = fused ? split->fkeep_cap : 0;
+    da.falpha = fused ? split->falpha : nullptr;
+    da.fbeta = fused ? split->fbeta : nullptr;
+    da.fsc = fused ? split->fsc : nullptr;
+    da.fkidx = fused ? split->fkidx : nullptr;
+    da.fnorm = fused ? split->fnorm : nullptr;
+    const HvPlan plan = hv_resolve(p, sizeof(T) == 8 ? PDZ_F64 : PDZ_F32);
+    const DownGeom gm = down_geom(p, sizeof(T), plan, (unsigned)ctx->cu_count);
+    da.rows = gm.rows;
+    if (fused) {
+        if (!(passes & kPassDown) || (passes & kPassUp) || !gm.wide ||
+            !(plan.down == 2 || plan.down == 3 || plan.down == 4 || sched_plan(plan.down)) || !split->dotp_dn ||
+            !split->fnorm)
+            return fail(PDZ_EINVAL, "fused recurrence needs the looped wide down pass, alone");
+        if (sched_plan(plan.down))
+            launch_sched<T, E, true>(p, plan.down, gm.grid, gm.lds, s, da, static_cast<const T*>(split->fq2), y);
+        else
+            launch_wide_fused<T, E>(plan.down, gm.grid, gm.lds, s, da, y);
+        PDZ_HIP(hipGetLastError());
+        return ok();
+    }
+    if (!split && gm.wide && sched_plan(plan.down) && p->up.max_hops > 0) {
+        // the up pass writes y and the down pass adds its part as it stores
+        // (so no pass re-reads y in its gathers); element sum: up hops, then
+        // the diagonal, then the down hops
+        if (passes & kPassUp) {
+            const pdz_status st = up_pass<T, E>(p, coef, x, y, s, skip, compact, plan, 0, nullptr);
+            if (st != PDZ_OK) return st;
+        }
+        if (passes & kPassDown) {
+            da.add_y = 1;
+            launch_sched<T, E, false>(p, plan.down, gm.grid, gm.lds, s, da, x, y);
+            PDZ_HIP(hipGetLastError());
+        }
+        return ok();
+    }
+    if (!(passes & kPassDown)) {
+        // up pass only
+    } else if (gm.wide && sched_plan(plan.down)) {
+        launch_sched<T, E, false>(p, plan.down, gm.grid, gm.lds, s, da, x, y);
+    } else if (gm.wide) {
+        launch_wide<T, E>(plan.down, p->dn.max_hops, gm.grid, gm.lds, s, da, x, y);
+    } else if (gm.stage) {
+        hipLaunchKernelGGL((k_hv_down_narrow<T, E, true>), dim3((unsigned)gm.grid), dim3(kNarrowBlock), gm.lds, s, da,
+                           x, y);
+    } else {
+        hipLaunchKernelGGL((k_hv_down_narrow<T, E, false>), dim3((unsigned)gm.grid), dim3(kNarrowBlock), gm.lds, s,
+                           da, x, y);
+    }
+    PDZ_HIP(hipGetLastError());
+    if (p->up.max_hops == 0 || !(passes & kPassUp)) {
+        if (split && split->z) {   // no up hops: the up term is zero
+            hipLaunchKernelGGL(k_zero_fill<T>, dim3(1024), dim3(256), 0, s, static_cast<T*>(split->z), p->D);
+            if (split->dotp_up) hipLaunchKernelGGL(k_zero_fill<double>, dim3(1), dim3(64), 0, s, split->dotp_up,
+                                                   (uint64_t)1);
+            PDZ_HIP(hipGetLastError());
+        }
+        return ok();
+    }
+    // split: the up term goes to its own buffer (no re-read of y); else it is added into y
+    if (split && split->z)
+        return up_pass<T, E>(p, coef, x, static_cast<T*>(split->z), s, skip, compact, plan, 0, split->dotp_up);
+    return up_pass<T, E>(p, coef, x, y, s, skip, compact, plan, 1, split ? split->dotp_up : nullptr);
 }
 
 template <typename T>
@@ -1467,14 +1561,6 @@ pdz_status prepare_one() {
     if (st == PDZ_OK) st = set_wide_lds<T, E, 1, 0, true>();
     if (st == PDZ_OK) st = set_wide_lds<T, E, 2, 0, true>();
     if (st == PDZ_OK) st = set_wide_lds<T, E, 3, 0, true>();
-    if (st == PDZ_OK) st = set_sched_lds<T, E, 1, false>();
-    if (st == PDZ_OK) st = set_sched_lds<T, E, 1, true>();
-    if (sizeof(T) == 4) {
-        if (st == PDZ_OK) st = set_sched_lds<T, E, sizeof(T) == 4 ? 2 : 1, false>();
-        if (st == PDZ_OK) st = set_sched_lds<T, E, sizeof(T) == 4 ? 2 : 1, true>();
-        if (st == PDZ_OK) st = set_sched_lds<T, E, sizeof(T) == 4 ? 3 : 1, false>();
-        if (st == PDZ_OK) st = set_sched_lds<T, E, sizeof(T) == 4 ? 3 : 1, true>();
-    }
     if (st != PDZ_OK) return st;
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_down_narrow<T, E, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));

@@ -33,12 +33,13 @@ struct BondDev {
 };
 
 // Bank-conflict-free gather schedule of the down pass over one sector
-// (pdz_sched.cpp): per wave of 64 columns an even number of steps S, the
-// first B of them with the smaller hop magnitude mag0, the rest with mag1;
-// a step is a 16-bit entry per lane, (target word in a row plane of
-// kSchedPlane words, whose last 32 are zeros) << 2 | sign.
-// words[off[w] + (t / 2) * 64 + lane] holds steps t and t + 1 of wave w;
-// steps[2 w] = S, steps[2 w + 1] = B.  words == NULL: no schedule.
+// (pdz_sched.cpp): per wave of 64 columns S steps (a multiple of 4), the
+// first B of them (a multiple of 4) with the smaller hop magnitude mag0, the
+// rest with mag1.  A step is a 16-bit entry per lane: the byte address of its
+// target in a row plane of kSchedPlane words (the last 32 are zeros), bit 0
+// set when the lane adds -mag.  words[off[w] + (t / 2) * 64 + lane] holds
+// steps t (low half) and t + 1 of wave w; steps[2 w] = S, steps[2 w + 1] = B.
+// words == NULL: no schedule.
 constexpr uint32_t kSchedPlane = 13312;   // words per plane: sectors of at most 13280 states
 constexpr int kSchedMaxSteps = 64;        // a longer schedule is not built
 struct DownSchedule {

@@ -17,14 +17,14 @@
 // that step, and add nothing.
 //
 // Steps are grouped by hop magnitude (all steps of the smaller magnitude
-// first, then the larger), so the magnitude of a step is the same in every
-// lane.  Entry (16 bits): (target index into the plane << 2) | sign (1: the
-// hop's amplitude is minus the magnitude), the target index below
-// kSchedPlane, whose last 32 words are the zero pad.  Layout: wave w (64
-// columns, two groups) has S_w steps, a multiple of 8 (idle steps read the
-// pad), the first B_w of the smaller magnitude (even); its entries are 32-bit
-// words
-// words[off_w + (t / 2) * 64 + lane] holding steps t (low half) and t + 1.
+// first, then the larger, each group a multiple of 4 steps), so the magnitude
+// of a step is the same in every lane; its sign comes with the lane's entry.
+// Entry (16 bits): the byte address of the target in its plane of
+// kSchedPlane words (whose last 32 words are the zero pad), with bit 0 set
+// when the hop's amplitude is minus the magnitude.  Layout: wave w (64
+// columns, two groups) has S_w steps, the first B_w of the smaller magnitude;
+// its entries are 32-bit words words[off_w + (t / 2) * 64 + lane] holding
+// steps t (low half) and t + 1.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -107,7 +107,7 @@ pdz_status build_down_schedule(const SectorTables& t, const std::vector<double>&
     std::vector<uint32_t> words;
     words.reserve(D * 24);
     for (uint64_t w = 0; w < nwaves; ++w) {
-        // per magnitude class: the colouring of each half-wave, steps = max over the two halves (even)
+        // per magnitude class: the colouring of each half-wave, steps = max over the two halves
         std::vector<uint16_t> ent;   // [step][lane]
         int S = 0, B = 0;
         for (int cls = 0; cls < ncls; ++cls) {
@@ -125,7 +125,7 @@ pdz_status build_down_schedule(const SectorTables& t, const std::vector<double>&
                         if ((std::fabs(c) == mags[0] ? 0 : 1) != cls) continue;
                         const uint32_t tg = e & kTargetMask;
                         edges[half].push_back({l, (int)(tg % 32)});
-                        val[half].push_back((uint16_t)((tg << 2) | (c < 0.0 ? 1u : 0u)));
+                        val[half].push_back((uint16_t)((tg << 1) | (c < 0.0 ? 1u : 0u)));   // target, sign
                         ++ldeg[l];
                         ++bdeg[tg % 32];
                     }
@@ -134,7 +134,7 @@ pdz_status build_down_schedule(const SectorTables& t, const std::vector<double>&
                                        *std::max_element(bdeg.begin(), bdeg.end()));
             }
             int Sc = std::max(delta[0], delta[1]);
-            Sc = (Sc + 1) & ~1;   // steps in pairs
+            Sc = (Sc + 3) & ~3;   // the kernel walks the steps four at a time
             const size_t base = ent.size() / 64;
             ent.resize((base + Sc) * 64);
             for (int half = 0; half < 2; ++half) {
@@ -151,7 +151,7 @@ pdz_status build_down_schedule(const SectorTables& t, const std::vector<double>&
                         const int e = at[(size_t)st * 32 + l];
                         uint16_t v;
                         if (e >= 0) {
-                            v = val[half][e];
+                            v = (uint16_t)(((val[half][e] >> 1) << 2) | (val[half][e] & 1u));
                         } else {
                             const int b = __builtin_ctz(freeb);   // a bank no lane reads at this step
                             freeb &= freeb - 1u;
@@ -165,13 +165,6 @@ pdz_status build_down_schedule(const SectorTables& t, const std::vector<double>&
             S += Sc;
         }
         if (ncls == 1) B = S;
-        while (S % 8) {   // the kernel walks the steps eight at a time: idle steps to a multiple of eight
-            const size_t base = ent.size() / 64;
-            ent.resize((base + 1) * 64);
-            for (int half = 0; half < 2; ++half)
-                for (int l = 0; l < 32; ++l) ent[base * 64 + half * 32 + l] = (uint16_t)((P - 32 + l) << 2);
-            ++S;
-        }
         if (S > kSchedMaxSteps) return ok();   // the kernel holds at most kSchedMaxSteps steps per wave
         // check: each half-wave step reads 32 different banks, and each column's
         // scheduled (target, sign, magnitude) triples are its hop list
@@ -194,6 +187,7 @@ pdz_status build_down_schedule(const SectorTables& t, const std::vector<double>&
                 for (int st = 0; st < S; ++st) {
                     const uint16_t v = ent[(size_t)st * 64 + half * 32 + l];
                     if ((uint32_t)(v >> 2) < P - 32) got.push_back((uint32_t)v | ((st >= B ? 1u : 0u) << 20));
+                    else if (v & 1u) return fail(PDZ_EDEVICE, "gather schedule: an idle lane carries a sign");
                 }
                 std::sort(want.begin(), want.end());
                 std::sort(got.begin(), got.end());

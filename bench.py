@@ -637,7 +637,8 @@ def main():
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the learned-start section and print its JSON object")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain device copy of D floats (known bytes) to scale counter readings")
+                    help="also run a plain device copy of D floats and a plain gather of 512-byte segments "
+                         "(known bytes) to scale counter readings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -717,8 +718,29 @@ def main():
         ev1.synchronize()
         cms = ev0.elapsed_time(ev1) / 5
         copy = {"bytes_read": D * 4, "bytes_written": D * 4, "ms": cms, "GBs": 2 * D * 4 / (cms * 1e-3) / 1e9}
+        # a plain gather of known bytes: every 512-byte segment (128 floats, one row segment of the
+        # up pass's 128-column chunks) read exactly once, in a random order, and written in order;
+        # its counter readings check the copy's scale factors on a gather
+        seg = 128
+        nseg = D // seg
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(20171207)
+        perm = torch.randperm(nseg, device="cuda", generator=gen)
+        srcv = src[:nseg * seg].view(nseg, seg)
+        dstv = dst[:nseg * seg].view(nseg, seg)
+        for _ in range(2):
+            torch.index_select(srcv, 0, perm, out=dstv)
+        ev0.record()
+        for _ in range(5):
+            torch.index_select(srcv, 0, perm, out=dstv)
+        ev1.record()
+        ev1.synchronize()
+        gms = ev0.elapsed_time(ev1) / 5
+        gb = nseg * seg * 4
+        copy["gather"] = {"segment_bytes": seg * 4, "segments": nseg, "bytes_read": gb, "bytes_written": gb,
+                          "index_bytes": nseg * 8, "ms": gms, "GBs": 2 * gb / (gms * 1e-3) / 1e9}
         detail["copy_calibration"] = copy
-        del src, dst
+        del src, dst, perm, srcv, dstv
 
     tte = None
     if not args.no_time_to_e0:

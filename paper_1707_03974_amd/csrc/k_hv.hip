@@ -463,8 +463,7 @@ constexpr int kSchedMaxWords = kSchedMaxSteps / 2;   // schedule words a wave ho
 template <typename T>
 struct SchedArgs {
     const uint32_t* words;
-    const uint32_t* off;
-    const uint16_t* steps;
+    const uint32_t* meta;  // per wave: word offset, steps | steps of the smaller magnitude << 16
     T mag0, mag1;          // hop magnitudes of the two step groups
 };
 
@@ -510,9 +509,10 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     constexpr int W = sizeof(T) / 4;      // 32-bit planes per row
     static_assert(R >= 1 && R <= 3 && (W == 1 || R == 1), "rows per group");
     constexpr uint32_t P = kSchedPlane;
-    // elements per thread loaded ahead for the next group
-    constexpr int PER = FUSE ? (W == 1 ? 4 : 3) : 8;
-    constexpr int NB = FUSE ? (W == 1 ? 8 : 4) : 16;   // batch of the remaining loads
+    // staging by quads of four consecutive elements of the group: quads per thread loaded ahead
+    // for the next group, and quads per batch of the remaining loads
+    constexpr int PQ = FUSE ? 1 : 2;
+    constexpr int NQ = FUSE ? (W == 1 ? 2 : 1) : 4;
     __shared__ __align__(16) uint32_t planes[R * W * P];   // plane (r, word) at (r * W + word) * P
     const unsigned char* lbase = reinterpret_cast<const unsigned char*>(planes);
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
@@ -555,34 +555,70 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
             return (T)__longlong_as_double((long long)(((unsigned long long)pr[P] << 32) | pr[0]));
         }
     };
-    T pre[PER];
-    T pz[FUSE ? PER : 1], p1[FUSE ? PER : 1], p2[FUSE ? PER : 1];
+    // the four elements of quad k0 / 4 of the group (k0 + j < nelem of them exist)
+    auto load4 = [&](const T* base, uint64_t e0, uint32_t k0, uint32_t nelem, T (&v)[4], bool stream) {
+        if (k0 + 4 <= nelem) {
+            if (stream) {
+                typedef T vt __attribute__((ext_vector_type(4), aligned(sizeof(T))));
+                const vt t = __builtin_nontemporal_load(reinterpret_cast<const vt*>(base + e0));
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = t[j];
+            } else {
+                vec_load<T, 4>(base + e0, v);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = (k0 + (uint32_t)j < nelem) ? base[e0 + j] : (T)0;
+        }
+    };
+    T pre[PQ][4];
+    T pz[FUSE ? PQ : 1][4], p1[FUSE ? PQ : 1][4], p2[FUSE ? PQ : 1][4];
     auto fetch = [&](uint64_t g) {
         const uint64_t u0 = g * R;
-        const uint64_t nelem = ((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * D_dn;
+        const uint32_t nelem = (uint32_t)(((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * D_dn);
         const uint64_t off = u0 * D_dn;
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const uint64_t k = threadIdx.x + (uint64_t)i * kWideBlock;
-            if constexpr (FUSE) {
-                if (k < nelem) {
-                    pre[i] = y[off + k];
-                    pz[i] = a.fz[off + k];
-                    p1[i] = a.fq1[off + k];
-                    p2[i] = a.fq2[off + k];
+        for (int i = 0; i < PQ; ++i) {
+            const uint32_t k0 = 4u * (threadIdx.x + (uint32_t)i * kWideBlock);
+            if (k0 < nelem) {
+                if constexpr (FUSE) {
+                    load4(y, off + k0, k0, nelem, pre[i], false);
+                    load4(a.fz, off + k0, k0, nelem, pz[i], false);
+                    load4(a.fq1, off + k0, k0, nelem, p1[i], false);
+                    load4(a.fq2, off + k0, k0, nelem, p2[i], false);
+                } else {
+                    load4(x, off + k0, k0, nelem, pre[i], true);
                 }
-            } else {
-                pre[i] = (k < nelem) ? __builtin_nontemporal_load(x + off + k) : (T)0;
             }
         }
     };
-    // q_{k+1} at element e (FUSE), stored back and counted in |q_{k+1}|^2
-    auto form = [&](uint64_t e, T hd, T hu, T q1, T q2) -> T {
-        const T v = lanczos_recurrence<T>(hd, hu, q1, q2, fa, fb, fc);
-        a.fq2[e] = v;
-        if (fkeep) fkeep[e] = v;
-        nsum += (double)v * (double)v;
-        return v;
+    // q_{k+1} at the elements of quad k0 / 4 (FUSE), stored back and counted in |q_{k+1}|^2
+    auto form4 = [&](uint64_t e0, uint32_t k0, uint32_t nelem, const T (&hd)[4], const T (&hu)[4], const T (&q1)[4],
+                     const T (&q2)[4], T (&v)[4]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = lanczos_recurrence<T>(hd[j], hu[j], q1[j], q2[j], fa, fb, fc);
+        if (k0 + 4 <= nelem) {
+            vec_store<T, 4>(a.fq2 + e0, v);
+            if (fkeep) vec_store<T, 4>(fkeep + e0, v);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) nsum += (double)v[j] * (double)v[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (k0 + (uint32_t)j < nelem) {
+                    a.fq2[e0 + j] = v[j];
+                    if (fkeep) fkeep[e0 + j] = v[j];
+                    nsum += (double)v[j] * (double)v[j];
+                }
+        }
+    };
+    // the staged values of quad k0 / 4 into the planes (zeros past the group's last element)
+    auto put4 = [&](uint32_t k0, uint32_t nelem, uint32_t nput, const T (&v)[4]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t k = k0 + (uint32_t)j;
+            if (k < nput) put(k, k < nelem ? v[j] : (T)0);
+        }
     };
     // +-magnitude bits: FP32 the whole word, FP64 the high word (the low word is the same for both signs)
     auto hi_bits = [](T m) -> uint32_t {
@@ -603,45 +639,48 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
         const uint32_t nput = (uint32_t)R * Dn;   // rows past the last are staged as zeros
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const uint32_t k = threadIdx.x + (uint32_t)i * kWideBlock;
-            if (k < nput) {
-                T v = (T)0;
-                if (k < nelem) v = FUSE ? form(u0 * D_dn + k, pre[i], pz[i], p1[i], p2[i]) : pre[i];
-                put(k, v);
+        for (int i = 0; i < PQ; ++i) {
+            const uint32_t k0 = 4u * (threadIdx.x + (uint32_t)i * kWideBlock);
+            if (k0 < nput) {
+                T v[4];
+                if constexpr (FUSE) {
+                    if (k0 < nelem) form4(u0 * D_dn + k0, k0, nelem, pre[i], pz[i], p1[i], p2[i], v);
+                    put4(k0, nelem, nput, v);
+                } else {
+                    put4(k0, nelem, nput, pre[i]);
+                }
             }
         }
 #pragma nounroll
-        for (uint32_t kb = threadIdx.x + (uint32_t)PER * kWideBlock; kb < nput; kb += (uint32_t)NB * kWideBlock) {
+        for (uint32_t qb = threadIdx.x + (uint32_t)PQ * kWideBlock; 4u * qb < nput; qb += (uint32_t)NQ * kWideBlock) {
             // every load of the batch issued before the first store to LDS
-            T v0[NB], v1[FUSE ? NB : 1], v2[FUSE ? NB : 1], v3[FUSE ? NB : 1];
+            T v0[NQ][4], v1[FUSE ? NQ : 1][4], v2[FUSE ? NQ : 1][4], v3[FUSE ? NQ : 1][4];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const uint32_t k = kb + (uint32_t)j * kWideBlock;
-                if (k < nelem) {
-                    const uint64_t e = u0 * D_dn + k;
+            for (int j = 0; j < NQ; ++j) {
+                const uint32_t k0 = 4u * (qb + (uint32_t)j * kWideBlock);
+                if (k0 < nelem) {
+                    const uint64_t e0 = u0 * D_dn + k0;
                     if constexpr (FUSE) {
-                        v0[j] = y[e];
-                        v1[j] = a.fz[e];
-                        v2[j] = a.fq1[e];
-                        v3[j] = a.fq2[e];
+                        load4(y, e0, k0, nelem, v0[j], false);
+                        load4(a.fz, e0, k0, nelem, v1[j], false);
+                        load4(a.fq1, e0, k0, nelem, v2[j], false);
+                        load4(a.fq2, e0, k0, nelem, v3[j], false);
                     } else {
-                        v0[j] = __builtin_nontemporal_load(x + e);
+                        load4(x, e0, k0, nelem, v0[j], true);
                     }
                 }
             }
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const uint32_t k = kb + (uint32_t)j * kWideBlock;
-                if (k < nput) {
-                    T v = (T)0;
-                    if (k < nelem) {
-                        if constexpr (FUSE)
-                            v = form(u0 * D_dn + k, v0[j], v1[j], v2[j], v3[j]);
-                        else
-                            v = v0[j];
+            for (int j = 0; j < NQ; ++j) {
+                const uint32_t k0 = 4u * (qb + (uint32_t)j * kWideBlock);
+                if (k0 < nput) {
+                    if constexpr (FUSE) {
+                        T v[4];
+                        if (k0 < nelem) form4(u0 * D_dn + k0, k0, nelem, v0[j], v1[j], v2[j], v3[j], v);
+                        put4(k0, nelem, nput, v);
+                    } else {
+                        put4(k0, nelem, nput, v0[j]);
                     }
-                    put(k, v);
                 }
             }
         }
@@ -650,17 +689,45 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
         uint32_t pu[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) pu[r] = a.up_states[u0 + (r < nr ? r : 0)];
+        const CPtr<uint32_t> cmeta = const_ptr(sc.meta);
+        uint32_t m_off = 0u, m_steps = 0u;   // the record of the wave's next column group
+        if (wave < nwaves) {
+            m_off = cmeta[2 * wave];
+            m_steps = cmeta[2 * wave + 1];
+        }
         for (uint32_t d0 = 0; d0 < Dn; d0 += kWideBlock) {
             const uint32_t wv = (d0 >> 6) + wave;
             if (wv >= nwaves) break;   // no barrier follows inside this loop
-            // this wave's schedule words, all loaded before its steps start
-            const uint32_t so = const_ptr(sc.off)[wv];
-            const int n = const_ptr(sc.steps)[2 * wv] / 2;       // words: a multiple of 2
-            const int nb = const_ptr(sc.steps)[2 * wv + 1] / 2;  // words of the smaller magnitude: a multiple of 2
-            const uint32_t* wp = sc.words + so + lane;
+            // this wave's schedule words, all loaded before its steps start (its record was read
+            // one column iteration ahead)
+            const uint32_t so = m_off;
+            const int n = (int)(m_steps & 0xFFFFu) / 2;   // words: a multiple of 2
+            const int nb = (int)(m_steps >> 16) / 2;      // words of the smaller magnitude: a multiple of 2
+            if (wv + kWideBlock / 64 < nwaves) {
+                m_off = cmeta[2 * (wv + kWideBlock / 64)];
+                m_steps = cmeta[2 * (wv + kWideBlock / 64) + 1];
+            }
+            // four words per lane in one 16-byte load (a last pair in one 8-byte load)
+            const uint32_t* wp = sc.words + so;
             uint32_t wbuf[kSchedMaxWords];
 #pragma unroll
-            for (int i = 0; i < kSchedMaxWords; ++i) wbuf[i] = i < n ? wp[(uint32_t)i * 64u] : 0u;
+            for (int q = 0; q < kSchedMaxWords / 4; ++q) {
+                if (4 * q + 4 <= n) {
+                    const uint4 w4 = *reinterpret_cast<const uint4*>(wp + (uint32_t)q * 256u + (uint32_t)lane * 4u);
+                    wbuf[4 * q] = w4.x;
+                    wbuf[4 * q + 1] = w4.y;
+                    wbuf[4 * q + 2] = w4.z;
+                    wbuf[4 * q + 3] = w4.w;
+                } else if (4 * q < n) {
+                    const uint2 w2 = *reinterpret_cast<const uint2*>(wp + (uint32_t)q * 256u + (uint32_t)lane * 2u);
+                    wbuf[4 * q] = w2.x;
+                    wbuf[4 * q + 1] = w2.y;
+                    wbuf[4 * q + 2] = 0u;
+                    wbuf[4 * q + 3] = 0u;
+                } else {
+                    wbuf[4 * q] = wbuf[4 * q + 1] = wbuf[4 * q + 2] = wbuf[4 * q + 3] = 0u;
+                }
+            }
             const uint32_t d = d0 + threadIdx.x;
             const bool live = d < Dn;
             const uint32_t pd = live ? a.dn_states[d] : 0u;
@@ -1149,8 +1216,7 @@ template <typename T>
 SchedArgs<T> sched_args(const pdz_problem_s* p) {
     SchedArgs<T> sa;
     sa.words = p->dn.sched.words;
-    sa.off = p->dn.sched.off;
-    sa.steps = p->dn.sched.steps;
+    sa.meta = p->dn.sched.meta;
     sa.mag0 = (T)p->dn.sched.mag0;
     sa.mag1 = (T)p->dn.sched.mag1;
     return sa;

@@ -37,15 +37,16 @@ struct BondDev {
 // first B of them (a multiple of 4) with the smaller hop magnitude mag0, the
 // rest with mag1.  A step is a 16-bit entry per lane: the byte address of its
 // target in a row plane of kSchedPlane words (the last 32 are zeros), bit 0
-// set when the lane adds -mag.  words[off[w] + (t / 2) * 64 + lane] holds
-// steps t (low half) and t + 1 of wave w; steps[2 w] = S, steps[2 w + 1] = B.
-// words == NULL: no schedule.
+// set when the lane adds -mag.  Word i of a lane holds steps 2i (low half)
+// and 2i + 1; a lane's words lie four at a time, words[off[w] + q * 256 +
+// lane * 4 + j] = word 4q + j of wave w (a last pair: lane * 2 + j);
+// meta[2 w] = off[w], meta[2 w + 1] = S | B << 16.  words == NULL: no
+// schedule.
 constexpr uint32_t kSchedPlane = 13312;   // words per plane: sectors of at most 13280 states
 constexpr int kSchedMaxSteps = 64;        // a longer schedule is not built
 struct DownSchedule {
     uint32_t* words = nullptr;
-    uint32_t* off = nullptr;     // per wave, and the total behind the last
-    uint16_t* steps = nullptr;   // per wave: S, B
+    uint32_t* meta = nullptr;    // per wave: word offset, S | B << 16
     uint32_t plane = 0;
     double mag0 = 0.0, mag1 = 0.0;
     size_t nwords = 0;

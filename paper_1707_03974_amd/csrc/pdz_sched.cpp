@@ -23,8 +23,10 @@
 // kSchedPlane words (whose last 32 words are the zero pad), with bit 0 set
 // when the hop's amplitude is minus the magnitude.  Layout: wave w (64
 // columns, two groups) has S_w steps, the first B_w of the smaller magnitude;
-// its entries are 32-bit words words[off_w + (t / 2) * 64 + lane] holding
-// steps t (low half) and t + 1.
+// word i of a lane holds steps 2i (low half) and 2i + 1, and a lane's words
+// are stored four at a time, words[off_w + q * 256 + lane * 4 + j] = word
+// 4q + j, the last two of an odd number of pairs as words[off_w + q * 256 +
+// lane * 2 + j].
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -197,22 +199,29 @@ pdz_status build_down_schedule(const SectorTables& t, const std::vector<double>&
         steps[w] = (uint16_t)S;
         split[w] = (uint16_t)B;
         off[w] = (uint32_t)words.size();
-        for (int st = 0; st < S; st += 2)
+        // word i of lane l (steps 2i, 2i + 1): four words of a lane side by side (one 16-byte load),
+        // the last two (when S / 2 is not a multiple of 4) as a pair
+        const int nw = S / 2;
+        auto word = [&](int i, int l) {
+            return (uint32_t)ent[(size_t)(2 * i) * 64 + l] | ((uint32_t)ent[(size_t)(2 * i + 1) * 64 + l] << 16);
+        };
+        for (int q = 0; 4 * q < nw; ++q) {
+            const int g = std::min(4, nw - 4 * q);
             for (int l = 0; l < 64; ++l)
-                words.push_back((uint32_t)ent[(size_t)st * 64 + l] | ((uint32_t)ent[(size_t)(st + 1) * 64 + l] << 16));
+                for (int j = 0; j < g; ++j) words.push_back(word(4 * q + j, l));
+        }
     }
     off[nwaves] = (uint32_t)words.size();
-    PDZ_HIP(hipMalloc(&out->words, std::max<size_t>(1, words.size()) * sizeof(uint32_t)));
-    PDZ_HIP(hipMalloc(&out->off, off.size() * sizeof(uint32_t)));
-    PDZ_HIP(hipMalloc(&out->steps, 2 * steps.size() * sizeof(uint16_t)));
-    std::vector<uint16_t> ss(2 * nwaves);
+    // per wave one record: word offset, then S | B << 16
+    std::vector<uint32_t> meta(2 * nwaves);
     for (uint64_t w = 0; w < nwaves; ++w) {
-        ss[2 * w] = steps[w];
-        ss[2 * w + 1] = split[w];
+        meta[2 * w] = off[w];
+        meta[2 * w + 1] = (uint32_t)steps[w] | ((uint32_t)split[w] << 16);
     }
+    PDZ_HIP(hipMalloc(&out->words, std::max<size_t>(1, words.size()) * sizeof(uint32_t)));
+    PDZ_HIP(hipMalloc(&out->meta, meta.size() * sizeof(uint32_t)));
     PDZ_HIP(hipMemcpy(out->words, words.data(), words.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    PDZ_HIP(hipMemcpy(out->off, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    PDZ_HIP(hipMemcpy(out->steps, ss.data(), ss.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    PDZ_HIP(hipMemcpy(out->meta, meta.data(), meta.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     out->plane = P;
     out->mag0 = mags[0];
     out->mag1 = mags.size() > 1 ? mags[1] : mags[0];
@@ -222,8 +231,7 @@ pdz_status build_down_schedule(const SectorTables& t, const std::vector<double>&
 
 void free_down_schedule(DownSchedule* sc) {
     if (sc->words) (void)hipFree(sc->words);
-    if (sc->off) (void)hipFree(sc->off);
-    if (sc->steps) (void)hipFree(sc->steps);
+    if (sc->meta) (void)hipFree(sc->meta);
     *sc = DownSchedule{};
 }
 

@@ -939,6 +939,17 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
         const UpHop<T>* hp = s_hop + r * maxh;
         const uint64_t* o64 = s_off64 + r * maxh;
         T* yr = y + u * D_dn + d;
+        // x at this row's own elements, for the x . out partial: loaded now, used after the hops
+        T xo[VEC];
+        if (a.dotp) {
+            const T* xr = x + u * D_dn + d;
+            if (nv == VEC) {
+                vec_load<T, VEC>(xr, xo);
+            } else {
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) xo[i] = (i < nv) ? xr[i] : (T)0;
+            }
+        }
         T acc[VEC];
         if (!a.add_y) {
 #pragma unroll
@@ -1007,10 +1018,9 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
                 if (i < nv) yr[i] = acc[i];
         }
         if (a.dotp) {
-            const T* xr = x + u * D_dn + d;
 #pragma unroll
             for (int i = 0; i < VEC; ++i)
-                if (i < nv) dsum += (double)xr[i] * (double)acc[i];
+                if (i < nv) dsum += (double)xo[i] * (double)acc[i];
         }
     }
     if (a.dotp) block_dot_store<kUpBlock>(dsum, a.dotp + blockIdx.x);

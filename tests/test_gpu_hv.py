@@ -220,3 +220,38 @@ def test_problem_plan_cache_round_trip(tmp_path):
     e2, t2 = tuning.tuned_plan(g, "f64", reps=1, path=path)
     assert t2 is None and e2 == e1
     assert g.get_plan("f64") == {k: e1[k] for k in ("down", "up_cw", "up", "map")}
+
+
+def _ring14(amps):
+    """14-site ring, 2 up and 7 down electrons (down rows of 3432 states: the wide down pass),
+    bond b carrying amplitude amps[b % len(amps)]."""
+    bonds = [(i, (i + 1) % 14, float(amps[i % len(amps)])) for i in range(14)]
+    return 14, bonds, 1.5, 2, 7
+
+
+@pytest.mark.parametrize("amps,scheduled", [((1.0, -0.45), True), ((1.0, 0.7, -0.4), False)])
+def test_down_families_on_rows_with_and_without_a_gather_schedule(amps, scheduled):
+    """A down sector with at most two hop magnitudes gets the bank-conflict-free gather schedule
+    (plans 5-7 by default); one with three keeps the looped family (plans 1-4).  Either way each
+    element equals the oracle within its own rounding bound; the looped family, set explicitly on the
+    scheduled problem, does too."""
+    torch = torch_cuda()
+    args = _ring14(amps)
+    g = _gpu_problem(args)
+    po = _oracle_problem(*args)
+    x = synth.random_vector(g.D, 17)
+    rows = np.unique(np.random.default_rng(3).integers(0, g.D, 3000))
+    ref, asum, nterm = oracle.hv_rows(po, x, rows, with_abs=True)
+    rows_d = torch.from_numpy(rows).cuda()
+    for dt, eps in ((torch.float64, EPS64), (torch.float32, EPS32)):
+        name = "f64" if dt == torch.float64 else "f32"
+        down = g.get_plan(name)["down"]
+        assert (5 <= down <= 7) if scheduled else (1 <= down <= 4), (amps, name, down)
+        plans = [0] + ([2] if scheduled else [])
+        for pl in plans:
+            g.set_plan(name, pl, 0, 0, 0)
+            y = to_host(g.hv(to_dev(x, dt))[rows_d])
+            bound = (nterm + 2) * eps * asum + nterm * EPS64 * asum
+            err = np.abs(y - ref)
+            assert np.all(err <= bound), (amps, name, pl, float(np.max(err / np.maximum(bound, 1e-300))))
+        g.set_plan(name, 0, 0, 0, 0)

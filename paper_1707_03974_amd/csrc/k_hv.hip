@@ -892,9 +892,10 @@ struct __align__(16) UpHop<double> {
 // turn, so the slab x[:, chunk] that all up hops of the chunk read stays in
 // that XCD's L2, and both halves of every 128-byte line are used there.
 // The tile's hop lists are decoded once into LDS.  IDX64 selects 64-bit
-// element offsets (D >= 2^32).
-template <typename T, typename E, int CW, int ROWS_PER_TILE, bool IDX64, int NB, int VECP = 0>
-__global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const T* __restrict__ x, T* __restrict__ y) {
+// element offsets (D >= 2^32).  BLK threads per work group (FP64 chunks of 128
+// columns take 512, so that one pass covers the tile's eight rows).
+template <typename T, typename E, int CW, int ROWS_PER_TILE, bool IDX64, int NB, int VECP = 0, int BLK = kUpBlock>
+__global__ __launch_bounds__(BLK) void k_hv_up(const UpArgs<T, E> a, const T* __restrict__ x, T* __restrict__ y) {
     if (a.skip && *a.skip) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int maxh = a.max_hops;
@@ -910,8 +911,8 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
     const uint64_t u_begin = (uint64_t)tile * ROWS_PER_TILE;
     const int nrows = (int)((D_up - u_begin) < (uint64_t)ROWS_PER_TILE ? (D_up - u_begin) : (uint64_t)ROWS_PER_TILE);
-    for (int r = threadIdx.x; r < nrows; r += kUpBlock) s_cnt[r] = a.up_count[u_begin + r];
-    for (int k = threadIdx.x; k < nrows * maxh; k += kUpBlock) {
+    for (int r = threadIdx.x; r < nrows; r += BLK) s_cnt[r] = a.up_count[u_begin + r];
+    for (int k = threadIdx.x; k < nrows * maxh; k += BLK) {
         const int r = k / maxh, h = k - r * maxh;
         const uint32_t e = hop_entry(a.up_ell, h, u_begin + r, D_up);   // slots past the count are never read
         const uint32_t ci = e >> a.cshift;
@@ -925,13 +926,13 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
     // each lane owns VEC consecutive columns: CW / VEC lanes per row segment
     // (VECP > 0: 16-byte lanes at any chunk width, several rows per wave)
     constexpr int VEC = VECP > 0 ? VECP : ((CW >= 256 && sizeof(T) == 4) ? 4 : (CW >= 128 ? 2 : 1));
-    static_assert(CW % VEC == 0 && kUpBlock % (CW / VEC) == 0, "lanes per row segment");
+    static_assert(CW % VEC == 0 && BLK % (CW / VEC) == 0, "lanes per row segment");
     constexpr int LANES = CW / VEC;
     const uint32_t lane = threadIdx.x % LANES;
     const uint64_t d = (uint64_t)chunk * CW + (uint64_t)lane * VEC;
     const bool active = d < D_dn;   // lanes past the last column idle (no early exit: a barrier follows)
     const int nv = !active ? 0 : ((d + VEC <= D_dn) ? VEC : (int)(D_dn - d));   // valid columns of this lane
-    constexpr int kSlots = kUpBlock / LANES;
+    constexpr int kSlots = BLK / LANES;
     double dsum = 0.0;
     for (int r = threadIdx.x / LANES; active && r < nrows; r += kSlots) {
         const uint64_t u = u_begin + r;
@@ -1023,7 +1024,7 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up(const UpArgs<T, E> a, const 
                 if (i < nv) dsum += (double)xo[i] * (double)acc[i];
         }
     }
-    if (a.dotp) block_dot_store<kUpBlock>(dsum, a.dotp + blockIdx.x);
+    if (a.dotp) block_dot_store<BLK>(dsum, a.dotp + blockIdx.x);
 }
 
 // Same tile order and decoded hop lists as k_hv_up, but every hop load of a
@@ -1256,6 +1257,12 @@ void launch_sched(const pdz_problem_s* p, int variant, uint64_t grid, size_t lds
 template <typename T>
 constexpr int up_rows() { return 8; }
 
+// Work-group size of the up pass with one column (two in FP64 at 128) per
+// lane: 512 threads for FP64 chunks of 128 columns (measured faster there;
+// FP32, and FP64 at narrower chunks, are faster at 256).
+template <typename T, int CW>
+constexpr int up_block() { return (sizeof(T) == 8 && CW >= 128) ? 512 : kUpBlock; }
+
 // Wide lanes (plan up 4): 16 bytes per lane, so a wave covers 64 * 16 / (CW * sizeof(T)) rows of
 // the chunk at once and a tile holds one row per lane group of the work group.
 template <typename T, int CW>
@@ -1271,13 +1278,15 @@ void launch_up_wide(uint64_t blocks, size_t lds, hipStream_t s, const UpArgs<T, 
 template <typename T, typename E, int CW>
 void launch_up(bool idx64, int nb, uint64_t blocks, size_t lds, hipStream_t s, const UpArgs<T, E>& ua, const T* x,
                T* y) {
-    const dim3 g((unsigned)blocks), b(kUpBlock);
+    const dim3 g((unsigned)blocks), b(kUpBlock), bb(up_block<T, CW>());
     if (idx64)
         hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), true, 8>), g, b, lds, s, ua, x, y);
     else if (nb == 16)
-        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), false, 16>), g, b, lds, s, ua, x, y);
+        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), false, 16, 0, up_block<T, CW>()>), g, bb, lds, s, ua, x,
+                           y);
     else
-        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), false, 8>), g, b, lds, s, ua, x, y);
+        hipLaunchKernelGGL((k_hv_up<T, E, CW, up_rows<T>(), false, 8, 0, up_block<T, CW>()>), g, bb, lds, s, ua, x,
+                           y);
 }
 
 template <typename T, typename E, int CW>
@@ -1595,10 +1604,12 @@ pdz_status run_hv(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipSt
 
 template <typename T, typename E, int CW>
 pdz_status set_up_lds() {
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), false, 8>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
-    PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), false, 16>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
+    PDZ_HIP(hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), false, 8, 0, up_block<T, CW>()>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
+    PDZ_HIP(hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), false, 16, 0, up_block<T, CW>()>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     PDZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hv_up<T, E, CW, up_rows<T>(), true, 8>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds));
     return ok();

@@ -255,3 +255,38 @@ def test_down_families_on_rows_with_and_without_a_gather_schedule(amps, schedule
             err = np.abs(y - ref)
             assert np.all(err <= bound), (amps, name, pl, float(np.max(err / np.maximum(bound, 1e-300))))
         g.set_plan(name, 0, 0, 0, 0)
+
+
+def _ring_nnn(N, nu, nd, U=2.5):
+    """N-site ring with first (t = 1) and second (t' = -0.35) neighbour bonds."""
+    bonds = [(i, (i + 1) % N, 1.0) for i in range(N)] + [(i, (i + 2) % N, -0.35) for i in range(N)]
+    return N, bonds, U, nu, nd
+
+
+@pytest.mark.parametrize("args", [_ring_nnn(17, 1, 8), _ring_nnn(18, 1, 9)], ids=["dn24310", "dn48620"])
+def test_down_rows_longer_than_the_gather_schedule_plane(args):
+    """Down sectors of 24,310 and 48,620 states: past the gather schedule's plane (13,280 states), so
+    the looped wide pass (rows staged in LDS) or the narrow pass (rows too long for LDS) runs; every
+    plan the autotuner offers, on sampled rows, within each row's own rounding bound."""
+    torch = torch_cuda()
+    g = _gpu_problem(args)
+    po = _oracle_problem(*args)
+    assert g.info["D_dn"] in (24310, 48620)
+    x = synth.random_vector(g.D, 23)
+    rng = np.random.default_rng(8)
+    Ddn = g.info["D_dn"]
+    rows = np.unique(np.concatenate([rng.integers(0, g.D, 2500), [0, Ddn - 1, Ddn, g.D - 1]]))
+    ref, asum, nterm = oracle.hv_rows(po, x, rows, with_abs=True)
+    rows_d = torch.from_numpy(rows).cuda()
+    for dt, eps in ((torch.float64, EPS64), (torch.float32, EPS32)):
+        name = "f64" if dt == torch.float64 else "f32"
+        xd = to_dev(x, dt)
+        _, trials = g.tune(dt, reps=1, x=xd, y=torch.empty_like(xd))
+        assert all(not (5 <= t["down"] <= 7) for t in trials), trials   # no schedule for these rows
+        bound = (nterm + 2) * eps * asum + nterm * EPS64 * asum
+        for t in trials:
+            g.set_plan(name, t["down"], t["up_cw"], t["up"], t["map"])
+            y = to_host(g.hv(xd)[rows_d])
+            err = np.abs(y - ref)
+            assert np.all(err <= bound), (args[:1], name, t, float(np.max(err / np.maximum(bound, 1e-300))))
+        g.set_plan(name, 0, 0, 0, 0)

@@ -222,7 +222,8 @@ typedef struct {
                            /*    refined energy is returned (and the status is that run's);   */
                            /*    the workspace then holds that FP64 run's workspace too        */
     int32_t keep_basis;    /* 1: keep every Lanczos vector in the workspace (max_iter + 1 of D   */
-                           /*    elements) so that refine combines them in one pass instead of */
+                           /*    elements, rows padded as described at pdz_lanczos) so that   */
+                           /*    refine combines them in one pass instead of                   */
                            /*    regenerating them with a second run of H.v products           */
 } pdz_lanczos_opts;
 
@@ -313,10 +314,13 @@ pdz_status pdz_lanczos_workspace_size(pdz_problem p, const pdz_lanczos_opts* o, 
  * v0: device array of D elements in `storage` precision, or NULL for the
  *     seeded start vector; it is normalised internally (not modified).
  * ws: caller-owned device workspace of at least pdz_lanczos_workspace_size
- *     bytes, 256-byte aligned.  ritz_out: NULL, or a device array of D doubles
- *     that receives the normalised Ritz vector (of the FP64 restart when one
- *     ran); it forces refine >= 1, so size the workspace with refine >= 1.
- *     Synchronous.
+ *     bytes, 256-byte aligned.  Inside it a real-space problem whose rows hold
+ *     1024 or more down strings keeps its Lanczos vectors with the rows padded
+ *     to a multiple of 32 elements (zeros past D_dn), so that every row starts
+ *     on a 128-byte line; v0 and ritz_out are in the plain basis order.
+ *     ritz_out: NULL, or a device array of D doubles that receives the
+ *     normalised Ritz vector (of the FP64 restart when one ran); it forces
+ *     refine >= 1, so size the workspace with refine >= 1.  Synchronous.
  * Errors: PDZ_EINVAL (bad options, null handle/result, ws too small, zero or
  * non-finite start vector); PDZ_ENOCONV when max_iter is reached (res holds
  * the best estimate). */

@@ -35,6 +35,8 @@ constexpr size_t kDynLds = kLdsBytes - 1024;   // kernels also hold a few static
 template <typename T, typename E>
 struct DownArgs {
     uint64_t D_up, D_dn;
+    uint64_t pitch;   // elements from one row of x, y (and the recurrence vectors) to the next: D_dn, or
+                      // more with zeros past column D_dn that the pass keeps zero
     T U;
     const uint32_t* up_states;
     const uint32_t* dn_states;
@@ -72,6 +74,7 @@ struct DownArgs {
 template <typename T, typename E>
 struct UpArgs {
     uint64_t D_up, D_dn;
+    uint64_t pitch;   // row pitch of x and y, as in DownArgs
     const uint8_t* up_count;
     const E* up_ell;
     uint32_t tmask;
@@ -232,6 +235,8 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
     load_coef(coef, a.coef, a.ncoef);
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
     const uint32_t Dn = (uint32_t)D_dn;
+    const uint64_t pitch = a.pitch;   // a group's rows are R * pitch consecutive elements
+    const uint32_t Pn = (uint32_t)pitch;
     const uint64_t ngroups = (D_up + R - 1) / R;
     // raw buffer over the 16-bit table (dword 3: the gfx9 untyped 32-bit format)
     const __amdgpu_buffer_rsrc_t ell_rs =
@@ -269,11 +274,11 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
     };
     auto fetch = [&](uint64_t g) {
         const uint64_t u0 = g * R;
-        const uint64_t nelem = ((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * D_dn;
+        const uint64_t nelem = ((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * pitch;
         if constexpr (FUSE) {
             // raw operands only: the recurrence is formed when the group is staged,
             // so these loads stay in flight while the current group computes
-            const uint64_t off = u0 * D_dn;
+            const uint64_t off = u0 * pitch;
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const uint64_t k = threadIdx.x + (uint64_t)i * kWideBlock;
@@ -285,7 +290,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
                 }
             }
         } else {
-            const T* base = x + u0 * D_dn;
+            const T* base = x + u0 * pitch;
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const uint64_t k = threadIdx.x + (uint64_t)i * kWideBlock;
@@ -298,34 +303,36 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
         const uint64_t u0 = g * R;
         const int nr = (int)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
         __syncthreads();
-        const uint64_t nelem_g = (uint64_t)nr * D_dn;
+        const uint64_t nelem_g = (uint64_t)nr * pitch;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const uint32_t k = threadIdx.x + (uint32_t)i * kWideBlock;
-            if (k < (uint32_t)R * Dn) {
-                const uint32_t r = row_of<R>(k, Dn);
+            if (k < (uint32_t)R * Pn) {
+                const uint32_t r = row_of<R>(k, Pn);
                 T v = pre[i];
                 if constexpr (FUSE) {
                     v = (T)0;
                     if (k < nelem_g) {
-                        const uint64_t e = u0 * D_dn + k;
+                        const uint64_t e = u0 * pitch + k;
                         v = lanczos_recurrence<T>(pre[i], pz[i], p1[i], p2[i], fa, fb, fc);
                         a.fq2[e] = v;
                         if (fkeep) fkeep[e] = v;
                         nsum += (double)v * (double)v;
                     }
                 }
-                rows[(size_t)(k - r * Dn) * R + r] = v;
+                const uint32_t dc = k - r * Pn;   // column (past D_dn: padding, not staged)
+                if (dc < Dn) rows[(size_t)dc * R + r] = v;
             }
         }
         {   // elements beyond the register prefetch, loaded now
-            const uint64_t nelem = (uint64_t)nr * D_dn;
-            const T* base = x + u0 * D_dn;
-            for (uint32_t k = threadIdx.x + (uint32_t)PER * kWideBlock; k < (uint32_t)R * Dn; k += kWideBlock) {
-                const uint32_t r = row_of<R>(k, Dn);
+            const uint64_t nelem = (uint64_t)nr * pitch;
+            const T* base = x + u0 * pitch;
+            for (uint32_t k = threadIdx.x + (uint32_t)PER * kWideBlock; k < (uint32_t)R * Pn; k += kWideBlock) {
+                const uint32_t r = row_of<R>(k, Pn);
                 T v = (T)0;
-                if (k < nelem) v = FUSE ? stage_elem(u0 * D_dn, k) : base[k];
-                rows[(size_t)(k - r * Dn) * R + r] = v;
+                if (k < nelem) v = FUSE ? stage_elem(u0 * pitch, k) : base[k];
+                const uint32_t dc = k - r * Pn;
+                if (dc < Dn) rows[(size_t)dc * R + r] = v;
             }
         }
         __syncthreads();
@@ -360,7 +367,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (r < nr) {
-                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * pitch + d);
                         dsum += (double)rows[(size_t)d * R + r] * (double)acc[r];
                     }
                 continue;
@@ -402,7 +409,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (r < nr) {
-                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * pitch + d);
                         dsum += (double)rows[(size_t)d * R + r] * (double)acc[r];
                     }
                 continue;
@@ -435,7 +442,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_wide(const DownArgs<T, E
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 if (r < nr) {
-                    __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                    __builtin_nontemporal_store(acc[r], y + (u0 + r) * pitch + d);
                     dsum += (double)rows[(size_t)d * R + r] * (double)acc[r];
                 }
         }
@@ -517,6 +524,8 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     const unsigned char* lbase = reinterpret_cast<const unsigned char*>(planes);
     const uint64_t D_up = a.D_up, D_dn = a.D_dn;
     const uint32_t Dn = (uint32_t)D_dn;
+    const uint64_t pitch = a.pitch;   // a group's rows are R * pitch consecutive elements (columns
+    const uint32_t Pn = (uint32_t)pitch;   // past Dn: zeros, staged too, never gathered)
     const uint64_t ngroups = (D_up + R - 1) / R;
     const uint32_t nwaves = (Dn + 63) / 64;
     const int lane = threadIdx.x & 63;
@@ -534,10 +543,10 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
         fc = k > 0 ? a.fbeta[k] * a.fsc[k - 1] : 0.0;
         if (a.fkeep && k + 1 < a.fkeep_cap) fkeep = a.fkeep + (uint64_t)(k + 1) * a.fkeep_ld;
     }
-    // element k of a group lives in row k / Dn at column k mod Dn
+    // element k of a group lives in row k / pitch at column k mod pitch
     auto put = [&](uint32_t k, T v) {
-        const uint32_t r = R == 1 ? 0u : (k >= 2 * Dn ? 2u : (k >= Dn ? 1u : 0u));
-        const uint32_t d = k - r * Dn;
+        const uint32_t r = R == 1 ? 0u : (k >= 2 * Pn ? 2u : (k >= Pn ? 1u : 0u));
+        const uint32_t d = k - r * Pn;
         if constexpr (W == 1) {
             planes[r * P + d] = __float_as_uint((float)v);
         } else {
@@ -575,8 +584,8 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     T pz[FUSE ? PQ : 1][4], p1[FUSE ? PQ : 1][4], p2[FUSE ? PQ : 1][4];
     auto fetch = [&](uint64_t g) {
         const uint64_t u0 = g * R;
-        const uint32_t nelem = (uint32_t)(((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * D_dn);
-        const uint64_t off = u0 * D_dn;
+        const uint32_t nelem = (uint32_t)(((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * pitch);
+        const uint64_t off = u0 * pitch;
 #pragma unroll
         for (int i = 0; i < PQ; ++i) {
             const uint32_t k0 = 4u * (threadIdx.x + (uint32_t)i * kWideBlock);
@@ -635,8 +644,8 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const uint64_t u0 = g * R;
         const int nr = (int)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
-        const uint32_t nelem = (uint32_t)nr * Dn;
-        const uint32_t nput = (uint32_t)R * Dn;   // rows past the last are staged as zeros
+        const uint32_t nelem = (uint32_t)nr * Pn;
+        const uint32_t nput = (uint32_t)R * Pn;   // rows past the last are staged as zeros
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < PQ; ++i) {
@@ -644,7 +653,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
             if (k0 < nput) {
                 T v[4];
                 if constexpr (FUSE) {
-                    if (k0 < nelem) form4(u0 * D_dn + k0, k0, nelem, pre[i], pz[i], p1[i], p2[i], v);
+                    if (k0 < nelem) form4(u0 * pitch + k0, k0, nelem, pre[i], pz[i], p1[i], p2[i], v);
                     put4(k0, nelem, nput, v);
                 } else {
                     put4(k0, nelem, nput, pre[i]);
@@ -659,7 +668,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
             for (int j = 0; j < NQ; ++j) {
                 const uint32_t k0 = 4u * (qb + (uint32_t)j * kWideBlock);
                 if (k0 < nelem) {
-                    const uint64_t e0 = u0 * D_dn + k0;
+                    const uint64_t e0 = u0 * pitch + k0;
                     if constexpr (FUSE) {
                         load4(y, e0, k0, nelem, v0[j], false);
                         load4(a.fz, e0, k0, nelem, v1[j], false);
@@ -676,7 +685,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
                 if (k0 < nput) {
                     if constexpr (FUSE) {
                         T v[4];
-                        if (k0 < nelem) form4(u0 * D_dn + k0, k0, nelem, v0[j], v1[j], v2[j], v3[j], v);
+                        if (k0 < nelem) form4(u0 * pitch + k0, k0, nelem, v0[j], v1[j], v2[j], v3[j], v);
                         put4(k0, nelem, nput, v);
                     } else {
                         put4(k0, nelem, nput, v0[j]);
@@ -735,7 +744,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
             if (a.add_y) {   // the up part of these elements, loaded with the schedule words
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    acc[r] = (live && r < nr) ? __builtin_nontemporal_load(y + (u0 + r) * D_dn + d) : (T)0;
+                    acc[r] = (live && r < nr) ? __builtin_nontemporal_load(y + (u0 + r) * pitch + d) : (T)0;
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -789,7 +798,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (r < nr) {
-                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * D_dn + d);
+                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * pitch + d);
                         dsum += (double)get(r, d * 4u) * (double)acc[r];
                     }
             }
@@ -819,15 +828,18 @@ __global__ __launch_bounds__(kNarrowBlock) void k_hv_down_narrow(const DownArgs<
         const uint64_t u0 = g * (uint64_t)R;
         const int nr = (int)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
         const uint64_t nelem = (uint64_t)nr * D_dn;
-        const T* xg = x + u0 * D_dn;
+        const T* xg = x + u0 * a.pitch;   // row r of the group at xg + r * pitch
         __syncthreads();
         if (STAGE)
-            for (uint64_t k = threadIdx.x; k < nelem; k += blockDim.x) rows[k] = xg[k];
+            for (uint64_t k = threadIdx.x; k < nelem; k += blockDim.x) {
+                const uint64_t r = k / D_dn;
+                rows[k] = xg[r * a.pitch + (k - r * D_dn)];
+            }
         __syncthreads();
         for (uint64_t k = threadIdx.x; k < nelem; k += blockDim.x) {
             const uint32_t r = (uint32_t)(k / D_dn);
             const uint32_t d = (uint32_t)(k - (uint64_t)r * D_dn);
-            const T* xrow = STAGE ? rows + (uint64_t)r * D_dn : xg + (uint64_t)r * D_dn;
+            const T* xrow = STAGE ? rows + (uint64_t)r * D_dn : xg + (uint64_t)r * a.pitch;
             const uint32_t pu = a.up_states[u0 + r];
             const uint32_t pd = a.dn_states[d];
             T acc = a.U * (T)__builtin_popcount(pu & pd) * xrow[d];
@@ -836,7 +848,7 @@ __global__ __launch_bounds__(kNarrowBlock) void k_hv_down_narrow(const DownArgs<
                 const uint32_t e = hop_entry(a.dn_ell, h, d, D_dn);
                 acc += coef[e >> a.cshift] * xrow[e & a.tmask];
             }
-            y[(u0 + r) * D_dn + d] = acc;
+            y[(u0 + r) * a.pitch + d] = acc;
             dsum += (double)xrow[d] * (double)acc;
         }
     }
@@ -918,9 +930,9 @@ __global__ __launch_bounds__(BLK) void k_hv_up(const UpArgs<T, E> a, const T* __
         const uint32_t ci = e >> a.cshift;
         s_hop[k].c = a.coef[ci < (uint32_t)a.ncoef ? ci : 0];
         if (IDX64)
-            s_off64[k] = (uint64_t)(e & a.tmask) * D_dn;
+            s_off64[k] = (uint64_t)(e & a.tmask) * a.pitch;
         else
-            s_hop[k].off = (e & a.tmask) * (uint32_t)D_dn;
+            s_hop[k].off = (e & a.tmask) * (uint32_t)a.pitch;
     }
     __syncthreads();
     // each lane owns VEC consecutive columns: CW / VEC lanes per row segment
@@ -939,11 +951,11 @@ __global__ __launch_bounds__(BLK) void k_hv_up(const UpArgs<T, E> a, const T* __
         const int cnt = s_cnt[r];
         const UpHop<T>* hp = s_hop + r * maxh;
         const uint64_t* o64 = s_off64 + r * maxh;
-        T* yr = y + u * D_dn + d;
+        T* yr = y + u * a.pitch + d;
         // x at this row's own elements, for the x . out partial: loaded now, used after the hops
         T xo[VEC];
         if (a.dotp) {
-            const T* xr = x + u * D_dn + d;
+            const T* xr = x + u * a.pitch + d;
             if (nv == VEC) {
                 vec_load<T, VEC>(xr, xo);
             } else {
@@ -1053,7 +1065,7 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up_pre(const UpArgs<T, E> a, co
         const uint32_t e = hop_entry(a.up_ell, h, u_begin + r, D_up);
         const uint32_t ci = e >> a.cshift;
         s_hop[k].c = a.coef[ci < (uint32_t)a.ncoef ? ci : 0];
-        s_hop[k].off = (e & a.tmask) * (uint32_t)D_dn;
+        s_hop[k].off = (e & a.tmask) * (uint32_t)a.pitch;
     }
     __syncthreads();
     const uint32_t col = threadIdx.x % CW;
@@ -1068,12 +1080,12 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up_pre(const UpArgs<T, E> a, co
         T v[MAXH];
 #pragma unroll
         for (int h = 0; h < MAXH; ++h) v[h] = (h < cnt) ? x[(uint32_t)(hp[h].off + (uint32_t)d)] : (T)0;
-        T acc = a.add_y ? __builtin_nontemporal_load(y + u * D_dn + d) : (T)0;
+        T acc = a.add_y ? __builtin_nontemporal_load(y + u * a.pitch + d) : (T)0;
 #pragma unroll
         for (int h = 0; h < MAXH; ++h)
             if (h < cnt) acc += hp[h].c * v[h];
-        __builtin_nontemporal_store(acc, y + u * D_dn + d);
-        if (a.dotp) dsum += (double)x[u * D_dn + d] * (double)acc;
+        __builtin_nontemporal_store(acc, y + u * a.pitch + d);
+        if (a.dotp) dsum += (double)x[u * a.pitch + d] * (double)acc;
     }
     if (a.dotp) block_dot_store<kUpBlock>(dsum, a.dotp + blockIdx.x);
 }
@@ -1411,12 +1423,13 @@ uint64_t up_blocks(const pdz_problem_s* p, size_t es, const HvPlan& plan) {
 // Up pass of the table path: yout = (add_y ? yout : 0) + the up hops of x.
 template <typename T, typename E>
 pdz_status up_pass(const pdz_problem_s* p, const T* coef, const T* x, T* yout, hipStream_t s, const int* skip,
-                   bool compact, const HvPlan& plan, int add_y, double* dotp) {
+                   bool compact, const HvPlan& plan, int add_y, double* dotp, uint64_t pitch) {
     const uint64_t D_up = p->up.D, D_dn = p->dn.D;
     const int ncoef = (int)p->coef_host.size();
     UpArgs<T, E> ua;
     ua.D_up = D_up;
     ua.D_dn = D_dn;
+    ua.pitch = pitch;
     ua.up_count = p->up.count;
     fill_table_view<T, E>(p->up, compact, &ua.up_ell, &ua.tmask, &ua.cshift);
     ua.coef = coef;
@@ -1426,7 +1439,7 @@ pdz_status up_pass(const pdz_problem_s* p, const T* coef, const T* x, T* yout, h
     ua.dotp = dotp;
     const int CW = plan.up_cw;
     const int ROWS = up_tile_rows(sizeof(T), plan);
-    const bool idx64 = p->D > 0xFFFFFFFFull;
+    const bool idx64 = D_up * pitch > 0xFFFFFFFFull;
     ua.row_tiles = (uint32_t)((D_up + ROWS - 1) / ROWS);
     ua.max_hops = p->up.max_hops;
     ua.n_chunks = (uint32_t)((D_dn + CW - 1) / CW);
@@ -1484,13 +1497,14 @@ pdz_status up_pass(const pdz_problem_s* p, const T* coef, const T* x, T* yout, h
 
 template <typename T, typename E>
 pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coef, const T* x, T* y, hipStream_t s,
-                      const int* skip, bool compact, unsigned passes, const HvSplit* split) {
+                      const int* skip, bool compact, unsigned passes, const HvSplit* split, uint64_t pitch) {
     const uint64_t D_up = p->up.D, D_dn = p->dn.D;
     const int ncoef = (int)p->coef_host.size();
     // ---- down pass
     DownArgs<T, E> da;
     da.D_up = D_up;
     da.D_dn = D_dn;
+    da.pitch = pitch;
     da.U = (T)p->U;
     da.up_states = p->up.states;
     da.dn_states = p->dn.states;
@@ -1517,6 +1531,8 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     const HvPlan plan = hv_resolve(p, sizeof(T) == 8 ? PDZ_F64 : PDZ_F32);
     const DownGeom gm = down_geom(p, sizeof(T), plan, (unsigned)ctx->cu_count);
     da.rows = gm.rows;
+    if (gm.wide && sched_plan(plan.down) && pitch + 32 > (uint64_t)kSchedPlane)
+        return fail(PDZ_EINVAL, "row pitch longer than the scheduled down pass's plane");
     if (fused) {
         if (!(passes & kPassDown) || (passes & kPassUp) || !gm.wide ||
             !(plan.down == 2 || plan.down == 3 || plan.down == 4 || sched_plan(plan.down)) || !split->dotp_dn ||
@@ -1534,7 +1550,7 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
         // (so no pass re-reads y in its gathers); element sum: up hops, then
         // the diagonal, then the down hops
         if (passes & kPassUp) {
-            const pdz_status st = up_pass<T, E>(p, coef, x, y, s, skip, compact, plan, 0, nullptr);
+            const pdz_status st = up_pass<T, E>(p, coef, x, y, s, skip, compact, plan, 0, nullptr, pitch);
             if (st != PDZ_OK) return st;
         }
         if (passes & kPassDown) {
@@ -1560,7 +1576,7 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     PDZ_HIP(hipGetLastError());
     if (p->up.max_hops == 0 || !(passes & kPassUp)) {
         if (split && split->z) {   // no up hops: the up term is zero
-            hipLaunchKernelGGL(k_zero_fill<T>, dim3(1024), dim3(256), 0, s, static_cast<T*>(split->z), p->D);
+            hipLaunchKernelGGL(k_zero_fill<T>, dim3(1024), dim3(256), 0, s, static_cast<T*>(split->z), D_up * pitch);
             if (split->dotp_up) hipLaunchKernelGGL(k_zero_fill<double>, dim3(1), dim3(64), 0, s, split->dotp_up,
                                                    (uint64_t)1);
             PDZ_HIP(hipGetLastError());
@@ -1569,21 +1585,25 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     }
     // split: the up term goes to its own buffer (no re-read of y); else it is added into y
     if (split && split->z)
-        return up_pass<T, E>(p, coef, x, static_cast<T*>(split->z), s, skip, compact, plan, 0, split->dotp_up);
-    return up_pass<T, E>(p, coef, x, y, s, skip, compact, plan, 1, split ? split->dotp_up : nullptr);
+        return up_pass<T, E>(p, coef, x, static_cast<T*>(split->z), s, skip, compact, plan, 0, split->dotp_up,
+                             pitch);
+    return up_pass<T, E>(p, coef, x, y, s, skip, compact, plan, 1, split ? split->dotp_up : nullptr, pitch);
 }
 
 template <typename T>
 pdz_status run_hv(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipStream_t s, const int* skip,
-                  unsigned passes, const HvSplit* split) {
+                  unsigned passes, const HvSplit* split, uint64_t pitch) {
     DeviceCtx* ctx = nullptr;
     pdz_status st = device_ctx(&ctx);
     if (st != PDZ_OK) return st;
+    if (pitch == 0) pitch = p->dn.D;
+    if (pitch < p->dn.D) return fail(PDZ_EINVAL, "row pitch shorter than a row");
     if (p->hv_path == 0) {
         const bool compact = p->up.tbits16 > 0 && p->dn.tbits16 > 0;
-        if (compact) return run_tables<T, uint16_t>(p, ctx, coef, x, y, s, skip, true, passes, split);
-        return run_tables<T, uint32_t>(p, ctx, coef, x, y, s, skip, false, passes, split);
+        if (compact) return run_tables<T, uint16_t>(p, ctx, coef, x, y, s, skip, true, passes, split, pitch);
+        return run_tables<T, uint32_t>(p, ctx, coef, x, y, s, skip, false, passes, split, pitch);
     }
+    if (pitch != p->dn.D) return fail(PDZ_EINVAL, "the on-the-fly H.v takes unpadded rows");
     FlyArgs f;
     f.N = p->N;
     f.n_up = p->n_up;
@@ -1726,13 +1746,13 @@ bool hv_plan_valid(const pdz_problem_s* p, pdz_dtype dt, const HvPlan& plan) {
 }
 
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
-                     const int* skip, unsigned passes, const HvSplit* split) {
+                     const int* skip, unsigned passes, const HvSplit* split, uint64_t pitch) {
     if (split && p->hv_path != 0) return fail(PDZ_EINVAL, "split H.v needs the table path");
     if (dt == PDZ_F64)
         return run_hv<double>(p, p->d_coef64, static_cast<const double*>(x), static_cast<double*>(y), s, skip,
-                              passes, split);
+                              passes, split, pitch);
     return run_hv<float>(p, p->d_coef32, static_cast<const float*>(x), static_cast<float*>(y), s, skip, passes,
-                         split);
+                         split, pitch);
 }
 
 bool hv_fused_available(const pdz_problem_s* p, pdz_dtype dt) {

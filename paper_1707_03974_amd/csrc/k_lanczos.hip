@@ -53,10 +53,38 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return r;
 }
 
+// Seeded start vector: element r of the basis (row r / dn, column r mod dn)
+// draws SplitMix64 output r; the vector is stored with row pitch `pitch`
+// (n = rows * pitch elements, zeros past column dn).
 template <typename T>
-__global__ __launch_bounds__(kRedBlock) void k_random_start(T* v, uint64_t D, uint64_t seed) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < D; i += (uint64_t)gridDim.x * blockDim.x)
-        v[i] = (T)splitmix_uniform(seed, i);
+__global__ __launch_bounds__(kRedBlock) void k_random_start(T* v, uint64_t n, uint64_t dn, uint64_t pitch,
+                                                            uint64_t seed) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t u = i / pitch, d = i - u * pitch;
+        v[i] = d < dn ? (T)splitmix_uniform(seed, u * dn + d) : (T)0;
+    }
+}
+
+// dst (row pitch dp) <- src (row pitch sp), rows of dn elements; n = rows *
+// dp destination elements, zeros past column dn.
+template <typename TS, typename TD>
+__global__ __launch_bounds__(kRedBlock) void k_repitch(const TS* __restrict__ s, uint64_t sp, TD* __restrict__ d,
+                                                       uint64_t dp, uint64_t dn, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t u = i / dp, c = i - u * dp;
+        d[i] = c < dn ? (TD)s[u * sp + c] : (TD)0;
+    }
+}
+
+// Columns dn..pitch-1 of every row of `nslots` vectors `stride` elements apart set to zero.
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_zero_pad(T* v, uint64_t stride, int nslots, uint64_t rows,
+                                                        uint64_t dn, uint64_t pitch) {
+    const uint64_t w = pitch - dn, per = rows * w, n = per * (uint64_t)nslots;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t sl = i / per, j = i - sl * per, u = j / w;
+        v[sl * stride + u * pitch + dn + (j - u * w)] = (T)0;
+    }
 }
 
 template <typename TS, typename TD>
@@ -464,6 +492,21 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiag(const double* alpha, cons
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Row pitch of the Lanczos vectors of a real-space table problem: rows of
+// 1024 or more elements are padded to a multiple of 32 elements (128 bytes in
+// FP32), so that every row starts on a cache line and the up pass's 16-byte
+// loads are aligned; 0 (no padding) for shorter rows and the other H.v paths.
+uint64_t lanczos_pitch(const pdz_problem_s* p) {
+    if (p->hv_path != 0 || p->ks || p->par || p->dn.D < 1024) return 0;
+    const uint64_t P = (p->dn.D + 31) / 32 * 32;
+    return P == p->dn.D ? 0 : P;
+}
+// Elements of one Lanczos vector (D, or D_up * pitch).
+uint64_t lanczos_len(const pdz_problem_s* p) {
+    const uint64_t P = lanczos_pitch(p);
+    return P ? p->up.D * P : p->D;
+}
+
 struct Layout {
     size_t vec = 0;
     size_t buf[3] = {0, 0, 0};
@@ -544,7 +587,7 @@ pdz_lanczos_opts restart_opts(const pdz_lanczos_opts* o) {
 }
 
 Layout make_layout(const pdz_problem_s* p, const pdz_lanczos_opts* o) {
-    const uint64_t D = p->D;
+    const uint64_t D = lanczos_len(p);
     Layout L;
     const size_t es = o->storage == PDZ_F64 ? 8 : 4;
     L.vec = align256((size_t)D * es);
@@ -622,7 +665,9 @@ struct Run {
     char* ws;
     hipStream_t s;
     uint32_t* err;
-    uint64_t D;
+    uint64_t D;              // elements of one vector (with the row padding)
+    uint64_t pitch = 0;      // row pitch of the vectors, 0: unpadded (D elements, the basis order)
+    bool v0_pitched = false; // v0 is already in the padded layout (the FP64 restart from y)
     T* buf(int i) const { return reinterpret_cast<T*>(ws + L.buf[i]); }
     T* basis(int j) const { return reinterpret_cast<T*>(ws + L.basis + (size_t)j * L.vec); }
     T* kept(int j) const { return L.nkept ? reinterpret_cast<T*>(ws + L.kept + (size_t)j * L.vec) : nullptr; }
@@ -660,10 +705,29 @@ struct Run {
         const unsigned g = grid_elems(D);
         hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, s, err, kErrNonFinite);
         hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, ctl(), beta());
-        if (v0)
+        const uint64_t dn = p->dn.D, rp = pitch ? pitch : dn;
+        if (pitch) {
+            // the H.v passes write columns below D_dn only: the padding of every vector they
+            // write starts at zero and stays zero
+            if (o->reorth)
+                hipLaunchKernelGGL(k_zero_pad<T>, dim3(g), dim3(kRedBlock), 0, s, basis(0), ld(), L.nvec_basis,
+                                   p->up.D, dn, pitch);
+            hipLaunchKernelGGL(k_zero_pad<T>, dim3(g), dim3(kRedBlock), 0, s, buf(0), ld(), o->reorth ? 1 : 3,
+                               p->up.D, dn, pitch);
+            if (L.z)
+                hipLaunchKernelGGL(k_zero_pad<T>, dim3(g), dim3(kRedBlock), 0, s, zbuf(), ld(), 1, p->up.D, dn,
+                                   pitch);
+            if (o->refine)
+                hipLaunchKernelGGL(k_zero_pad<double>, dim3(g), dim3(kRedBlock), 0, s, hy(), (uint64_t)0, 1, p->up.D,
+                                   dn, pitch);
+        }
+        if (v0 && (v0_pitched || !pitch))
             hipLaunchKernelGGL((k_copy<T, T>), dim3(g), dim3(kRedBlock), 0, s, static_cast<const T*>(v0), dst, D);
+        else if (v0)
+            hipLaunchKernelGGL((k_repitch<T, T>), dim3(g), dim3(kRedBlock), 0, s, static_cast<const T*>(v0), dn, dst,
+                               pitch, dn, D);
         else
-            hipLaunchKernelGGL(k_random_start<T>, dim3(g), dim3(kRedBlock), 0, s, dst, D, (uint64_t)o->seed);
+            hipLaunchKernelGGL(k_random_start<T>, dim3(g), dim3(kRedBlock), 0, s, dst, D, dn, rp, (uint64_t)o->seed);
         hipLaunchKernelGGL(k_fill_zero<T>, dim3(g), dim3(kRedBlock), 0, s, zero_dst, D);
         hipLaunchKernelGGL((k_dot_partial<T, T>), dim3(kRedGrid), dim3(kRedBlock), 0, s, dst, dst, D, partial(),
                            (const int*)nullptr);
@@ -709,13 +773,13 @@ struct Run {
         if (c.ndn > 0) {
             HvSplit sd;   // down pass (no z: it would be cleared after a down-only launch)
             sd.dotp_dn = partial();
-            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown, &sd);
+            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown, &sd, pitch);
             if (st != PDZ_OK) return st;
             mark(1);
             HvSplit su;
             su.z = zbuf();
             su.dotp_up = partial() + c.ndn;
-            st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassUp, &su);
+            st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassUp, &su, pitch);
             if (st != PDZ_OK) return st;
             mark(2);
             hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn,
@@ -725,7 +789,7 @@ struct Run {
         } else if (c.nwhole > 0) {   // the H.v writes partial sums of q . H q
             HvSplit sw;
             sw.dotp_up = partial();
-            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sw);
+            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sw, pitch);
             if (st != PDZ_OK) return st;
             mark(1);
             mark(2);
@@ -734,7 +798,7 @@ struct Run {
             hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(kRedBlock), 0, s, partial(), 0, partial2(),
                                (int)kRedGrid, alpha(), sc(), kptr(), done(), err);
         } else {
-            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done());
+            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, nullptr, pitch);
             if (st != PDZ_OK) return st;
             mark(1);
             mark(2);
@@ -761,7 +825,7 @@ struct Run {
         if (p->par) {   // the whole H q_0 into w, alpha_0 from its x . y partials
             HvSplit sw;
             sw.dotp_up = partial();
-            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sw);
+            pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sw, pitch);
             if (st != PDZ_OK) return st;
             hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial(), (uint64_t)c.nwhole,
                                partial2(), done());
@@ -773,7 +837,7 @@ struct Run {
         sp.z = zbuf();
         sp.dotp_dn = partial();
         sp.dotp_up = partial() + c.ndn;
-        pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sp);
+        pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, done(), kPassDown | kPassUp, &sp, pitch);
         if (st != PDZ_OK) return st;
         hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn, (uint64_t)c.nup,
                            partial2(), done());
@@ -804,7 +868,7 @@ struct Run {
         f.fsc = sc();
         f.fkidx = kptr();
         f.fnorm = partial3();
-        pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassDown, &f);
+        pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassDown, &f, pitch);
         if (st != PDZ_OK) return st;
         mark(1);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial3(), c.ndn, beta(), kptr(), 1,
@@ -816,7 +880,7 @@ struct Run {
         HvSplit u;
         u.z = zbuf();
         u.dotp_up = partial() + c.ndn;
-        st = launch_hv_any(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassUp, &u);
+        st = launch_hv_any(p, (pdz_dtype)o->storage, q2, w, s, done(), kPassUp, &u, pitch);
         if (st != PDZ_OK) return st;
         mark(3);
         hipLaunchKernelGGL(k_sum_strided, dim3(kRedGrid), dim3(kRedBlock), 0, s, partial() + c.ndn, (uint64_t)c.nup,
@@ -932,7 +996,7 @@ struct Run {
     // full re-orthogonalisation, v_{k-1} and v_k for local.
     pdz_status step(T* v, T* vp, T* w, int rfirst, int rn) {
         const unsigned g = grid_elems(D);
-        pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, v, w, s, done());
+        pdz_status st = launch_hv_any(p, (pdz_dtype)o->storage, v, w, s, done(), kPassDown | kPassUp, nullptr, pitch);
         if (st != PDZ_OK) return st;
         hipLaunchKernelGGL((k_dot_partial<T, T>), dim3(kRedGrid), dim3(kRedBlock), 0, s, v, w, D, partial(), done());
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlock), 0, s, partial(), kRedGrid, alpha(), kptr(), 0,
@@ -1104,7 +1168,7 @@ struct Run {
                     HvSplit sp;
                     sp.z = zbuf();
                     st = launch_hv_any(p, (pdz_dtype)o->storage, q, w, s, nullptr, kPassDown | kPassUp,
-                                   counts.ndn > 0 ? &sp : nullptr);
+                                       counts.ndn > 0 ? &sp : nullptr, pitch);
                     if (st != PDZ_OK) return st;
                     launch_update_scaled<T>(w, counts.ndn > 0 ? (const T*)zbuf() : (const T*)nullptr, q, qp, D,
                                             alpha(), beta(), sc(), kptr(), partial(), (const int*)nullptr, s);
@@ -1119,7 +1183,7 @@ struct Run {
                            (int)kStoreSqrt, (const int*)nullptr, err);
         hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kRedBlock), 0, s, y(), D, scr, (const int*)nullptr, 0,
                            (const int*)nullptr);
-        pdz_status st = launch_hv_any(p, PDZ_F64, y(), hy(), s, nullptr);
+        pdz_status st = launch_hv_any(p, PDZ_F64, y(), hy(), s, nullptr, kPassDown | kPassUp, nullptr, pitch);
         if (st != PDZ_OK) return st;
         hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(kRedGrid), dim3(kRedBlock), 0, s, y(), hy(), D,
                            partial(), (const int*)nullptr);
@@ -1169,7 +1233,14 @@ struct Run {
                 if (st != PDZ_OK && st != PDZ_ENOCONV) return st;
                 if (restarted) return st;
             }
-            if (ritz_out) PDZ_HIP(hipMemcpyAsync(ritz_out, y(), (size_t)D * 8, hipMemcpyDeviceToDevice, s));
+            if (ritz_out && pitch) {   // back to the basis order (unpadded rows)
+                hipLaunchKernelGGL((k_repitch<double, double>), dim3(grid_elems(p->D)), dim3(kRedBlock), 0, s, y(),
+                                   pitch, ritz_out, p->dn.D, p->dn.D, p->D);
+                st = launch_check();
+                if (st != PDZ_OK) return st;
+            } else if (ritz_out) {
+                PDZ_HIP(hipMemcpyAsync(ritz_out, y(), (size_t)D * 8, hipMemcpyDeviceToDevice, s));
+            }
         }
         PDZ_HIP(hipStreamSynchronize(s));
         return h.converged ? ok() : fail(PDZ_ENOCONV, "max_iter reached before the tolerance");
@@ -1191,6 +1262,8 @@ struct Run {
         const pdz_lanczos_opts ro = restart_opts(o);
         const Layout L2 = make_layout(p, &ro);
         Run<double> r2{p, &ro, L2, ws + L.restart, s, err, D};
+        r2.pitch = pitch;
+        r2.v0_pitched = true;   // y is in the padded layout
         pdz_lanczos_result rr;
         std::memset(&rr, 0, sizeof(rr));
         pdz_status st = r2.run(y(), ritz_out, &rr);
@@ -1321,10 +1394,12 @@ pdz_status pdz_lanczos_kernel_times(pdz_problem p, const pdz_lanczos_opts* o, vo
     hipStream_t s = (hipStream_t)stream;
     int f = 0;
     if (oo.storage == PDZ_F64) {
-        Run<double> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, p->D};
+        Run<double> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, lanczos_len(p)};
+        r.pitch = lanczos_pitch(p);
         st = r.timed_steps(steps, ms, &f);
     } else {
-        Run<float> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, p->D};
+        Run<float> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, lanczos_len(p)};
+        r.pitch = lanczos_pitch(p);
         st = r.timed_steps(steps, ms, &f);
     }
     *fused = f;
@@ -1360,10 +1435,12 @@ pdz_status pdz_lanczos(pdz_problem p, const pdz_lanczos_opts* o, const void* v0,
         s = own;
     }
     if (oo.storage == PDZ_F64) {
-        Run<double> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, p->D};
+        Run<double> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, lanczos_len(p)};
+        r.pitch = lanczos_pitch(p);
         st = r.run(v0, ritz_out, res);
     } else {
-        Run<float> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, p->D};
+        Run<float> r{p, &oo, L, static_cast<char*>(ws), s, ctx->err, lanczos_len(p)};
+        r.pitch = lanczos_pitch(p);
         st = r.run(v0, ritz_out, res);
     }
     if (own) {

@@ -75,14 +75,15 @@ uint64_t binom(int n, int k) {
 }
 
 pdz_status launch_hv_any(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
-                         const int* skip, unsigned passes, const HvSplit* split) {
+                         const int* skip, unsigned passes, const HvSplit* split, uint64_t pitch) {
+    if ((p->ks || p->par) && pitch != 0) return fail(PDZ_EINVAL, "a symmetry-sector H.v takes unpadded vectors");
     if (p->ks) {
         if (split || passes != (kPassDown | kPassUp))
             return fail(PDZ_EINVAL, "a momentum-space H.v has no separate passes");
         return launch_hvk(p, dt, x, y, s, skip);
     }
     if (p->par) return launch_hvp_split(p, dt, x, y, s, skip, passes, split);
-    return launch_hv(p, dt, x, y, s, skip, passes, split);
+    return launch_hv(p, dt, x, y, s, skip, passes, split, pitch);
 }
 
 }  // namespace pdz

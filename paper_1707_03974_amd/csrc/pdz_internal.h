@@ -221,15 +221,18 @@ pdz_status launch_hvp_split(const pdz_problem_s* p, pdz_dtype dt, const void* x,
 // |q_{k+1}|^2 partials the fused parity down pass writes to fnorm; 0 when
 // the problem has no fused form
 int parity_fused_norms(const pdz_problem_s* p, pdz_dtype dt);
-// H.v of a real-space problem (k_hv.hip)
+// H.v of a real-space problem (k_hv.hip).  pitch: elements from one row of
+// x, y (and of the split and recurrence vectors) to the next; 0 means D_dn.
+// A longer pitch (table path only) leaves columns D_dn..pitch-1 of every row
+// as they are: zeros there stay zeros.
 pdz_status launch_hv(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                      const int* skip = nullptr, unsigned passes = kPassDown | kPassUp,
-                     const HvSplit* split = nullptr);
+                     const HvSplit* split = nullptr, uint64_t pitch = 0);
 // H.v of any problem: momentum and parity sectors go to their kernels (every
-// pass at once, no split form), real-space problems to launch_hv.
+// pass at once, no split form, no pitch), real-space problems to launch_hv.
 pdz_status launch_hv_any(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                          const int* skip = nullptr, unsigned passes = kPassDown | kPassUp,
-                         const HvSplit* split = nullptr);
+                         const HvSplit* split = nullptr, uint64_t pitch = 0);
 bool hv_dot_counts(const pdz_problem_s* p, pdz_dtype dt, int* n_dn, int* n_up);   // false: no split path
 size_t hv_dot_count_max(const pdz_problem_s* p, pdz_dtype dt);   // n_dn + n_up over every valid plan
 

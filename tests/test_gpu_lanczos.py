@@ -300,3 +300,39 @@ def test_errors_and_noconv():
     assert r["status"] == -5 and r["iters"] == 5 and r["converged"] == 0
     E = _energies()["ring8"]["E0"]
     assert r["E0"] > E
+
+
+def test_padded_rows_keep_every_lanczos_path_exact():
+    """Rows of 3,432 down strings are stored with a pitch of 3,456 inside Lanczos (aligned rows for the
+    up pass): the seeded start equals the oracle's SplitMix64 vector given as v0, the Ritz vector comes
+    back in the basis order as an eigenvector, and the restart, re-orthogonalisation and kept-basis
+    paths reach the oracle's energy."""
+    torch = torch_cuda()
+    g = _ring14()
+    assert g.info["D_dn"] == 3432
+    E = _ring14_e0()
+    v0 = to_dev(oracle.start_vector(77, g.D), torch.float64)
+    a = g.lanczos(seed=77, tol=1e-12, max_iter=600)
+    b = g.lanczos(v0=v0, tol=1e-12, max_iter=600)
+    assert a["E0"] == b["E0"] and a["iters"] == b["iters"], (a, b)
+    assert abs(a["E0"] - E) <= 1e-10 * abs(E), (a, E)
+    y = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    r = g.lanczos(ritz=y, tol=1e-12, max_iter=600)
+    assert abs(float(torch.linalg.norm(y)) - 1.0) < 1e-12
+    hy = g.hv(y)
+    assert float(torch.linalg.norm(hy - r["E0_refined"] * y)) < 1e-6, r
+    assert abs(r["E0_refined"] - E) <= 1e-10 * abs(E), (r, E)
+    # FP32 run stopped early, FP64 restart from its (padded) Ritz vector
+    y2 = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    r2 = g.lanczos(storage="f32", tol=1e-12, max_iter=25, refine=2, ritz=y2)
+    assert r2["restart_iters"] > 0 and abs(r2["E0_refined"] - E) <= 1e-10 * abs(E), r2
+    assert float(torch.linalg.norm(g.hv(y2) - r2["E0_refined"] * y2)) < 1e-5, r2
+    for reorth in (1, 2):
+        rr = g.lanczos(reorth=reorth, tol=1e-12, max_iter=300)
+        assert rr["converged"] == 1 and abs(rr["E0"] - E) <= 1e-9 * abs(E), (reorth, rr, E)
+    ya = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    yb = torch.empty(g.D, dtype=torch.float64, device="cuda")
+    ka = g.lanczos(storage="f32", tol=1e-9, max_iter=400, ritz=ya)
+    kb = g.lanczos(storage="f32", tol=1e-9, max_iter=400, ritz=yb, keep_basis=1)
+    assert ka["E0_refined"] == kb["E0_refined"] and torch.equal(ya, yb), (ka, kb)
+    assert abs(ka["E0_refined"] - E) <= 1e-8 * abs(E), (ka, E)

@@ -402,17 +402,22 @@ def parity_bench(torch, pdz, synth, reps=20, E_real=None, calibrate=False):
     return out
 
 
-def hv_median_ms(torch, g, dtype, n=50, warm=5):
-    """Median duration of n back-to-back pdz_hv launches after warm-ups, each bracketed by HIP events."""
-    x = torch.empty(g.D, dtype=dtype, device="cuda").uniform_(-1.0, 1.0)
-    y = torch.empty_like(x)
+def hv_median_ms(torch, g, dtype, n=50, warm=5, pitch=None):
+    """Median duration of n back-to-back pdz_hv launches after warm-ups, each bracketed by HIP events.
+    pitch: pdz_hv_pitched on rows that many elements apart (zeros in the padding) instead."""
+    n_el = g.D if pitch is None else g.info["D_up"] * pitch
+    x = torch.empty(n_el, dtype=dtype, device="cuda").uniform_(-1.0, 1.0)
+    if pitch is not None:
+        x.view(g.info["D_up"], pitch)[:, g.info["D_dn"]:] = 0
+    y = torch.zeros_like(x)
     stream = torch.cuda.current_stream()
+    run = (lambda: g.hv(x, y, stream=stream)) if pitch is None else (lambda: g.hv_pitched(x, pitch, y, stream=stream))
     for _ in range(warm):
-        g.hv(x, y, stream=stream)
+        run()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
     evs[0].record(stream)
     for i in range(n):
-        g.hv(x, y, stream=stream)
+        run()
         evs[i + 1].record(stream)
     evs[-1].synchronize()
     t = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(n))
@@ -699,6 +704,10 @@ def main():
                   "frac": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "kernels_ms": {"down": kt["down"], "up": kt["up"]}}
         lk = g.lanczos_kernel_times(dn, steps=20)
         hv[dn]["lanczos_step_kernels_ms"] = {k: lk[k] for k in ("down", "up", "update", "scalars", "step")}
+        # the row layout Lanczos keeps its vectors in: rows padded to a multiple of 32 elements
+        pitch = (g.info["D_dn"] + 31) // 32 * 32
+        msp = hv_median_ms(torch, g, dt, n=args.hv_reps, warm=5, pitch=pitch)
+        hv[dn]["padded_rows"] = {"pitch": pitch, "ms": msp, "frac": alg / (msp * 1e-3) / 1e9 / PEAK_HBM_GBS}
     _log(f"hv {hv}")
     detail["hv"] = hv
     traffic = recorded_traffic(w.name, tuned["f32"])
@@ -833,6 +842,9 @@ def main():
                      "avg_ms": h32["ms"], "kernels_ms": h32["kernels_ms"], "plan": tuned["f32"]},
         "hv_f64": {"ms": h64["ms"], "nnz_per_s": h64["nnz_per_s"], "achieved_GBs": h64["achieved_GBs"],
                    "frac": h64["frac"], "kernels_ms": h64["kernels_ms"]},
+        "hv_padded_rows": {"pitch": h32["padded_rows"]["pitch"], "f32_ms": h32["padded_rows"]["ms"],
+                           "f32_frac": h32["padded_rows"]["frac"], "f64_ms": h64["padded_rows"]["ms"],
+                           "f64_frac": h64["padded_rows"]["frac"]},
         "fp64_steps": {"value": nnz * args.steps / t64, "ms_per_step": t64 / args.steps * 1e3},
         "time_to_E0_1e-8": tte_c,
         "sections": summ,

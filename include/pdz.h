@@ -133,6 +133,18 @@ pdz_status pdz_device_errors(uint32_t* word);
  * Errors: PDZ_EINVAL (null handle/pointer, overlapping x and y, bad dtype). */
 pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* stream);
 
+/* pdz_hv on vectors whose rows (one per up string) start `pitch` elements
+ * apart: x and y hold D_up * pitch elements, element (u, d) at u * pitch + d;
+ * columns D_dn..pitch-1 of x are not read and those of y are not written.
+ * Same sums in the same order as pdz_hv, so the D elements are bitwise equal
+ * to its output.  A pitch that is a multiple of 32 elements starts every row
+ * on a 128-byte line, which the up pass reads faster (the layout pdz_lanczos
+ * keeps its vectors in).  Real-space problems with hop tables only.
+ * Errors: PDZ_EINVAL (as pdz_hv; pitch < D_dn; pitch != D_dn on a symmetry
+ * sector or the on-the-fly path; pitch > 13,280 when the down pass that runs
+ * is the scheduled one). */
+pdz_status pdz_hv_pitched(pdz_problem p, pdz_dtype dt, const void* x, void* y, uint64_t pitch, void* stream);
+
 /* ------------------------------------------------------ H.v launch plans */
 
 /* Launch geometry of pdz_hv for one precision.  0 in a field = automatic.

@@ -93,6 +93,21 @@ class Problem:
                                 ctypes.c_void_p(y.data_ptr()), _stream_handle(stream)))
         return y
 
+    def hv_pitched(self, x, pitch, y=None, stream=None):
+        """y = H x on vectors of D_up rows `pitch` elements apart (columns past D_dn not read in x, not
+        written in y)."""
+        import torch
+        n = self.info["D_up"] * int(pitch)
+        if not x.is_cuda or not x.is_contiguous() or x.numel() != n:
+            raise ValueError("x must be a contiguous device tensor of D_up * pitch elements")
+        if y is None:
+            y = torch.zeros_like(x)
+        if y.dtype != x.dtype or y.numel() != n or not y.is_contiguous():
+            raise ValueError("y must match x")
+        _lib.check(lib().pdz_hv_pitched(self._h, _dtype_code(x.dtype), ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(y.data_ptr()), int(pitch), _stream_handle(stream)))
+        return y
+
     def get_plan(self, dtype):
         pl = _lib.HvPlan()
         _lib.check(lib().pdz_hv_get_plan(self._h, _dtype_code(dtype), ctypes.byref(pl)))
@@ -126,7 +141,8 @@ class Problem:
         fastest is timed as Lanczos steps (libpdz wall time of a steps[1]-step run minus that of a
         steps[0]-step run, so that set-up and graph capture cancel) and the fastest is selected.
         Inside Lanczos the update rides on the down pass and the up pass writes its part apart, so
-        the ranking can differ from that of the bare H.v.  Returns (best, hv_trials, step_trials)."""
+        the ranking can differ from that of the bare H.v; step times within 1 % of the fastest count
+        as a tie, settled by the bare H.v time.  Returns (best, hv_trials, step_trials)."""
         import torch
         _, trials = self.tune(dtype, reps=reps)
         keys = ("down", "up_cw", "up", "map")
@@ -148,7 +164,15 @@ class Problem:
             t1 = self.lanczos(workspace=ws, max_iter=steps[1], **kw)["seconds"]
             out.append(dict(zip(keys, k), ms_per_step=(t1 - t0) / (steps[1] - steps[0]) * 1e3))
         del ws
-        best = min(out, key=lambda r: r["ms_per_step"])
+        # step times within 1 % of the fastest are a tie (run-to-run noise): the tie goes to the
+        # plan with the fastest plain H.v
+        fastest = min(r["ms_per_step"] for r in out)
+        hv_ms = {}
+        for t in trials:
+            k = tuple(t[n] for n in keys)
+            hv_ms[k] = min(hv_ms.get(k, float("inf")), t["ms"])
+        near = [r for r in out if r["ms_per_step"] <= 1.01 * fastest]
+        best = min(near, key=lambda r: (hv_ms.get(tuple(r[n] for n in keys), float("inf")), r["ms_per_step"]))
         self.set_plan(dtype, *(best[n] for n in keys))
         return {n: best[n] for n in keys}, trials, out
 

@@ -83,6 +83,7 @@ _SIGNATURES = {
     "pdz_unrank": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]),
     "pdz_device_errors": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_uint32)]),
     "pdz_hv": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, _P]),
+    "pdz_hv_pitched": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.c_uint64, _P]),
     "pdz_hv_get_plan": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(HvPlan)]),
     "pdz_hv_set_plan": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(HvPlan)]),
     "pdz_hv_tune": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(HvTrial),

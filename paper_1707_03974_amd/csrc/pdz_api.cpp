@@ -357,4 +357,23 @@ pdz_status pdz_hv(pdz_problem p, pdz_dtype dt, const void* x, void* y, void* str
     return launch_hv_any(p, dt, x, y, (hipStream_t)stream);
 }
 
+pdz_status pdz_hv_pitched(pdz_problem p, pdz_dtype dt, const void* x, void* y, uint64_t pitch, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(PDZ_EINVAL, "problem is NULL");
+    if (dt != PDZ_F64 && dt != PDZ_F32) return fail(PDZ_EINVAL, "dtype must be PDZ_F64 or PDZ_F32");
+    if (!x || !y) return fail(PDZ_EINVAL, "NULL vector");
+    if (pitch < p->dn.D) return fail(PDZ_EINVAL, "pitch shorter than a row");
+    if ((p->ks || p->par || p->hv_path != 0) && pitch != p->dn.D)
+        return fail(PDZ_EINVAL, "padded rows need a real-space problem with hop tables");
+    const size_t bytes = (size_t)(p->up.D * pitch) * (dt == PDZ_F64 ? 8 : 4);
+    const char* xb = static_cast<const char*>(x);
+    const char* yb = static_cast<const char*>(y);
+    if (xb < yb + bytes && yb < xb + bytes) return fail(PDZ_EINVAL, "x and y overlap");
+    int dev = 0;
+    PDZ_HIP(hipGetDevice(&dev));
+    if (dev != p->device) return fail(PDZ_EINVAL, "problem lives on another device");
+    return launch_hv_any(p, dt, x, y, (hipStream_t)stream, nullptr, kPassDown | kPassUp, nullptr,
+                         pitch == p->dn.D ? 0 : pitch);
+}
+
 }  // extern "C"

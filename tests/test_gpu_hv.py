@@ -290,3 +290,27 @@ def test_down_rows_longer_than_the_gather_schedule_plane(args):
             err = np.abs(y - ref)
             assert np.all(err <= bound), (args[:1], name, t, float(np.max(err / np.maximum(bound, 1e-300))))
         g.set_plan(name, 0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("name", ["torus4x3", "torus4x4_nnn"])
+def test_pitched_rows_give_the_plain_result_bitwise(name):
+    """pdz_hv_pitched on rows padded to a multiple of 32 elements (and to one element more than a row):
+    every element bitwise equal to pdz_hv's, the padding columns of y untouched, x's never read."""
+    torch = torch_cuda()
+    import paper_1707_03974_amd as pdz
+    g = _gpu_problem(synth.workload(name))
+    Dup, Ddn = g.info["D_up"], g.info["D_dn"]
+    for dt in (torch.float64, torch.float32):
+        x = to_dev(synth.random_vector(g.D, 31), dt)
+        ref = g.hv(x)
+        for pitch in ((Ddn + 31) // 32 * 32 + (32 if Ddn % 32 == 0 else 0), Ddn + 1):
+            xp = torch.full((Dup, pitch), float("nan"), dtype=dt, device="cuda")   # padding never read
+            xp[:, :Ddn] = x.view(Dup, Ddn)
+            yp = torch.full((Dup, pitch), 7.0, dtype=dt, device="cuda")
+            g.hv_pitched(xp.view(-1), pitch, y=yp.view(-1))
+            assert torch.equal(yp[:, :Ddn].reshape(-1), ref), (name, dt, pitch)
+            assert bool(torch.all(yp[:, Ddn:] == 7.0)), (name, dt, pitch)
+            del xp, yp
+        del x, ref
+    with pytest.raises(pdz.PdzError):
+        g.hv_pitched(torch.zeros(Dup * (Ddn - 1), device="cuda"), Ddn - 1)

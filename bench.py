@@ -627,6 +627,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-dynamics", action="store_true")
     ap.add_argument("--no-kspace", action="store_true")
+    ap.add_argument("--no-padded-hv", action="store_true",
+                    help="skip the H.v on padded rows (keeps a counter run's H.v dispatches to the plain layout)")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="only the Lanczos steps, the H.v timing and "
@@ -705,9 +707,10 @@ def main():
         lk = g.lanczos_kernel_times(dn, steps=20)
         hv[dn]["lanczos_step_kernels_ms"] = {k: lk[k] for k in ("down", "up", "update", "scalars", "step")}
         # the row layout Lanczos keeps its vectors in: rows padded to a multiple of 32 elements
-        pitch = (g.info["D_dn"] + 31) // 32 * 32
-        msp = hv_median_ms(torch, g, dt, n=args.hv_reps, warm=5, pitch=pitch)
-        hv[dn]["padded_rows"] = {"pitch": pitch, "ms": msp, "frac": alg / (msp * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        if not args.no_padded_hv:
+            pitch = (g.info["D_dn"] + 31) // 32 * 32
+            msp = hv_median_ms(torch, g, dt, n=args.hv_reps, warm=5, pitch=pitch)
+            hv[dn]["padded_rows"] = {"pitch": pitch, "ms": msp, "frac": alg / (msp * 1e-3) / 1e9 / PEAK_HBM_GBS}
     _log(f"hv {hv}")
     detail["hv"] = hv
     traffic = recorded_traffic(w.name, tuned["f32"])
@@ -842,9 +845,10 @@ def main():
                      "avg_ms": h32["ms"], "kernels_ms": h32["kernels_ms"], "plan": tuned["f32"]},
         "hv_f64": {"ms": h64["ms"], "nnz_per_s": h64["nnz_per_s"], "achieved_GBs": h64["achieved_GBs"],
                    "frac": h64["frac"], "kernels_ms": h64["kernels_ms"]},
-        "hv_padded_rows": {"pitch": h32["padded_rows"]["pitch"], "f32_ms": h32["padded_rows"]["ms"],
-                           "f32_frac": h32["padded_rows"]["frac"], "f64_ms": h64["padded_rows"]["ms"],
-                           "f64_frac": h64["padded_rows"]["frac"]},
+        "hv_padded_rows": None if args.no_padded_hv else {
+            "pitch": h32["padded_rows"]["pitch"], "f32_ms": h32["padded_rows"]["ms"],
+            "f32_frac": h32["padded_rows"]["frac"], "f64_ms": h64["padded_rows"]["ms"],
+            "f64_frac": h64["padded_rows"]["frac"]},
         "fp64_steps": {"value": nnz * args.steps / t64, "ms_per_step": t64 / args.steps * 1e3},
         "time_to_E0_1e-8": tte_c,
         "sections": summ,

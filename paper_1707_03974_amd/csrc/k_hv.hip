@@ -51,8 +51,16 @@ struct DownArgs {
     int add_y;        // scheduled pass: 1 adds its part to y (written by the up pass), 0 writes y
     double* dotp;     // NULL, or one partial sum of x . y (this pass's output) per work group
     const int* skip;
+    // Row groups other than R consecutive rows of the D_up x pitch matrix
+    // (scheduled pass only; the full rows of a parity subspace): group g has
+    // gnr[g] rows of pitch elements from element goff[g]; up_states then holds
+    // the up string of row r of group g at g * R + r, and dn_states the down
+    // string of each column.  goff == NULL: the plain matrix.
+    const uint64_t* goff;
+    const uint8_t* gnr;
+    uint64_t ngroups;
     // Fused Lanczos recurrence (FUSE kernels only): the staged rows are
-    // q_{k+1} = sc[k] (y + fz) - alpha[k] sc[k] fq1 - beta[k] sc[k-1] fq2,
+    // q_{k+1} = sc[k] (y + fz) - alpha[k] sc[k] fq1 - beta[k] sc[k-1] fq2 (fz NULL: y alone),
     // formed element by element from the previous step's down part (y, then
     // overwritten by this pass's output), its up part fz, q_k (fq1) and
     // q_{k-1} (fq2, overwritten by q_{k+1}; also copied to slot k + 1 of fkeep
@@ -526,8 +534,15 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     const uint32_t Dn = (uint32_t)D_dn;
     const uint64_t pitch = a.pitch;   // a group's rows are R * pitch consecutive elements (columns
     const uint32_t Pn = (uint32_t)pitch;   // past Dn: zeros, staged too, never gathered)
-    const uint64_t ngroups = (D_up + R - 1) / R;
+    const uint64_t ngroups = a.goff ? a.ngroups : (D_up + R - 1) / R;
     const uint32_t nwaves = (Dn + 63) / 64;
+    // rows and first element of group g
+    auto grows = [&](uint64_t g) -> uint32_t {
+        if (a.goff) return a.gnr[g];
+        const uint64_t u0 = g * R;
+        return (uint32_t)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
+    };
+    auto gstart = [&](uint64_t g) -> uint64_t { return a.goff ? a.goff[g] : g * R * pitch; };
     const int lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // zero pads: read by lanes without a hop at a step
@@ -583,16 +598,16 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     T pre[PQ][4];
     T pz[FUSE ? PQ : 1][4], p1[FUSE ? PQ : 1][4], p2[FUSE ? PQ : 1][4];
     auto fetch = [&](uint64_t g) {
-        const uint64_t u0 = g * R;
-        const uint32_t nelem = (uint32_t)(((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R) * pitch);
-        const uint64_t off = u0 * pitch;
+        const uint32_t nelem = grows(g) * Pn;
+        const uint64_t off = gstart(g);
 #pragma unroll
         for (int i = 0; i < PQ; ++i) {
             const uint32_t k0 = 4u * (threadIdx.x + (uint32_t)i * kWideBlock);
             if (k0 < nelem) {
                 if constexpr (FUSE) {
                     load4(y, off + k0, k0, nelem, pre[i], false);
-                    load4(a.fz, off + k0, k0, nelem, pz[i], false);
+                    if (a.fz) load4(a.fz, off + k0, k0, nelem, pz[i], false);
+                    else pz[i][0] = pz[i][1] = pz[i][2] = pz[i][3] = (T)0;
                     load4(a.fq1, off + k0, k0, nelem, p1[i], false);
                     load4(a.fq2, off + k0, k0, nelem, p2[i], false);
                 } else {
@@ -643,7 +658,8 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     if (blockIdx.x < ngroups) fetch(blockIdx.x);
     for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const uint64_t u0 = g * R;
-        const int nr = (int)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
+        const uint64_t g0 = gstart(g);   // first element of the group
+        const int nr = (int)grows(g);
         const uint32_t nelem = (uint32_t)nr * Pn;
         const uint32_t nput = (uint32_t)R * Pn;   // rows past the last are staged as zeros
         __syncthreads();
@@ -653,7 +669,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
             if (k0 < nput) {
                 T v[4];
                 if constexpr (FUSE) {
-                    if (k0 < nelem) form4(u0 * pitch + k0, k0, nelem, pre[i], pz[i], p1[i], p2[i], v);
+                    if (k0 < nelem) form4(g0 + k0, k0, nelem, pre[i], pz[i], p1[i], p2[i], v);
                     put4(k0, nelem, nput, v);
                 } else {
                     put4(k0, nelem, nput, pre[i]);
@@ -668,10 +684,11 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
             for (int j = 0; j < NQ; ++j) {
                 const uint32_t k0 = 4u * (qb + (uint32_t)j * kWideBlock);
                 if (k0 < nelem) {
-                    const uint64_t e0 = u0 * pitch + k0;
+                    const uint64_t e0 = g0 + k0;
                     if constexpr (FUSE) {
                         load4(y, e0, k0, nelem, v0[j], false);
-                        load4(a.fz, e0, k0, nelem, v1[j], false);
+                        if (a.fz) load4(a.fz, e0, k0, nelem, v1[j], false);
+                        else v1[j][0] = v1[j][1] = v1[j][2] = v1[j][3] = (T)0;
                         load4(a.fq1, e0, k0, nelem, v2[j], false);
                         load4(a.fq2, e0, k0, nelem, v3[j], false);
                     } else {
@@ -685,7 +702,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
                 if (k0 < nput) {
                     if constexpr (FUSE) {
                         T v[4];
-                        if (k0 < nelem) form4(u0 * pitch + k0, k0, nelem, v0[j], v1[j], v2[j], v3[j], v);
+                        if (k0 < nelem) form4(g0 + k0, k0, nelem, v0[j], v1[j], v2[j], v3[j], v);
                         put4(k0, nelem, nput, v);
                     } else {
                         put4(k0, nelem, nput, v0[j]);
@@ -744,7 +761,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
             if (a.add_y) {   // the up part of these elements, loaded with the schedule words
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    acc[r] = (live && r < nr) ? __builtin_nontemporal_load(y + (u0 + r) * pitch + d) : (T)0;
+                    acc[r] = (live && r < nr) ? __builtin_nontemporal_load(y + g0 + r * pitch + d) : (T)0;
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -798,7 +815,7 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (r < nr) {
-                        __builtin_nontemporal_store(acc[r], y + (u0 + r) * pitch + d);
+                        __builtin_nontemporal_store(acc[r], y + g0 + r * pitch + d);
                         dsum += (double)get(r, d * 4u) * (double)acc[r];
                     }
             }
@@ -1501,7 +1518,7 @@ pdz_status run_tables(const pdz_problem_s* p, const DeviceCtx* ctx, const T* coe
     const uint64_t D_up = p->up.D, D_dn = p->dn.D;
     const int ncoef = (int)p->coef_host.size();
     // ---- down pass
-    DownArgs<T, E> da;
+    DownArgs<T, E> da{};
     da.D_up = D_up;
     da.D_dn = D_dn;
     da.pitch = pitch;
@@ -1777,6 +1794,92 @@ size_t hv_dot_count_max(const pdz_problem_s* p, pdz_dtype dt) {
         if (n > best) best = n;
     }
     return best;
+}
+
+namespace {
+
+template <typename T, int R, bool FUSE>
+void launch_groups_r(uint64_t grid, hipStream_t s, const DownArgs<T, uint16_t>& da, const SchedArgs<T>& sa,
+                     const T* x, T* y) {
+    hipLaunchKernelGGL((k_hv_down_sched<T, uint16_t, R, FUSE>), dim3((unsigned)grid), dim3(kWideBlock), 0, s, da, sa,
+                       x, y);
+}
+
+template <typename T>
+pdz_status run_sched_groups(const SchedGroups& gr, const T* x, T* y, hipStream_t s, const int* skip,
+                            const HvSplit* f) {
+    if (!gr.sched || !gr.sched->words) return fail(PDZ_EINVAL, "no gather schedule for these rows");
+    if (gr.R < 1 || gr.R > 3 || (sizeof(T) == 8 && gr.R != 1)) return fail(PDZ_EINVAL, "rows per group");
+    if (gr.D_dn + 32 > (uint64_t)kSchedPlane) return fail(PDZ_EINVAL, "rows longer than the schedule's plane");
+    const bool fuse = f && f->fq2;
+    if (fuse && (f->fz || !f->fnorm || !f->fq1)) return fail(PDZ_EINVAL, "fused recurrence arguments");
+    DownArgs<T, uint16_t> da{};
+    da.D_up = gr.ngroups * (uint64_t)gr.R;
+    da.D_dn = gr.D_dn;
+    da.pitch = gr.D_dn;
+    da.U = (T)gr.U;
+    da.up_states = gr.grp_up;
+    da.dn_states = gr.col_dn;
+    da.rows = gr.R;
+    da.skip = skip;
+    da.goff = gr.goff;
+    da.gnr = gr.gnr;
+    da.ngroups = gr.ngroups;
+    if (fuse) {
+        da.fq1 = static_cast<const T*>(f->fq1);
+        da.fq2 = static_cast<T*>(f->fq2);
+        da.fkeep = static_cast<T*>(f->fkeep);
+        da.fkeep_ld = f->fkeep_ld;
+        da.fkeep_cap = f->fkeep_cap;
+        da.falpha = f->falpha;
+        da.fbeta = f->fbeta;
+        da.fsc = f->fsc;
+        da.fkidx = f->fkidx;
+        da.fnorm = f->fnorm;
+    }
+    SchedArgs<T> sa;
+    sa.words = gr.sched->words;
+    sa.meta = gr.sched->meta;
+    sa.mag0 = (T)gr.sched->mag0;
+    sa.mag1 = (T)gr.sched->mag1;
+    const uint64_t grid = sched_groups_grid(gr);
+    if (grid == 0) return ok();
+    if constexpr (sizeof(T) == 4) {
+        if (gr.R == 3) {
+            if (fuse) launch_groups_r<T, 3, true>(grid, s, da, sa, x, y);
+            else launch_groups_r<T, 3, false>(grid, s, da, sa, x, y);
+            PDZ_HIP(hipGetLastError());
+            return ok();
+        }
+        if (gr.R == 2) {
+            if (fuse) launch_groups_r<T, 2, true>(grid, s, da, sa, x, y);
+            else launch_groups_r<T, 2, false>(grid, s, da, sa, x, y);
+            PDZ_HIP(hipGetLastError());
+            return ok();
+        }
+    }
+    {
+        if (fuse) launch_groups_r<T, 1, true>(grid, s, da, sa, x, y);
+        else launch_groups_r<T, 1, false>(grid, s, da, sa, x, y);
+    }
+    PDZ_HIP(hipGetLastError());
+    return ok();
+}
+
+}  // namespace
+
+uint64_t sched_groups_grid(const SchedGroups& g) {
+    DeviceCtx* ctx = nullptr;
+    if (device_ctx(&ctx) != PDZ_OK) return 0;
+    const uint64_t cu = (uint64_t)ctx->cu_count;   // one work group per CU: the planes fill the LDS
+    return g.ngroups < cu ? g.ngroups : cu;
+}
+
+pdz_status launch_sched_groups(const SchedGroups& g, pdz_dtype dt, const void* x, void* y, hipStream_t s,
+                               const int* skip, const HvSplit* fuse) {
+    if (dt == PDZ_F64)
+        return run_sched_groups<double>(g, static_cast<const double*>(x), static_cast<double*>(y), s, skip, fuse);
+    return run_sched_groups<float>(g, static_cast<const float*>(x), static_cast<float*>(y), s, skip, fuse);
 }
 
 bool hv_dot_counts(const pdz_problem_s* p, pdz_dtype dt, int* n_dn, int* n_up) {

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -1029,11 +1030,12 @@ struct Run {
         const SplitCounts c = split_counts();
         if (p->par) {
             // parity: the recurrence rides on its down pass (two-pass form) in
-            // FP64 storage, where a row fills the LDS budget and the fused pass
-            // costs less than the separate update; in FP32 two rows share a CU
-            // and the separate update is the faster of the two
+            // FP64 storage, and in FP32 where that pass is the gather-scheduled
+            // one; the looped FP32 pass (two rows share a CU) is faster with
+            // the separate update
             const int nn = parity_fused_norms(p, (pdz_dtype)o->storage);
-            return o->storage == PDZ_F64 && nn > 0 && nn <= kMaxPartials && c.nwhole > 0;
+            const bool f32 = parity_sched_down(p, (pdz_dtype)o->storage);
+            return (o->storage == PDZ_F64 || f32) && nn > 0 && nn <= kMaxPartials && c.nwhole > 0;
         }
         return c.ndn > 0 && c.ndn <= kMaxPartials && hv_fused_available(p, (pdz_dtype)o->storage);
     }

@@ -78,6 +78,19 @@ struct ParSpace {
     uint32_t* d_rows_pal = nullptr;   // rows of palindromic up strings
     uint64_t n_full = 0, n_pal = 0;
     uint32_t* d_S = nullptr;          // (N+1) x (nmax+1): representatives (palindromes included), Sec. IV.B
+    // Scheduled down pass of the full rows (two-pass form): the gather
+    // schedule of the column hop table (fcnt, fell), the down string of each
+    // column, and the rows in groups of consecutive full rows that follow
+    // each other in memory, at most 1 (index 0, FP64) or 3 (index 1, FP32)
+    // rows a group.  No schedule (rows shorter than 1024 or longer than a
+    // plane, more than two hop magnitudes): the looped down pass.
+    DownSchedule fsched;
+    uint32_t* d_col_dn = nullptr;
+    uint64_t* d_goff[2] = {nullptr, nullptr};
+    uint8_t* d_gnr[2] = {nullptr, nullptr};
+    uint32_t* d_grp_up[2] = {nullptr, nullptr};
+    uint64_t ngroups[2] = {0, 0};
+    bool force_loop = false;          // PDZ_PARITY_LOOPED_DOWN=1: the looped down pass (its test)
 };
 
 namespace {
@@ -799,6 +812,10 @@ void parity_free(ParSpace* q) {
                     q->d_dcolf, q->d_dlistf, q->d_fmir, q->d_fcnt, q->d_fell, q->d_fell2, q->d_fup};
     for (void* v : ptrs)
         if (v) (void)hipFree(v);
+    void* gptrs[] = {q->d_col_dn, q->d_goff[0], q->d_goff[1], q->d_gnr[0], q->d_gnr[1], q->d_grp_up[0], q->d_grp_up[1]};
+    for (void* v : gptrs)
+        if (v) (void)hipFree(v);
+    free_down_schedule(&q->fsched);
     delete q;
 }
 
@@ -834,6 +851,35 @@ PGeom pgeom(const ParSpace* q, uint64_t Ddn, size_t es) {
 constexpr uint64_t kPFuseGrid = 2048;
 constexpr uint64_t kPFormGrid = 256;
 
+// The scheduled down pass's row groups for element size es, or none (the
+// looped down pass runs).
+bool sched_groups_of(const pdz_problem_s* p, size_t es, SchedGroups* g) {
+    const ParSpace* q = p->par;
+    if (q->force_loop || !q->fsched.words) return false;
+    const int i = es == 8 ? 0 : 1;
+    if (!q->d_goff[i]) return false;
+    g->sched = &q->fsched;
+    g->D_dn = p->dn.D;
+    g->U = p->U;
+    g->grp_up = q->d_grp_up[i];
+    g->col_dn = q->d_col_dn;
+    g->goff = q->d_goff[i];
+    g->gnr = q->d_gnr[i];
+    g->ngroups = q->ngroups[i];
+    g->R = es == 8 ? 1 : 3;
+    return true;
+}
+
+// Work groups of the fused down pass over the full rows (one |q_{k+1}|^2
+// partial each).
+uint64_t full_fuse_grid(const pdz_problem_s* p, size_t es) {
+    const ParSpace* q = p->par;
+    if (q->n_full == 0) return 0;
+    SchedGroups g;
+    if (sched_groups_of(p, es, &g)) return sched_groups_grid(g);
+    return std::min<uint64_t>(q->n_full, kPFuseGrid);
+}
+
 // passes: kPassDown launches the down pass (with the recurrence when f is
 // set: then x is unused and the palindromic rows' q_{k+1} is formed too),
 // kPassUp the up pass and the palindromic rows; both: the whole H.v.
@@ -858,7 +904,25 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
         if (m.two_pass) {
             const size_t lds = (size_t)a.Ddn * sizeof(T);
             const PFuse<T> f0 = f ? *f : PFuse<T>();
-            if (down) {
+            SchedGroups sg;
+            if (down && sched_groups_of(p, sizeof(T), &sg)) {
+                HvSplit hs;
+                if (f) {
+                    hs.fq1 = f->q1;
+                    hs.fq2 = f->q2;
+                    hs.fkeep = f->keep;
+                    hs.fkeep_ld = f->keep_ld;
+                    hs.fkeep_cap = f->keep_cap;
+                    hs.falpha = f->alpha;
+                    hs.fbeta = f->beta;
+                    hs.fsc = f->sc;
+                    hs.fkidx = f->kidx;
+                    hs.fnorm = f->norm;
+                }
+                const pdz_status st =
+                    launch_sched_groups(sg, sizeof(T) == 8 ? PDZ_F64 : PDZ_F32, x, y, s, skip, f ? &hs : nullptr);
+                if (st != PDZ_OK) return st;
+            } else if (down) {
                 if (f && q->d_fell2)
                     hipLaunchKernelGGL((k_hvp_down<T, true, true>), dim3(grid), dim3(kPLdsBlock), lds, s, a, coef, x, y,
                                        skip, f0);
@@ -896,7 +960,7 @@ pdz_status run_hvp(const pdz_problem_s* p, const T* coef, const T* x, T* y, hipS
         a.nlist = q->n_pal;
         if (f)
             hipLaunchKernelGGL(k_pform<T>, dim3((unsigned)kPFormGrid), dim3(kPBlock), 0, s, a, y, skip, *f,
-                               q->n_full > 0 ? (int)std::min<uint64_t>(q->n_full, kPFuseGrid) : 0);
+                               (int)full_fuse_grid(p, sizeof(T)));
         if (up)
             hipLaunchKernelGGL(k_hvp<T>, dim3((unsigned)m.g_pal), dim3(kPBlock), 0, s, a, coef, x, y, skip,
                                dotp ? dotp + m.g_up : nullptr);
@@ -973,7 +1037,15 @@ int parity_fused_norms(const pdz_problem_s* p, pdz_dtype dt) {
     const ParSpace* q = p->par;
     const PGeom m = pgeom(q, p->dn.D, dt == PDZ_F64 ? 8 : 4);
     if (q->n_full > 0 && !m.two_pass) return 0;
-    return (int)((q->n_full > 0 ? std::min<uint64_t>(q->n_full, kPFuseGrid) : 0) + (q->n_pal > 0 ? kPFormGrid : 0));
+    return (int)(full_fuse_grid(p, dt == PDZ_F64 ? 8 : 4) + (q->n_pal > 0 ? kPFormGrid : 0));
+}
+
+bool parity_sched_down(const pdz_problem_s* p, pdz_dtype dt) {
+    if (!p->par) return false;
+    const ParSpace* q = p->par;
+    const size_t es = dt == PDZ_F64 ? 8 : 4;
+    SchedGroups g;
+    return q->n_full > 0 && pgeom(q, p->dn.D, es).two_pass && sched_groups_of(p, es, &g);
 }
 
 int parity_dot_count(const pdz_problem_s* p, pdz_dtype dt) {
@@ -995,6 +1067,8 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
         q->force_gather = env && env[0] == '1';
         const char* wide = std::getenv("PDZ_PARITY_WIDE_TABLE");
         q->wide_table = wide && wide[0] == '1';
+        const char* loop = std::getenv("PDZ_PARITY_LOOPED_DOWN");
+        q->force_loop = loop && loop[0] == '1';
         const char* lanes = std::getenv("PDZ_PARITY_UP_LANES");
         if (lanes) {
             const std::string v(lanes);
@@ -1173,6 +1247,43 @@ pdz_status parity_build(pdz_problem_s* p, int P) {
         }
     }
     if ((st = dupload(&q->d_rows_pal, rows_pal)) != PDZ_OK) return st;
+    if (!q->force_loop && q->n_full > 0 && p->dn.max_hops > 0) {
+        // the scheduled down pass: the column hop table's gather schedule
+        // (none when it does not apply), then the row groups
+        SectorTables cv;
+        cv.D = Dd;
+        cv.max_hops = mh;
+        cv.count = q->d_fcnt;
+        cv.ell = q->d_fell;
+        if ((st = build_down_schedule(cv, p->coef_host, &q->fsched, nullptr)) != PDZ_OK) return st;
+    }
+    if (q->fsched.words) {
+        std::vector<uint32_t> ust(Du), dst(Dd), col_dn(Dd);
+        PDZ_HIP(hipMemcpy(ust.data(), p->up.states, Du * 4, hipMemcpyDeviceToHost));
+        PDZ_HIP(hipMemcpy(dst.data(), p->dn.states, Dd * 4, hipMemcpyDeviceToHost));
+        for (uint64_t c = 0; c < Dd; ++c) col_dn[c] = dst[dlistf[c]];
+        if ((st = dupload(&q->d_col_dn, col_dn)) != PDZ_OK) return st;
+        for (int i = 0; i < 2; ++i) {
+            const uint32_t R = i == 0 ? 1u : 3u;
+            std::vector<uint64_t> goff;
+            std::vector<uint8_t> gnr;
+            std::vector<uint32_t> gup;
+            for (uint32_t k : rows_full) {
+                const bool join = !gnr.empty() && gnr.back() < R && row_off[k] == goff.back() + gnr.back() * Dd;
+                if (!join) {
+                    goff.push_back(row_off[k]);
+                    gnr.push_back(0);
+                    gup.resize(gup.size() + R, 0u);
+                }
+                gup[(gnr.size() - 1) * R + gnr.back()] = ust[row_rank[k]];
+                ++gnr.back();
+            }
+            q->ngroups[i] = gnr.size();
+            if ((st = dupload(&q->d_goff[i], goff)) != PDZ_OK) return st;
+            if ((st = dupload(&q->d_gnr[i], gnr)) != PDZ_OK) return st;
+            if ((st = dupload(&q->d_grp_up[i], gup)) != PDZ_OK) return st;
+        }
+    }
     // structural nonzeros: per element its diagonal plus every hop whose source has a component here
     std::vector<uint8_t> ucnt(Du), dcnt(Dd);
     PDZ_HIP(hipMemcpy(ucnt.data(), p->up.count, Du, hipMemcpyDeviceToHost));

@@ -173,6 +173,8 @@ pdz_status launch_hvp(const pdz_problem_s* p, pdz_dtype dt, const void* x, void*
                       const int* skip, double* dotp = nullptr);
 // partial sums launch_hvp writes to dotp; 0 when it cannot write them
 int parity_dot_count(const pdz_problem_s* p, pdz_dtype dt);
+// whether the parity down pass of the full rows runs gather-scheduled
+bool parity_sched_down(const pdz_problem_s* p, pdz_dtype dt);
 // y = H x on a momentum-space problem (every pass at once; no split form)
 pdz_status launch_hvk(const pdz_problem_s* p, pdz_dtype dt, const void* x, void* y, hipStream_t s,
                       const int* skip);
@@ -221,6 +223,30 @@ pdz_status launch_hvp_split(const pdz_problem_s* p, pdz_dtype dt, const void* x,
 // |q_{k+1}|^2 partials the fused parity down pass writes to fnorm; 0 when
 // the problem has no fused form
 int parity_fused_norms(const pdz_problem_s* p, pdz_dtype dt);
+// The scheduled down pass over explicit row groups (k_hv.hip): the full rows
+// of a parity subspace (every down string, in the column order whose hops
+// `sched` was built from).  Group g: gnr[g] (1..R) rows of D_dn elements,
+// consecutive from element goff[g]; grp_up[g * R + r] the up string of its
+// row r (0 past its rows); col_dn[c] the down string of column c.
+struct SchedGroups {
+    const DownSchedule* sched = nullptr;
+    uint64_t D_dn = 0;
+    double U = 0.0;
+    const uint32_t* grp_up = nullptr;
+    const uint32_t* col_dn = nullptr;
+    const uint64_t* goff = nullptr;
+    const uint8_t* gnr = nullptr;
+    uint64_t ngroups = 0;
+    int R = 1;   // 1 to 3 (FP64: 1)
+};
+// y = diagonal + down hops over the groups' rows (fuse == NULL), or, with
+// fuse->fq2 set, q_{k+1} formed from y (the whole H q_k, fuse->fz NULL), q_k
+// and q_{k-1} as in HvSplit, staged, and the down part of H q_{k+1} written
+// to y; one |q_{k+1}|^2 partial per work group in fuse->fnorm.
+pdz_status launch_sched_groups(const SchedGroups& g, pdz_dtype dt, const void* x, void* y, hipStream_t s,
+                               const int* skip, const HvSplit* fuse);
+uint64_t sched_groups_grid(const SchedGroups& g);   // work groups launch_sched_groups runs
+
 // H.v of a real-space problem (k_hv.hip).  pitch: elements from one row of
 // x, y (and of the split and recurrence vectors) to the next; 0 means D_dn.
 // A longer pitch (table path only) leaves columns D_dn..pitch-1 of every row

@@ -314,3 +314,74 @@ def test_lowest_parity_is_the_real_space_ground_state():
         e.append(g.lanczos(storage="f64", tol=1e-11, max_iter=400)["E0"])
         g.close()
     assert abs(min(e) - e_real) <= 1e-8 * abs(e_real), (e, e_real)
+
+
+def _chain14():
+    """Open 14-site chain with NNN hops (two hop magnitudes), 7+7: full rows of C(14,7) = 3432 columns, long
+    enough for the gather-scheduled down pass; palindromic rows split the full rows into runs of every length."""
+    from synth.lattices import Bond
+    from synth.workloads import Workload
+    return Workload("chain14nnn", 14, [Bond(i, j, t) for i, j, t in _chain(14, 1.0, -0.35)], 5.0, 7, 7)
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+@pytest.mark.parametrize("P", [1, -1])
+def test_parity_scheduled_down_pass_sampled_rows(P, dtype_name):
+    _sampled(_chain14(), P, 200, 13, dtype_name)
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_parity_scheduled_and_looped_down_passes_agree(dtype_name, monkeypatch):
+    """The whole H.v from the scheduled down pass and from the looped one (PDZ_PARITY_LOOPED_DOWN=1) on every
+    element: each is within (n + 6) eps sum|terms| of the exact value, so they are within twice that of each
+    other; sum|terms| <= (U n_dn + sqrt(2) * 2 * (hops per string)) max|x| bounds every element's terms."""
+    torch = torch_cuda()
+    w = _chain14()
+    bonds = [(b.i, b.j, b.t) for b in w.bonds]
+    dt, e = (torch.float64, EPS64) if dtype_name == "f64" else (torch.float32, EPS32)
+    for P in (1, -1):
+        g = _gpu(w.n_sites, bonds, w.U, w.n_up, w.n_dn, P)
+        x = np.random.default_rng(31).uniform(-1, 1, g.D)
+        y1 = to_host(g.hv(to_dev(x, dt))).astype(np.float64)
+        monkeypatch.setenv("PDZ_PARITY_LOOPED_DOWN", "1")
+        g2 = _gpu(w.n_sites, bonds, w.U, w.n_up, w.n_dn, P)
+        monkeypatch.delenv("PDZ_PARITY_LOOPED_DOWN")
+        y2 = to_host(g2.hv(to_dev(x, dt))).astype(np.float64)
+        hops = 2 * (2 * 13 + 2 * 12)   # bonds touching a string's electrons, both spins, at most
+        n = 1 + hops
+        a = (w.U * w.n_dn + np.sqrt(2.0) * hops) * np.max(np.abs(x))
+        err = np.max(np.abs(y1 - y2))
+        assert err <= 2 * (n + 6) * e * a, (P, dtype_name, err)
+        assert err > 0.0 or dtype_name == "f64"   # FP32: the two summation orders differ somewhere
+        g.close()
+        g2.close()
+
+
+def test_parity_scheduled_down_pass_lanczos_gives_the_real_space_ground_state(monkeypatch):
+    """Lanczos with the recurrence fused into the scheduled parity down pass (FP64 storage, and FP32 storage with
+    the FP64 refinement from regenerated or kept vectors): min over the parities is the real-space ground state, and each parity's E0 equals the
+    looped down pass's."""
+    torch_cuda()
+    import paper_1707_03974_amd as pdz
+    w = _chain14()
+    bonds = [(b.i, b.j, b.t) for b in w.bonds]
+    real = pdz.Problem(w.n_sites, bonds, w.U, w.n_up, w.n_dn)
+    e_real = real.lanczos(storage="f64", tol=1e-11, max_iter=400)["E0"]
+    real.close()
+    es = []
+    for P in (1, -1):
+        g = _gpu(w.n_sites, bonds, w.U, w.n_up, w.n_dn, P)
+        e64 = g.lanczos(storage="f64", tol=1e-11, max_iter=400)["E0"]
+        e32 = g.lanczos(storage="f32", tol=1e-7, refine=1, keep_basis=0, max_iter=400)["E0_refined"]
+        e32k = g.lanczos(storage="f32", tol=1e-7, refine=1, keep_basis=1, max_iter=400)["E0_refined"]
+        g.close()
+        monkeypatch.setenv("PDZ_PARITY_LOOPED_DOWN", "1")
+        g2 = _gpu(w.n_sites, bonds, w.U, w.n_up, w.n_dn, P)
+        monkeypatch.delenv("PDZ_PARITY_LOOPED_DOWN")
+        e_loop = g2.lanczos(storage="f64", tol=1e-11, max_iter=400)["E0"]
+        g2.close()
+        assert abs(e64 - e_loop) <= 1e-9 * abs(e_loop), (P, e64, e_loop)
+        assert abs(e32 - e64) <= 1e-8 * abs(e64), (P, e32, e64)
+        assert abs(e32k - e64) <= 1e-8 * abs(e64), (P, e32k, e64)
+        es.append(e64)
+    assert abs(min(es) - e_real) <= 1e-9 * abs(e_real), (es, e_real)

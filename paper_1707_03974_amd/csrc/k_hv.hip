@@ -55,12 +55,12 @@ struct DownArgs {
     // (scheduled pass only; the full rows of a parity subspace): group g has
     // gnr[g] rows of pitch elements from element goff[g]; up_states then holds
     // the up string of row r of group g at g * R + r, and dn_states the down
-    // string of each column.  goff == NULL: the plain matrix.
+    // string of each column (the GRP kernels; the others ignore these).
     const uint64_t* goff;
     const uint8_t* gnr;
     uint64_t ngroups;
     // Fused Lanczos recurrence (FUSE kernels only): the staged rows are
-    // q_{k+1} = sc[k] (y + fz) - alpha[k] sc[k] fq1 - beta[k] sc[k-1] fq2 (fz NULL: y alone),
+    // q_{k+1} = sc[k] (y + fz) - alpha[k] sc[k] fq1 - beta[k] sc[k-1] fq2 (row groups: y alone),
     // formed element by element from the previous step's down part (y, then
     // overwritten by this pass's output), its up part fz, q_k (fq1) and
     // q_{k-1} (fq2, overwritten by q_{k+1}; also copied to slot k + 1 of fkeep
@@ -517,7 +517,9 @@ __device__ __forceinline__ CPtr<U> const_ptr(const U* p) {
 }
 
 
-template <typename T, typename E, int R, bool FUSE>
+// GRP: the row groups come from a.goff / a.gnr (and fz is not read: the
+// recurrence takes the whole H q_k from y); otherwise R consecutive rows.
+template <typename T, typename E, int R, bool FUSE, bool GRP = false>
 __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, E> a, const SchedArgs<T> sc,
                                                               const T* __restrict__ x, T* __restrict__ y) {
     if (a.skip && *a.skip) return;
@@ -534,15 +536,23 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
     const uint32_t Dn = (uint32_t)D_dn;
     const uint64_t pitch = a.pitch;   // a group's rows are R * pitch consecutive elements (columns
     const uint32_t Pn = (uint32_t)pitch;   // past Dn: zeros, staged too, never gathered)
-    const uint64_t ngroups = a.goff ? a.ngroups : (D_up + R - 1) / R;
+    const uint64_t ngroups = GRP ? a.ngroups : (D_up + R - 1) / R;
     const uint32_t nwaves = (Dn + 63) / 64;
     // rows and first element of group g
     auto grows = [&](uint64_t g) -> uint32_t {
-        if (a.goff) return a.gnr[g];
-        const uint64_t u0 = g * R;
-        return (uint32_t)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
+        if constexpr (GRP && R == 1) {
+            return 1u;
+        } else if constexpr (GRP) {
+            return const_ptr(a.gnr)[g];   // wave-uniform: scalar loads
+        } else {
+            const uint64_t u0 = g * R;
+            return (uint32_t)((D_up - u0) < (uint64_t)R ? (D_up - u0) : (uint64_t)R);
+        }
     };
-    auto gstart = [&](uint64_t g) -> uint64_t { return a.goff ? a.goff[g] : g * R * pitch; };
+    auto gstart = [&](uint64_t g) -> uint64_t {
+        if constexpr (GRP) return const_ptr(a.goff)[g];
+        else return g * R * pitch;
+    };
     const int lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // zero pads: read by lanes without a hop at a step
@@ -606,8 +616,8 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
             if (k0 < nelem) {
                 if constexpr (FUSE) {
                     load4(y, off + k0, k0, nelem, pre[i], false);
-                    if (a.fz) load4(a.fz, off + k0, k0, nelem, pz[i], false);
-                    else pz[i][0] = pz[i][1] = pz[i][2] = pz[i][3] = (T)0;
+                    if constexpr (GRP) pz[i][0] = pz[i][1] = pz[i][2] = pz[i][3] = (T)0;
+                    else load4(a.fz, off + k0, k0, nelem, pz[i], false);
                     load4(a.fq1, off + k0, k0, nelem, p1[i], false);
                     load4(a.fq2, off + k0, k0, nelem, p2[i], false);
                 } else {
@@ -687,8 +697,8 @@ __global__ __launch_bounds__(kWideBlock) void k_hv_down_sched(const DownArgs<T, 
                     const uint64_t e0 = g0 + k0;
                     if constexpr (FUSE) {
                         load4(y, e0, k0, nelem, v0[j], false);
-                        if (a.fz) load4(a.fz, e0, k0, nelem, v1[j], false);
-                        else v1[j][0] = v1[j][1] = v1[j][2] = v1[j][3] = (T)0;
+                        if constexpr (GRP) v1[j][0] = v1[j][1] = v1[j][2] = v1[j][3] = (T)0;
+                        else load4(a.fz, e0, k0, nelem, v1[j], false);
                         load4(a.fq1, e0, k0, nelem, v2[j], false);
                         load4(a.fq2, e0, k0, nelem, v3[j], false);
                     } else {
@@ -1801,8 +1811,8 @@ namespace {
 template <typename T, int R, bool FUSE>
 void launch_groups_r(uint64_t grid, hipStream_t s, const DownArgs<T, uint16_t>& da, const SchedArgs<T>& sa,
                      const T* x, T* y) {
-    hipLaunchKernelGGL((k_hv_down_sched<T, uint16_t, R, FUSE>), dim3((unsigned)grid), dim3(kWideBlock), 0, s, da, sa,
-                       x, y);
+    hipLaunchKernelGGL((k_hv_down_sched<T, uint16_t, R, FUSE, true>), dim3((unsigned)grid), dim3(kWideBlock), 0, s, da,
+                       sa, x, y);
 }
 
 template <typename T>

@@ -284,9 +284,12 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_act(const uint16_t* __restrict_
 }
 
 // Weight-gradient partials over one slice of states (one wave per job):
-// jobs 0..63: 16x16 tiles of dW2 = dz2^T h1; jobs 64..71: 16-unit rows of
-// dW1 = dz1^T x; job 72: b1, b2, W3, b3.  part[slice * kParams + k].
-constexpr int kGradJobs = 73;
+// jobs 0..63: 16x16 tiles of dW2 = dz2^T h1 (tiles of column block 0 also
+// b2 = dz2^T 1, a second product with an all-ones operand); jobs 64..71:
+// 16-unit rows of dW1 = dz1^T x (and b1 = dz1^T 1); jobs 72..79: 16 columns
+// of W3 = dout^T h2 each, the 64 lanes as 16 columns x 4 interleaved sample
+// streams (job 72 also b3 = dout^T 1).  part[slice * kParams + k].
+constexpr int kGradJobs = 80;
 __global__ __launch_bounds__(64) void k_mlp_bwd_grad(const uint32_t* __restrict__ occ, uint64_t n, Act act,
                                                      const float* __restrict__ dout,
                                                      const uint16_t* __restrict__ dz2t,
@@ -297,17 +300,27 @@ __global__ __launch_bounds__(64) void k_mlp_bwd_grad(const uint32_t* __restrict_
     const uint64_t b1 = (b0 + kSlice < n) ? b0 + kSlice : n;
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
     float* P = part + (size_t)slice * kParams;
+    const uint16_t one8[8] = {0x3F80, 0x3F80, 0x3F80, 0x3F80, 0x3F80, 0x3F80, 0x3F80, 0x3F80};   // BF16 1.0
+    const bf16x8 ones = pack8(one8);
     if (job < 64) {
         const int ot = job >> 3, jt = job & 7;
         const int o = 16 * ot + c, j = 16 * jt + c;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (uint64_t s = b0; s < b1; s += 32)
-            acc = mma(ld8(dz2t + (uint64_t)o * n + s + 8 * g), ld8(act.h1t + (uint64_t)j * n + s + 8 * g), acc);
+        const bool bias = jt == 0;   // wave-uniform
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+        for (uint64_t s = b0; s < b1; s += 32) {
+            const bf16x8 a = ld8(dz2t + (uint64_t)o * n + s + 8 * g);
+            acc = mma(a, ld8(act.h1t + (uint64_t)j * n + s + 8 * g), acc);
+            if (bias) accb = mma(a, ones, accb);
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) P[oW2 + (16 * ot + 4 * g + t) * kHid + j] = acc[t];
+        if (bias && c == 0)   // every column of accb holds the row sums
+#pragma unroll
+            for (int t = 0; t < 4; ++t) P[oB2 + 16 * ot + 4 * g + t] = accb[t];
     } else if (job < 72) {
         const int ot = job - 64;
         const int o = 16 * ot + c;
+        f32x4 accb = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -319,31 +332,59 @@ __global__ __launch_bounds__(64) void k_mlp_bwd_grad(const uint32_t* __restrict_
                     const uint32_t bits = occ[2 * (s + 8 * g + t) + (i >> 4)];
                     v[t] = ((bits >> (i & 15)) & 1u) ? (uint16_t)0x3F80 : (uint16_t)0xBF80;
                 }
-                acc = mma(ld8(dz1t + (uint64_t)o * n + s + 8 * g), pack8(v), acc);
+                const bf16x8 a = ld8(dz1t + (uint64_t)o * n + s + 8 * g);
+                acc = mma(a, pack8(v), acc);
+                if (it == 0) accb = mma(a, ones, accb);
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) P[oW1 + (16 * ot + 4 * g + t) * kIn + i] = acc[t];
         }
+        if (c == 0)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) P[oB1 + 16 * ot + 4 * g + t] = accb[t];
     } else {
-        for (int o = lane; o < kHid; o += 64) {
-            float s1 = 0.f, s2 = 0.f;
-            for (uint64_t s = b0; s < b1; ++s) {
-                s1 += bf2f(dz1t[(uint64_t)o * n + s]);
-                s2 += bf2f(dz2t[(uint64_t)o * n + s]);
+        const int jt = job - 72;
+        const int j = 16 * jt + c;
+        float a0 = 0.f, a1 = 0.f;
+        constexpr int U = 8;   // loads in flight per lane
+        for (uint64_t s0 = b0 + (uint64_t)g; s0 < b1; s0 += 4 * U) {
+            float h[U], d0[U], d1[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t s = s0 + 4 * (uint64_t)u;
+                const bool in = s < b1;
+                h[u] = in ? bf2f(act.h2[s * kHid + j]) : 0.f;
+                d0[u] = in ? dout[2 * s] : 0.f;
+                d1[u] = in ? dout[2 * s + 1] : 0.f;
             }
-            P[oB1 + o] = s1;
-            P[oB2 + o] = s2;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                a0 += d0[u] * h[u];
+                a1 += d1[u] * h[u];
+            }
         }
-        for (int q = lane; q < kOut * kHid; q += 64) {
-            const int m = q / kHid, j = q % kHid;
-            float a = 0.f;
-            for (uint64_t s = b0; s < b1; ++s) a += dout[2 * s + m] * bf2f(act.h2[s * kHid + j]);
-            P[oW3 + q] = a;
+        a0 += __shfl_xor(a0, 16);
+        a0 += __shfl_xor(a0, 32);
+        a1 += __shfl_xor(a1, 16);
+        a1 += __shfl_xor(a1, 32);
+        if (g == 0) {
+            P[oW3 + j] = a0;
+            P[oW3 + kHid + j] = a1;
         }
-        if (lane < kOut) {
-            float a = 0.f;
-            for (uint64_t s = b0; s < b1; ++s) a += dout[2 * s + lane];
-            P[oB3 + lane] = a;
+        if (jt == 0) {
+            float e0 = 0.f, e1 = 0.f;
+            for (uint64_t s = b0 + (uint64_t)lane; s < b1; s += 64) {
+                e0 += dout[2 * s];
+                e1 += dout[2 * s + 1];
+            }
+            for (int m = 32; m > 0; m >>= 1) {
+                e0 += __shfl_xor(e0, m);
+                e1 += __shfl_xor(e1, m);
+            }
+            if (lane == 0) {
+                P[oB3] = e0;
+                P[oB3 + 1] = e1;
+            }
         }
     }
 }

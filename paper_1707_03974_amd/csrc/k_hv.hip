@@ -19,6 +19,8 @@
 // Every output element is summed by one thread in a fixed order (diagonal,
 // down hops in bond order, up hops in bond order): no atomics, bitwise
 // reproducible, and the same order as the fallback path.
+#include <type_traits>
+
 #include "pdz_internal.h"
 
 namespace pdz {
@@ -1019,27 +1021,34 @@ __global__ __launch_bounds__(BLK) void k_hv_up(const UpArgs<T, E> a, const T* __
 #pragma unroll
                     for (int i = 0; i < VEC; ++i) acc[i] += c[q] * v[q][i];
             }
-            if (h < cnt) {
-                // the last cnt - h (< NB) hops as one batch: every load issued
-                // before the first multiply-add; slots past the count reload
-                // hop h and their products are not added
-                T v[NB][VEC];
-                T c[NB];
+            // the last cnt - h (< NB) hops in batches of NB/2, NB/4, ..., 1 taken
+            // while they fit: exactly one load per hop, every load of a batch
+            // issued before its first multiply-add, the hops in order
+            auto tail = [&](auto bc) {
+                constexpr int B = decltype(bc)::value;
+                if constexpr (B >= 1 && B < NB) {
+                    if (h + B <= cnt) {
+                        T v[B][VEC];
+                        T c[B];
 #pragma unroll
-                for (int q = 0; q < NB; ++q) {
-                    const int k = h + q < cnt ? h + q : h;
-                    const UpHop<T> hq = hp[k];
-                    c[q] = hq.c;
-                    const T* src = IDX64 ? x + o64[k] + d : x + (uint32_t)(hq.off + (uint32_t)d);
-                    vec_load<T, VEC>(src, v[q]);
+                        for (int q = 0; q < B; ++q) {
+                            const UpHop<T> hq = hp[h + q];
+                            c[q] = hq.c;
+                            const T* src = IDX64 ? x + o64[h + q] + d : x + (uint32_t)(hq.off + (uint32_t)d);
+                            vec_load<T, VEC>(src, v[q]);
+                        }
+#pragma unroll
+                        for (int q = 0; q < B; ++q)
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i) acc[i] += c[q] * v[q][i];
+                        h += B;
+                    }
                 }
-#pragma unroll
-                for (int q = 0; q < NB; ++q)
-                    if (h + q < cnt)
-#pragma unroll
-                        for (int i = 0; i < VEC; ++i) acc[i] += c[q] * v[q][i];
-                h = cnt;
-            }
+            };
+            tail(std::integral_constant<int, 8>{});
+            tail(std::integral_constant<int, 4>{});
+            tail(std::integral_constant<int, 2>{});
+            tail(std::integral_constant<int, 1>{});
         }
         for (; h < cnt; ++h) {
             const UpHop<T> hq = hp[h];

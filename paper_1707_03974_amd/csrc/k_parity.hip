@@ -37,6 +37,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pdz_internal.h"
@@ -560,32 +561,41 @@ __global__ __launch_bounds__(kPUpBlock) void k_hvp_up(const PArgs a, const T* __
             T accI[CPT];
 #pragma unroll
             for (int t = 0; t < CPT; ++t) accI[t] = (T)0;
-            for (int h = 0; h < n_np; h += kPUpNB) {
-                T v[kPUpNB][CPT], fa[kPUpNB], fi[kPUpNB];
-                uint64_t e[kPUpNB];
+            // hops in batches of kPUpNB, then of kPUpNB/2, ..., 1 while they
+            // fit: one load per hop, the batch's entries first, then its loads
+            int h = 0;
+            auto batch = [&](auto bc) {
+                constexpr int B = decltype(bc)::value;
+                T v[B][CPT], fa[B], fi[B];
+                uint64_t e[B];
 #pragma unroll
-                for (int q = 0; q < kPUpNB; ++q) {   // the batch's entries first, then its loads
-                    const int hq = h + q < n_np ? h + q : h;   // slots past the count reload hop h, factor 0
-                    e[q] = er[hq];
-                    const T f = h + q < n_np ? fr[hq] : (T)0;
+                for (int q = 0; q < B; ++q) {
+                    e[q] = er[h + q];
+                    const T f = fr[h + q];
                     const bool img = ((e[q] >> 40) & 3u) == kClsImage;
                     fa[q] = img ? (T)0 : f;
                     fi[q] = img ? f : (T)0;
                 }
 #pragma unroll
-                for (int q = 0; q < kPUpNB; ++q) {
+                for (int q = 0; q < B; ++q) {
                     const T* src = x + (e[q] & 0xFFFFFFFFFFull) + c0;   // one wide load (any alignment)
 #pragma unroll
                     for (int t = 0; t < CPT; ++t) v[q][t] = src[t];
                 }
 #pragma unroll
-                for (int q = 0; q < kPUpNB; ++q)
+                for (int q = 0; q < B; ++q)
 #pragma unroll
                     for (int t = 0; t < CPT; ++t) {
                         acc[t] += fa[q] * v[q][t];
                         accI[t] += fi[q] * v[q][t];
                     }
-            }
+                h += B;
+            };
+            static_assert(kPUpNB == 8, "tail batches below");
+            while (h + kPUpNB <= n_np) batch(std::integral_constant<int, kPUpNB>{});
+            if (h + 4 <= n_np) batch(std::integral_constant<int, 4>{});
+            if (h + 2 <= n_np) batch(std::integral_constant<int, 2>{});
+            if (h + 1 <= n_np) batch(std::integral_constant<int, 1>{});
 #pragma unroll
             for (int t = 0; t < CPT; ++t) acc[t] += accI[t ^ 1];
         } else {

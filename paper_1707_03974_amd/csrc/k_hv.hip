@@ -953,9 +953,11 @@ __global__ __launch_bounds__(BLK) void k_hv_up(const UpArgs<T, E> a, const T* __
     const uint64_t u_begin = (uint64_t)tile * ROWS_PER_TILE;
     const int nrows = (int)((D_up - u_begin) < (uint64_t)ROWS_PER_TILE ? (D_up - u_begin) : (uint64_t)ROWS_PER_TILE);
     for (int r = threadIdx.x; r < nrows; r += BLK) s_cnt[r] = a.up_count[u_begin + r];
+    __syncthreads();
     for (int k = threadIdx.x; k < nrows * maxh; k += BLK) {
         const int r = k / maxh, h = k - r * maxh;
-        const uint32_t e = hop_entry(a.up_ell, h, u_begin + r, D_up);   // slots past the count are never read
+        if (h >= s_cnt[r]) continue;   // slots past the count: neither loaded nor read
+        const uint32_t e = hop_entry(a.up_ell, h, u_begin + r, D_up);
         const uint32_t ci = e >> a.cshift;
         s_hop[k].c = a.coef[ci < (uint32_t)a.ncoef ? ci : 0];
         if (IDX64)

@@ -14,16 +14,45 @@
 
 namespace pdz {
 
+// 1/q in FP64 from the hardware reciprocal estimate and two steps of Newton's
+// iteration r <- r + r (1 - q r), each of which doubles the number of correct
+// bits; a few fused operations in place of a division on the serial chains
+// below (q finite, |q| >= 1e-300: the callers lift smaller pivots to 1e-300).
+__device__ inline double tridiag_recip(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    double t = fma(-q, r, 1.0);
+    r = fma(r, t, r);
+    t = fma(-q, r, 1.0);
+    return fma(r, t, r);
+}
+
+// Operands read ahead of the serial steps below: the LDS reads of a batch are
+// issued together, so one wait covers them, and the steps then run on
+// registers (the arithmetic and its order are those of the plain loops).
+constexpr int kTriBatch = 8;
+
 // Number of eigenvalues of T below x (signs of the LDL^T pivots of T - x I).
 __device__ inline int tridiag_sturm_count(const double* a, const double* e, int k, double x) {
     int cnt = 0;
     double q = a[0] - x;
     if (q < 0.0) ++cnt;
-    for (int i = 1; i < k; ++i) {
-        if (q == 0.0) q = 1e-300;
-        q = (a[i] - x) - e[i] * e[i] / q;
+    auto step = [&](double am, double e2) {
+        if (fabs(q) < 1e-300) q = q < 0.0 ? -1e-300 : 1e-300;   // the sign is counted already
+        q = am - e2 * tridiag_recip(q);
         if (q < 0.0) ++cnt;
+    };
+    int i = 1;
+    for (; i + kTriBatch <= k; i += kTriBatch) {
+        double am[kTriBatch], e2[kTriBatch];
+#pragma unroll
+        for (int j = 0; j < kTriBatch; ++j) {
+            am[j] = a[i + j] - x;
+            e2[j] = e[i + j] * e[i + j];
+        }
+#pragma unroll
+        for (int j = 0; j < kTriBatch; ++j) step(am[j], e2[j]);
     }
+    for (; i < k; ++i) step(a[i] - x, e[i] * e[i]);
     return cnt;
 }
 
@@ -126,30 +155,84 @@ __device__ inline void ritz_hint(double theta1, double theta2, double* lo, doubl
 // value stays on the critical path.
 __device__ inline void tridiag_min_vector(const double* a, const double* e, int k, double lower, double* z,
                                           double* rp) {
+    constexpr int B = kTriBatch;
     const double sigma = lower - 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(lower));
     double d = a[0] - sigma;
-    if (d == 0.0) d = 1e-300;
-    double r = 1.0 / d;
+    if (fabs(d) < 1e-300) d = d < 0.0 ? -1e-300 : 1e-300;
+    double r = tridiag_recip(d);
     rp[0] = r;
     z[0] = 1.0;
-    for (int i = 1; i < k; ++i) {
-        d = (a[i] - sigma) - (e[i] * r) * e[i];
-        if (d == 0.0) d = 1e-300;
-        r = 1.0 / d;
-        rp[i] = r;
+    auto pivot = [&](double am, double ei) {
+        d = am - (ei * r) * ei;
+        if (fabs(d) < 1e-300) d = d < 0.0 ? -1e-300 : 1e-300;
+        r = tridiag_recip(d);
+        return r;
+    };
+    int i = 1;
+    for (; i + B <= k; i += B) {
+        double am[B], ev[B], rv[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            am[j] = a[i + j] - sigma;
+            ev[j] = e[i + j];
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) rv[j] = pivot(am[j], ev[j]);
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            rp[i + j] = rv[j];
+            z[i + j] = 1.0;
+        }
+    }
+    for (; i < k; ++i) {
+        rp[i] = pivot(a[i] - sigma, e[i]);
         z[i] = 1.0;
     }
     for (int it = 0; it < 3; ++it) {
         // L y = z (forward), then D L^T x = y (backward); x overwrites z
         double c = z[0];
-        for (int i = 1; i < k; ++i) {
+        i = 1;
+        for (; i + B <= k; i += B) {
+            double zv[B], mv[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                zv[j] = z[i + j];
+                mv[j] = e[i + j] * rp[i + j - 1];
+            }
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                c = zv[j] - mv[j] * c;
+                zv[j] = c;
+            }
+#pragma unroll
+            for (int j = 0; j < B; ++j) z[i + j] = zv[j];
+        }
+        for (; i < k; ++i) {
             c = z[i] - (e[i] * rp[i - 1]) * c;
             z[i] = c;
         }
         c = z[k - 1] * rp[k - 1];
         z[k - 1] = c;
         double nrm = c * c;
-        for (int i = k - 2; i >= 0; --i) {
+        i = k - 2;
+        for (; i - B + 1 >= 0; i -= B) {   // i, i - 1, ..., i - B + 1
+            double rv[B], zv[B], ev[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                rv[j] = rp[i - j];
+                zv[j] = z[i - j];
+                ev[j] = e[i - j + 1];
+            }
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                c = rv[j] * (zv[j] - ev[j] * c);
+                zv[j] = c;
+                nrm += c * c;
+            }
+#pragma unroll
+            for (int j = 0; j < B; ++j) z[i - j] = zv[j];
+        }
+        for (; i >= 0; --i) {
             c = rp[i] * (z[i] - e[i + 1] * c);
             z[i] = c;
             nrm += c * c;
@@ -157,7 +240,8 @@ __device__ inline void tridiag_min_vector(const double* a, const double* e, int 
         nrm = sqrt(nrm);
         if (!(nrm > 0.0) || !isfinite(nrm)) break;
         const double inv = 1.0 / nrm;
-        for (int i = 0; i < k; ++i) z[i] *= inv;
+#pragma unroll 8
+        for (int t = 0; t < k; ++t) z[t] *= inv;
     }
 }
 

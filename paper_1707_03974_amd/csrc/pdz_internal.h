@@ -237,7 +237,7 @@ struct SchedGroups {
     const uint64_t* goff = nullptr;
     const uint8_t* gnr = nullptr;
     uint64_t ngroups = 0;
-    int R = 1;   // 1 to 3 (FP64: 1)
+    int R = 1;   // 1 to 3 (FP64: 1); with R = 1 every group is one row and gnr is not read
 };
 // y = diagonal + down hops over the groups' rows (fuse == NULL), or, with
 // fuse->fq2 set, q_{k+1} formed from y (the whole H q_k, fuse->fz NULL), q_k

@@ -49,6 +49,9 @@ struct KSpace {
     std::vector<uint32_t> Ld;       // N: down strings per momentum
     std::vector<uint64_t> dn_off;   // N+1: first down string of each momentum
     std::vector<uint64_t> tb_off;   // N x N: first entry of the down-move table of (target momentum, q)
+    std::vector<uint32_t> Lp;       // N: table pitch of each momentum (its down strings, padded so that
+                                    // a thread's run of consecutive strings is one aligned load)
+    std::vector<uint64_t> cnt_off;  // N+1: first count of each momentum
     uint64_t D_up = 0, D_dn = 0, nrows = 0, entries = 0;
     uint64_t staged = 0;            // source-row elements one H.v stages: sum over rows and q of moves x row length
     uint32_t Lmax = 0;
@@ -62,9 +65,12 @@ struct KSpace {
     double* d_eps = nullptr;
     uint32_t* d_dn_str = nullptr;   // D_dn: down strings, grouped by momentum, ascending within
     double* d_eps_dn = nullptr;     // D_dn: band energy of each down string
-    uint8_t* d_dcnt = nullptr;      // D_dn x N: down moves of (string, q), [momentum][q][rank]
+    uint32_t* d_Lp = nullptr;
+    uint64_t* d_cnt_off = nullptr;
+    uint8_t* d_dcnt = nullptr;      // down moves of (string, q): [momentum][q][rank], pitch Lp, 0 past Ld
     void* d_dtab = nullptr;         // entries: source rank | sign in the top bit (16 bits when every
-                                    // momentum has < 2^15 down strings, else 32), slot major per (momentum, q)
+                                    // momentum has < 2^15 down strings, else 32), slot major per
+                                    // (momentum, q) with pitch Lp
     bool dtab16 = false;
     int uslots = 0;                 // most up moves of one string for one q
     uint64_t* d_upm = nullptr;      // D_up x (N-1) x uslots: source row start | sign << 63 of each up
@@ -91,6 +97,8 @@ struct KArgs {
     const double* eps;
     const uint32_t* dn_str;
     const double* eps_dn;
+    const uint32_t* Lp;
+    const uint64_t* cnt_off;
     const uint8_t* dcnt;
     const void* dtab;
     const uint64_t* upm;
@@ -224,8 +232,8 @@ __global__ __launch_bounds__(kKBlock) void k_kdn_moves(const KArgs a, int slots,
         int kd = 0;
         while (kd + 1 < a.N && a.dn_off[kd + 1] <= j) ++kd;
         const uint64_t dp = j - a.dn_off[kd];
-        const uint64_t L = a.Ld[kd];
-        const uint64_t cidx = a.dn_off[kd] * a.N + (uint64_t)q * L + dp;
+        const uint64_t L = a.Lp[kd];   // pitch
+        const uint64_t cidx = a.cnt_off[kd] + (uint64_t)q * L + dp;
         if (q == 0) {
             dcnt[cidx] = 0;
             continue;
@@ -365,71 +373,231 @@ constexpr uint64_t kMoveNeg = 1ull << 63;
 
 __host__ __device__ constexpr size_t hvk_z_bytes(uint32_t Lmax, size_t es) { return ((size_t)Lmax * es + 15) & ~(size_t)15; }
 
+// A thread takes E consecutive elements of a row, read and written as one
+// vector where all E lie inside the row (16-byte pieces; memory rows start at
+// any element, so memory pieces are element aligned).
+template <typename T, int E>
+__device__ __forceinline__ void kvec_load(const T* p, T (&o)[E]) {
+    constexpr int C = (E * (int)sizeof(T) >= 16) ? 16 / (int)sizeof(T) : E;
+    if constexpr (C == 1) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) o[i] = p[i];
+    } else {
+        typedef T ct __attribute__((ext_vector_type(C), aligned(sizeof(T))));
+#pragma unroll
+        for (int c = 0; c < E; c += C) {
+            const ct t = *reinterpret_cast<const ct*>(p + c);
+#pragma unroll
+            for (int i = 0; i < C; ++i) o[c + i] = t[i];
+        }
+    }
+}
+template <typename T, int E>
+__device__ __forceinline__ void kvec_store(T* p, const T (&v)[E]) {
+    constexpr int C = (E * (int)sizeof(T) >= 16) ? 16 / (int)sizeof(T) : E;
+    if constexpr (C == 1) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) p[i] = v[i];
+    } else {
+        typedef T ct __attribute__((ext_vector_type(C), aligned(sizeof(T))));
+#pragma unroll
+        for (int c = 0; c < E; c += C) {
+            ct t;
+#pragma unroll
+            for (int i = 0; i < C; ++i) t[i] = v[c + i];
+            *reinterpret_cast<ct*>(p + c) = t;
+        }
+    }
+}
+// E values at p, aligned to E values (table rows, whose pitch is a multiple of
+// E, and the LDS rows Z)
+template <typename V, int E>
+__device__ __forceinline__ void kvec_store_aligned(V* p, const V (&v)[E]) {
+    constexpr int C = (E * (int)sizeof(V) >= 16) ? 16 / (int)sizeof(V) : E;
+    if constexpr (C == 1) {
+        p[0] = v[0];
+    } else {
+        typedef V ct __attribute__((ext_vector_type(C)));
+#pragma unroll
+        for (int c = 0; c < E; c += C) {
+            ct t;
+#pragma unroll
+            for (int i = 0; i < C; ++i) t[i] = v[c + i];
+            *reinterpret_cast<ct*>(p + c) = t;
+        }
+    }
+}
+template <typename V, int E>
+__device__ __forceinline__ void kvec_load_aligned(const V* p, V (&o)[E]) {
+    constexpr int C = (E * (int)sizeof(V) >= 16) ? 16 / (int)sizeof(V) : E;
+    if constexpr (C == 1) {
+        o[0] = p[0];
+    } else {
+        typedef V ct __attribute__((ext_vector_type(C)));
+#pragma unroll
+        for (int c = 0; c < E; c += C) {
+            const ct t = *reinterpret_cast<const ct*>(p + c);
+#pragma unroll
+            for (int i = 0; i < C; ++i) o[c + i] = t[i];
+        }
+    }
+}
+
+// Element mapping of a thread's E elements: FP32, E consecutive elements
+// (vector loads and stores, measured faster); FP64, elements tid + e * kKBlock
+// (the vector form measured slower there).  Either way each element sums the
+// same terms in the same order.
+template <typename T>
+constexpr bool hvk_consecutive() { return sizeof(T) == 4; }
+
 // Z_b[d] = sum over the nv up moves mv[0..nv) of +-(source row)[d], summed in
-// move order.  Two moves at a time: the 2E loads of a thread are independent.
+// move order.  Several moves at a time: the loads of a thread are independent.
 template <typename T, int E>
 __device__ __forceinline__ void hvk_stage(const T* __restrict__ x, const uint64_t* mv, int nv, uint32_t Ls, T* Zb) {
-    T z[E];
+    if constexpr (!hvk_consecutive<T>()) {
+        T z[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) z[e] = (T)0;
-    int m = 0;
-    for (; m + 1 < nv; m += 2) {
-        const uint64_t e0 = mv[m], e1 = mv[m + 1];
-        const T* r0 = x + (e0 & ~kMoveNeg);
-        const T* r1 = x + (e1 & ~kMoveNeg);
-        T v0[E], v1[E];
+        for (int e = 0; e < E; ++e) z[e] = (T)0;
+        int m = 0;
+        for (; m + 1 < nv; m += 2) {
+            const uint64_t e0 = mv[m], e1 = mv[m + 1];
+            const T* r0 = x + (e0 & ~kMoveNeg);
+            const T* r1 = x + (e1 & ~kMoveNeg);
+            T v0[E], v1[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const uint32_t d = threadIdx.x + e * kKBlock;
+                v0[e] = d < Ls ? r0[d] : (T)0;
+                v1[e] = d < Ls ? r1[d] : (T)0;
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                z[e] += (e0 & kMoveNeg) ? -v0[e] : v0[e];
+                z[e] += (e1 & kMoveNeg) ? -v1[e] : v1[e];
+            }
+        }
+        if (m < nv) {
+            const uint64_t e0 = mv[m];
+            const T* r0 = x + (e0 & ~kMoveNeg);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const uint32_t d = threadIdx.x + e * kKBlock;
+                const T v = d < Ls ? r0[d] : (T)0;
+                z[e] += (e0 & kMoveNeg) ? -v : v;
+            }
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const uint32_t d = threadIdx.x + e * kKBlock;
-            v0[e] = d < Ls ? r0[d] : (T)0;
-            v1[e] = d < Ls ? r1[d] : (T)0;
+            if (d < Ls) Zb[d] = z[e];
         }
+        return;
+    }
+    const uint32_t d0 = E * threadIdx.x;
+    if (d0 >= Ls) return;
+    const bool full = d0 + E <= Ls;
+    T z[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) z[e] = (T)0;
+    auto row = [&](uint64_t m, T (&v)[E]) {
+        const T* r = x + (m & ~kMoveNeg) + d0;
+        if (full) {
+            kvec_load<T, E>(r, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = d0 + e < Ls ? r[e] : (T)0;
+        }
+    };
+    int m = 0;
+    for (; m + 3 < nv; m += 4) {
+        const uint64_t e0 = mv[m], e1 = mv[m + 1], e2 = mv[m + 2], e3 = mv[m + 3];
+        T v0[E], v1[E], v2[E], v3[E];
+        row(e0, v0);
+        row(e1, v1);
+        row(e2, v2);
+        row(e3, v3);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             z[e] += (e0 & kMoveNeg) ? -v0[e] : v0[e];
             z[e] += (e1 & kMoveNeg) ? -v1[e] : v1[e];
+            z[e] += (e2 & kMoveNeg) ? -v2[e] : v2[e];
+            z[e] += (e3 & kMoveNeg) ? -v3[e] : v3[e];
         }
     }
-    if (m < nv) {
+    for (; m < nv; ++m) {
         const uint64_t e0 = mv[m];
-        const T* r0 = x + (e0 & ~kMoveNeg);
+        T v0[E];
+        row(e0, v0);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t d = threadIdx.x + e * kKBlock;
-            const T v = d < Ls ? r0[d] : (T)0;
-            z[e] += (e0 & kMoveNeg) ? -v : v;
-        }
+        for (int e = 0; e < E; ++e) z[e] += (e0 & kMoveNeg) ? -v0[e] : v0[e];
     }
+    if (full) {
+        kvec_store_aligned<T, E>(Zb + d0, z);
+    } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t d = threadIdx.x + e * kKBlock;
-        if (d < Ls) Zb[d] = z[e];
+        for (int e = 0; e < E; ++e)
+            if (d0 + e < Ls) Zb[d0 + e] = z[e];
     }
 }
 
-// acc[e] += sum over the down moves of element tid + e*256 of +-Z[source]:
-// counts of all E elements first, then the table entries four slots at a time
-// (independent loads), then the LDS reads in slot order.
+// acc[e] += sum over the down moves of element E tid + e of +-Z[source]: the
+// counts of the thread's E elements (one load; zero past the row), then the
+// table entries four slots at a time (one load per slot), then the LDS reads
+// in slot order.  cnt and the slot rows have pitch Lp.
 template <typename T, int E, typename TE>
 __device__ __forceinline__ void hvk_gather(const TE* __restrict__ dtab, const uint8_t* __restrict__ cnt, uint64_t tb,
-                                           uint32_t L, int slots, const T* Z, T* acc) {
+                                           uint32_t Lp, uint32_t L, int slots, const T* Z, T* acc) {
     constexpr TE neg = (TE)((TE)1 << (8 * sizeof(TE) - 1));
     constexpr int SB = 4;
+    if constexpr (!hvk_consecutive<T>()) {   // element tid + e * kKBlock: counts first, then four slots at a time
+        int c[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t dp = threadIdx.x + e * kKBlock;
+            c[e] = dp < L ? (int)cnt[dp] : 0;
+        }
+        for (int s0 = 0; s0 < slots; s0 += SB) {
+            TE ent[SB][E];
+#pragma unroll
+            for (int j = 0; j < SB; ++j)
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const uint32_t dp = threadIdx.x + e * kKBlock;
+                    ent[j][e] = (s0 + j < c[e]) ? dtab[tb + (uint64_t)(s0 + j) * Lp + dp] : (TE)0;
+                }
+#pragma unroll
+            for (int j = 0; j < SB; ++j)
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if (s0 + j < c[e]) {
+                        const T v = Z[ent[j][e] & (TE)~neg];
+                        acc[e] += (ent[j][e] & neg) ? -v : v;
+                    }
+        }
+        return;
+    }
+    const uint32_t d0 = E * threadIdx.x;
+    if (d0 >= L) return;
+    uint8_t c8[E];
+    kvec_load_aligned<uint8_t, E>(cnt + d0, c8);
     int c[E];
+    int cmax = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const uint32_t dp = threadIdx.x + e * kKBlock;
-        c[e] = dp < L ? (int)cnt[dp] : 0;
+        c[e] = c8[e];
+        cmax = c[e] > cmax ? c[e] : cmax;
     }
     for (int s0 = 0; s0 < slots; s0 += SB) {
         TE ent[SB][E];
 #pragma unroll
-        for (int j = 0; j < SB; ++j)
+        for (int j = 0; j < SB; ++j) {
+            if (s0 + j < cmax) {
+                kvec_load_aligned<TE, E>(dtab + tb + (uint64_t)(s0 + j) * Lp + d0, ent[j]);
+            } else {
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const uint32_t dp = threadIdx.x + e * kKBlock;
-                ent[j][e] = (s0 + j < c[e]) ? dtab[tb + (uint64_t)(s0 + j) * L + dp] : (TE)0;
+                for (int e = 0; e < E; ++e) ent[j][e] = (TE)0;
             }
+        }
 #pragma unroll
         for (int j = 0; j < SB; ++j)
 #pragma unroll
@@ -468,7 +636,7 @@ __global__ __launch_bounds__(kKBlock) void k_hvk(const KArgs a, const T* __restr
     }
     __syncthreads();
     const TE* __restrict__ dtab = static_cast<const TE*>(a.dtab);
-    const uint32_t L = a.Ld[kd];
+    const uint32_t L = a.Ld[kd], Lp = a.Lp[kd];
     const uint64_t off = a.row_off[r];
     const uint64_t dbase = a.dn_off[kd];
     const int tid = threadIdx.x;
@@ -487,19 +655,42 @@ __global__ __launch_bounds__(kKBlock) void k_hvk(const KArgs a, const T* __restr
     while (q < a.N) {
         const int qn = next_q(q + 1);
         if (qn < a.N) hvk_stage<T, E>(x, smv + (qn - 1) * a.uslots, snv[qn], a.Ld[skadd[kd * a.N + qn]], Zbuf[b ^ 1]);
-        hvk_gather<T, E, TE>(dtab, a.dcnt + dbase * a.N + (uint64_t)q * L, a.tb_off[kd * a.N + q], L, a.slots,
-                             Zbuf[b], acc);
+        hvk_gather<T, E, TE>(dtab, a.dcnt + a.cnt_off[kd] + (uint64_t)q * Lp, a.tb_off[kd * a.N + q], Lp, L,
+                             a.slots, Zbuf[b], acc);
         __syncthreads();
         q = qn;
         b ^= 1;
     }
     const double eu = a.eps_up[r] + a.diag_u;
+    if constexpr (!hvk_consecutive<T>()) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t dp = tid + e * kKBlock;
-        if (dp < L) {
-            const T dg = (T)(eu + a.eps_dn[dbase + dp]);
-            y[off + dp] = dg * x[off + dp] + (T)a.u_n * acc[e];
+        for (int e = 0; e < E; ++e) {
+            const uint32_t dp = tid + e * kKBlock;
+            if (dp < L) {
+                const T dg = (T)(eu + a.eps_dn[dbase + dp]);
+                y[off + dp] = dg * x[off + dp] + (T)a.u_n * acc[e];
+            }
+        }
+        return;
+    }
+    const uint32_t d0 = E * (uint32_t)tid;
+    if (d0 + E <= L) {
+        T xv[E], yv[E];
+        kvec_load<T, E>(x + off + d0, xv);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const T dg = (T)(eu + a.eps_dn[dbase + d0 + e]);
+            yv[e] = dg * xv[e] + (T)a.u_n * acc[e];
+        }
+        kvec_store<T, E>(y + off + d0, yv);
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t dp = d0 + e;
+            if (dp < L) {
+                const T dg = (T)(eu + a.eps_dn[dbase + dp]);
+                y[off + dp] = dg * x[off + dp] + (T)a.u_n * acc[e];
+            }
         }
     }
 }
@@ -546,6 +737,8 @@ KArgs kargs(const pdz_problem_s* p) {
     a.dn_str = ks->d_dn_str;
     a.eps_dn = ks->d_eps_dn;
     a.dcnt = ks->d_dcnt;
+    a.Lp = ks->d_Lp;
+    a.cnt_off = ks->d_cnt_off;
     a.dtab = ks->d_dtab;
     a.upm = ks->d_upm;
     a.uslots = ks->uslots;
@@ -613,9 +806,10 @@ pdz_status alloc(V** dst, uint64_t n) {
 
 void kspace_free(KSpace* ks) {
     if (!ks) return;
-    void* ptrs[] = {ks->d_kadd, ks->d_Ck, ks->d_Ct, ks->d_Ld, ks->d_dn_off, ks->d_tb_off, ks->d_eps,
-                    ks->d_dn_str, ks->d_eps_dn, ks->d_dcnt, ks->d_dtab, ks->d_up_str, ks->d_row_off,
-                    ks->d_row_kd, ks->d_eps_up, ks->d_rows, ks->d_upm};
+    void* ptrs[] = {ks->d_kadd,   ks->d_Ck,      ks->d_Ct,     ks->d_Ld,      ks->d_dn_off, ks->d_tb_off,
+                    ks->d_Lp,     ks->d_cnt_off, ks->d_eps,    ks->d_dn_str,  ks->d_eps_dn, ks->d_dcnt,
+                    ks->d_dtab,   ks->d_up_str,  ks->d_row_off, ks->d_row_kd, ks->d_eps_up, ks->d_rows,
+                    ks->d_upm};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete ks;
@@ -699,12 +893,20 @@ pdz_status kspace_build(pdz_problem_s* p, int L1, int L2, const double* eps, int
     ks->slots = std::min(nd, N - nd);
     ks->uslots = std::min(nu, N - nu);
     ks->dtab16 = ks->Lmax < 32768u;
+    // pitch: a multiple of 8 and of the run of consecutive strings one H.v thread takes
+    const uint32_t pa = (uint32_t)std::max(8, hvk_elems(ks->Lmax));
+    ks->Lp.resize(N);
+    ks->cnt_off.assign(N + 1, 0);
+    for (int k = 0; k < N; ++k) {
+        ks->Lp[k] = (ks->Ld[k] + pa - 1) / pa * pa;
+        ks->cnt_off[k + 1] = ks->cnt_off[k] + (uint64_t)N * ks->Lp[k];
+    }
     ks->tb_off.assign((size_t)N * N, 0);
     uint64_t e = 0;
     for (int k = 0; k < N; ++k)
         for (int q = 0; q < N; ++q) {
             ks->tb_off[(size_t)k * N + q] = e;
-            if (q != 0) e += (uint64_t)ks->Ld[k] * ks->slots;
+            if (q != 0) e += (uint64_t)ks->Lp[k] * ks->slots;
         }
     ks->entries = e;
 
@@ -717,10 +919,13 @@ pdz_status kspace_build(pdz_problem_s* p, int L1, int L2, const double* eps, int
     if ((st = upload(&ks->d_Ld, ks->Ld)) != PDZ_OK) return st;
     if ((st = upload(&ks->d_dn_off, ks->dn_off)) != PDZ_OK) return st;
     if ((st = upload(&ks->d_tb_off, ks->tb_off)) != PDZ_OK) return st;
+    if ((st = upload(&ks->d_Lp, ks->Lp)) != PDZ_OK) return st;
+    if ((st = upload(&ks->d_cnt_off, ks->cnt_off)) != PDZ_OK) return st;
     if ((st = upload(&ks->d_eps, ks->eps)) != PDZ_OK) return st;
     if ((st = alloc(&ks->d_dn_str, ks->D_dn)) != PDZ_OK) return st;
     if ((st = alloc(&ks->d_eps_dn, ks->D_dn)) != PDZ_OK) return st;
-    if ((st = alloc(&ks->d_dcnt, ks->D_dn * N)) != PDZ_OK) return st;
+    if ((st = alloc(&ks->d_dcnt, ks->cnt_off[N])) != PDZ_OK) return st;
+    PDZ_HIP(hipMemset(ks->d_dcnt, 0, ks->cnt_off[N]));   // padding past Ld: no moves
     if (ks->dtab16) {
         uint16_t* t = nullptr;
         if ((st = alloc(&t, ks->entries)) != PDZ_OK) return st;
@@ -730,6 +935,7 @@ pdz_status kspace_build(pdz_problem_s* p, int L1, int L2, const double* eps, int
         if ((st = alloc(&t, ks->entries)) != PDZ_OK) return st;
         ks->d_dtab = t;
     }
+    PDZ_HIP(hipMemset(ks->d_dtab, 0, ks->entries * (ks->dtab16 ? 2 : 4)));
     if ((st = alloc(&ks->d_upm, ks->D_up * (uint64_t)(N > 1 ? N - 1 : 0) * ks->uslots)) != PDZ_OK) return st;
     if ((st = alloc(&ks->d_up_str, ks->D_up)) != PDZ_OK) return st;
     if ((st = alloc(&ks->d_row_off, ks->D_up)) != PDZ_OK) return st;
@@ -765,7 +971,7 @@ pdz_status kspace_build(pdz_problem_s* p, int L1, int L2, const double* eps, int
     std::vector<uint64_t> off(ks->D_up);
     std::vector<uint8_t> rkd(ks->D_up);
     std::vector<uint32_t> ups(ks->D_up);
-    std::vector<uint8_t> cnt(ks->D_dn * N);
+    std::vector<uint8_t> cnt(ks->cnt_off[N]);
     PDZ_HIP(hipMemcpy(off.data(), ks->d_row_off, off.size() * 8, hipMemcpyDeviceToHost));
     PDZ_HIP(hipMemcpy(rkd.data(), ks->d_row_kd, rkd.size(), hipMemcpyDeviceToHost));
     PDZ_HIP(hipMemcpy(ups.data(), ks->d_up_str, ups.size() * 4, hipMemcpyDeviceToHost));
@@ -787,7 +993,7 @@ pdz_status kspace_build(pdz_problem_s* p, int L1, int L2, const double* eps, int
     for (int k = 0; k < N; ++k)
         for (int q = 1; q < N; ++q) {
             uint64_t sum = 0;
-            const uint8_t* c = cnt.data() + ks->dn_off[k] * N + (uint64_t)q * ks->Ld[k];
+            const uint8_t* c = cnt.data() + ks->cnt_off[k] + (uint64_t)q * ks->Lp[k];
             for (uint32_t d = 0; d < ks->Ld[k]; ++d) sum += c[d];
             mdn[(size_t)k * N + q] = sum;
         }

@@ -87,6 +87,8 @@ __device__ __forceinline__ const double* bcoef<double>(const BProb& p) { return 
 template <>
 __device__ __forceinline__ const float* bcoef<float>(const BProb& p) { return p.coef32; }
 
+constexpr int kBHopNB = 8;   // hops of one element whose loads are in flight together
+
 // done: per-cluster flags with stride `dstride` ints (NULL: none skipped).
 template <typename T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_batch_hv(const BProb* __restrict__ probs, const BTile* __restrict__ tiles,
@@ -124,14 +126,35 @@ __global__ __launch_bounds__(BLOCK) void k_batch_hv(const BProb* __restrict__ pr
             // the barriers keep the rounding of the two-pass H.v: the diagonal
             // product and the down-hop sum are rounded before the next term
             asm volatile("" : "+v"(acc));
+            // hops in order, kBHopNB at a time: a batch's table entries (and, for
+            // up hops, its operands) are loaded before its first multiply-add
             const int cd = pr.dn_count[d];
-            for (int h = 0; h < cd; ++h) {
+            int h = 0;
+            for (; h + kBHopNB <= cd; h += kBHopNB) {
+                uint32_t e[kBHopNB];
+#pragma unroll
+                for (int j = 0; j < kBHopNB; ++j) e[j] = pr.dn_ell[(uint64_t)(h + j) * D_dn + d];
+#pragma unroll
+                for (int j = 0; j < kBHopNB; ++j) acc += coef[e[j] >> kTargetBits] * xrow[e[j] & kTargetMask];
+            }
+            for (; h < cd; ++h) {
                 const uint32_t e = pr.dn_ell[(uint64_t)h * D_dn + d];
                 acc += coef[e >> kTargetBits] * xrow[e & kTargetMask];
             }
             asm volatile("" : "+v"(acc));
             const int cu = pr.up_count[u];
-            for (int h = 0; h < cu; ++h) {
+            h = 0;
+            for (; h + kBHopNB <= cu; h += kBHopNB) {
+                uint32_t e[kBHopNB];
+                T v[kBHopNB];
+#pragma unroll
+                for (int j = 0; j < kBHopNB; ++j) e[j] = pr.up_ell[(uint64_t)(h + j) * D_up + u];
+#pragma unroll
+                for (int j = 0; j < kBHopNB; ++j) v[j] = xp[(uint64_t)(e[j] & kTargetMask) * D_dn + d];
+#pragma unroll
+                for (int j = 0; j < kBHopNB; ++j) acc += coef[e[j] >> kTargetBits] * v[j];
+            }
+            for (; h < cu; ++h) {
                 const uint32_t e = pr.up_ell[(uint64_t)h * D_up + u];
                 acc += coef[e >> kTargetBits] * xp[(uint64_t)(e & kTargetMask) * D_dn + d];
             }

@@ -873,8 +873,18 @@ __global__ __launch_bounds__(kNarrowBlock) void k_hv_down_narrow(const DownArgs<
             const uint32_t pd = a.dn_states[d];
             T acc = a.U * (T)__builtin_popcount(pu & pd) * xrow[d];
             const int cnt = a.dn_count[d];
-            for (int h = 0; h < cnt; ++h) {
-                const uint32_t e = hop_entry(a.dn_ell, h, d, D_dn);
+            // hops in order, eight table entries loaded before their multiply-adds
+            constexpr int NB = 8;
+            int h = 0;
+            for (; h + NB <= cnt; h += NB) {
+                uint32_t e[NB];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) e[j] = hop_entry(a.dn_ell, (uint32_t)(h + j), d, D_dn);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc += coef[e[j] >> a.cshift] * xrow[e[j] & a.tmask];
+            }
+            for (; h < cnt; ++h) {
+                const uint32_t e = hop_entry(a.dn_ell, (uint32_t)h, d, D_dn);
                 acc += coef[e >> a.cshift] * xrow[e & a.tmask];
             }
             y[(u0 + r) * a.pitch + d] = acc;

@@ -99,6 +99,7 @@ namespace {
 constexpr int kPBlock = 256;
 constexpr uint8_t kClsA = 0, kClsImage = 1, kClsPal = 2;
 constexpr uint32_t kNoCol = 0xFFFFFFFFu;
+constexpr int kPHopNB = 8;   // hops of an element whose lookups are in flight together
 
 __device__ __forceinline__ uint32_t mirror(uint32_t phi, int N) {
     return N >= 32 ? __builtin_bitreverse32(phi) : (__builtin_bitreverse32(phi) >> (32 - N));
@@ -226,7 +227,37 @@ __global__ __launch_bounds__(kPBlock) void k_hvp(const PArgs a, const T* __restr
             const T xc = x[off + c];
             T acc = (T)(a.U * __builtin_popcount(phu & a.dn_states[rd])) * xc;
             const int ndh = a.dn_cnt[rd];
-            for (int h = 0; h < ndh; ++h) {   // the up string stays: a column of this row
+            // hops in order, kPHopNB at a time: each level of a batch's lookups
+            // (entries, classes, columns, operands) is loaded before the next
+            int h = 0;
+            for (; h + kPHopNB <= ndh; h += kPHopNB) {   // the up string stays: a column of this row
+                uint32_t rd2[kPHopNB], col[kPHopNB];
+                uint8_t cl[kPHopNB];
+                T cf[kPHopNB], xv[kPHopNB];
+#pragma unroll
+                for (int j = 0; j < kPHopNB; ++j) {
+                    const uint32_t e = a.dn_ell[(uint64_t)(h + j) * a.Ddn + rd];
+                    rd2[j] = e & kTargetMask;
+                    cf[j] = coef[e >> kTargetBits];
+                }
+#pragma unroll
+                for (int j = 0; j < kPHopNB; ++j) cl[j] = a.dcls[rd2[j]];
+#pragma unroll
+                for (int j = 0; j < kPHopNB; ++j) col[j] = a.dcol[cl[j] == kClsImage ? a.dinv[rd2[j]] : rd2[j]];
+#pragma unroll
+                for (int j = 0; j < kPHopNB; ++j)   // excluded palindromes have no column
+                    xv[j] = (cl[j] != kClsPal || a.pal_in) ? x[off + col[j]] : (T)0;
+#pragma unroll
+                for (int j = 0; j < kPHopNB; ++j) {
+                    if (cl[j] == kClsA)
+                        acc += wt * ir2 * cf[j] * xv[j];
+                    else if (cl[j] == kClsImage)
+                        acc += wt * ir2 * ps * cf[j] * xv[j];
+                    else if (a.pal_in)
+                        acc += wt * cf[j] * xv[j];
+                }
+            }
+            for (; h < ndh; ++h) {
                 const uint32_t e = a.dn_ell[(uint64_t)h * a.Ddn + rd];
                 const uint32_t rd2 = e & kTargetMask;
                 const T cf = coef[e >> kTargetBits];
@@ -238,15 +269,44 @@ __global__ __launch_bounds__(kPBlock) void k_hvp(const PArgs a, const T* __restr
                 else if (a.pal_in)
                     acc += wt * cf * x[off + a.dcol[rd2]];
             }
-            for (int h = 0; h < nup_h; ++h) {   // one hop never leaves a palindrome a palindrome: a full row
+            // one hop never leaves a palindrome a palindrome: a full row
+            const uint32_t cA = a.dcolf[rd], cI = a.dcolf[a.dinv[rd]];
+            h = 0;
+            for (; h + kPHopNB <= nup_h; h += kPHopNB) {
+                uint32_t ru2[kPHopNB];
+                uint64_t off2[kPHopNB];
+                bool isA[kPHopNB];
+                T cf[kPHopNB], xv[kPHopNB];
+#pragma unroll
+                for (int j = 0; j < kPHopNB; ++j) {
+                    const uint32_t e = a.up_ell[(uint64_t)(h + j) * a.Dup + ru];
+                    ru2[j] = e & kTargetMask;
+                    cf[j] = coef[e >> kTargetBits];
+                }
+#pragma unroll
+                for (int j = 0; j < kPHopNB; ++j) {
+                    off2[j] = a.row_off[a.urow[ru2[j]]];
+                    isA[j] = a.ucls[ru2[j]] == kClsA;
+                }
+#pragma unroll
+                for (int j = 0; j < kPHopNB; ++j) xv[j] = x[off2[j] + (isA[j] ? cA : cI)];
+#pragma unroll
+                for (int j = 0; j < kPHopNB; ++j) {
+                    if (isA[j])
+                        acc += wt * ir2 * cf[j] * xv[j];
+                    else
+                        acc += wt * ir2 * ps * cf[j] * xv[j];
+                }
+            }
+            for (; h < nup_h; ++h) {
                 const uint32_t e = a.up_ell[(uint64_t)h * a.Dup + ru];
                 const uint32_t ru2 = e & kTargetMask;
                 const T cf = coef[e >> kTargetBits];
                 const uint64_t off2 = a.row_off[a.urow[ru2]];
                 if (a.ucls[ru2] == kClsA)
-                    acc += wt * ir2 * cf * x[off2 + a.dcolf[rd]];
+                    acc += wt * ir2 * cf * x[off2 + cA];
                 else
-                    acc += wt * ir2 * ps * cf * x[off2 + a.dcolf[a.dinv[rd]]];
+                    acc += wt * ir2 * ps * cf * x[off2 + cI];
             }
             y[off + c] = acc;
             dsum += (double)xc * (double)acc;

@@ -1142,6 +1142,8 @@ __global__ __launch_bounds__(kUpBlock) void k_hv_up_pre(const UpArgs<T, E> a, co
 
 // Every sector rank and every hop target computed per element with the
 // forward and backward maps (binomial table in LDS).
+constexpr int kFlyNB = 8;   // bonds of an element whose targets are ranked and loaded together
+
 struct FlyArgs {
     int N, n_up, n_dn, nb;
     uint64_t D_up, D_dn;
@@ -1190,22 +1192,37 @@ __global__ __launch_bounds__(kFlyBlock) void k_hv_fly(const FlyArgs f, T U, cons
         const uint32_t pu = fly_unrank((uint32_t)u, f.n_up, f.N, sC);
         const uint32_t pd = fly_unrank((uint32_t)d, f.n_dn, f.N, sC);
         T acc = U * (T)__builtin_popcount(pu & pd) * x[r];
-        for (int b = 0; b < f.nb; ++b) {
-            const BondDev bd = f.bonds[b];
-            const uint32_t od = pd & bd.mask;
-            if (od != 0u && od != bd.mask) {
-                const int c = (__builtin_popcount(pd & bd.between) & 1) ? bd.coef_neg : bd.coef_pos;
-                acc += coef_g[c] * x[u * f.D_dn + fly_rank(pd ^ bd.mask, sC)];
+        // bonds in order, kFlyNB at a time: the batch's targets are ranked and
+        // their operands loaded before its first multiply-add (a bond that
+        // moves no electron adds nothing)
+        auto bonds = [&](uint32_t phi, bool down) {
+            int b = 0;
+            for (; b < f.nb; b += kFlyNB) {
+                T cf[kFlyNB], xv[kFlyNB];
+                bool hop[kFlyNB];
+#pragma unroll
+                for (int j = 0; j < kFlyNB; ++j) {
+                    hop[j] = false;
+                    cf[j] = (T)0;
+                    xv[j] = (T)0;
+                    if (b + j < f.nb) {
+                        const BondDev bd = f.bonds[b + j];
+                        const uint32_t o = phi & bd.mask;
+                        hop[j] = o != 0u && o != bd.mask;
+                        if (hop[j]) {
+                            cf[j] = coef_g[(__builtin_popcount(phi & bd.between) & 1) ? bd.coef_neg : bd.coef_pos];
+                            const uint64_t t = fly_rank(phi ^ bd.mask, sC);
+                            xv[j] = down ? x[u * f.D_dn + t] : x[t * f.D_dn + d];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kFlyNB; ++j)
+                    if (hop[j]) acc += cf[j] * xv[j];
             }
-        }
-        for (int b = 0; b < f.nb; ++b) {
-            const BondDev bd = f.bonds[b];
-            const uint32_t ou = pu & bd.mask;
-            if (ou != 0u && ou != bd.mask) {
-                const int c = (__builtin_popcount(pu & bd.between) & 1) ? bd.coef_neg : bd.coef_pos;
-                acc += coef_g[c] * x[(uint64_t)fly_rank(pu ^ bd.mask, sC) * f.D_dn + d];
-            }
-        }
+        };
+        bonds(pd, true);
+        bonds(pu, false);
         y[r] = acc;
     }
 }
